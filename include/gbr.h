@@ -1,0 +1,219 @@
+/*
+ * gbr.h -- C ABI of libgbr, the gfx950 (MI355X) batch-parallel differentiable
+ * renderer for reduced Gaussian blendshape avatars (RGBAvatar, arXiv
+ * 2503.12886).
+ *
+ * The calls follow the paper's problem statement:
+ *   blend     G^psi = G_0 + sum_k psi_k dG_k                    (Eq. 1)
+ *   render    per-frame preprocess (activation + EWA projection), tile
+ *             binning + depth order, front-to-back alpha compositing; a
+ *             whole batch of frames, each with its own Gaussian set and
+ *             camera, in one pass with no host synchronisation (Sec. 3.2,
+ *             "Batch-parallel Gaussian Rasterization", Fig. 4c)
+ *   backward  dL/dimages -> dL/d(blended Gaussians) -> dL/dbases, dL/dweights
+ *             (the bases and weights are what training optimises, Sec. 3.2
+ *             and Sec. A.3)
+ * plus the pieces of the training step around them: the weight MLP
+ * psi = F(theta) (Eq. 2), the L1 colour loss (Sec. 3.2 "Loss Function"),
+ * Adam with per-attribute learning rates (Sec. A.3), the single status read
+ * per step, graph capture and tile/chunk autotuning.
+ *
+ * Conventions shared by every call
+ *  - All tensors are float32 in device memory unless stated otherwise; the
+ *    caller allocates and owns every input and output pointer and the
+ *    library never frees them.  Host-side arrays are marked "host".
+ *  - A blended Gaussian is 16 floats: position [0:3], quaternion (w,x,y,z)
+ *    [3:7], log-scale [7:10], opacity logit [10], RGB [11:14], pad [14:16]
+ *    (pads are ignored on input and written as 0).  Activations after
+ *    blending (Sec. A.3): normalised quaternion, exp scale, sigmoid opacity,
+ *    identity colour.
+ *  - bases: [(K+1)][N][16]; slice 0 is G_0, slices 1..K are dG_1..dG_K.
+ *    weights: [B][K] (psi of every frame; G_0 has the implicit weight 1).
+ *  - Images: frame b is a CHW block of 3*H_b*W_b floats; frames are packed
+ *    back to back in call order (offset of frame b = 3 * sum_{b'<b} H W).
+ *  - Every call is stream-ordered and enqueue-only unless it says it
+ *    synchronises; `stream` is a hipStream_t passed as void* (NULL = the
+ *    null stream).
+ *  - Return value: GBR_OK or a negative GBR_ERR_* code (gbr_strerror).
+ *    Arguments are validated on the host before anything is enqueued; an
+ *    error leaves the context and the outputs untouched.  Capacity overflow
+ *    that only the device can see (the number of tile entries) sets a
+ *    device flag instead: every later kernel of that pass becomes a no-op,
+ *    Adam skips its update, and gbr_query_status reports it; the caller then
+ *    calls gbr_reserve and replays the step.
+ *  - A context is used by one host thread and one stream at a time.
+ */
+#ifndef GBR_H
+#define GBR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GBR_OK 0
+#define GBR_ERR_INVALID_ARG (-1)
+#define GBR_ERR_CAPACITY (-2)   /* host-visible capacity exceeded (frames, splats, pixels) */
+#define GBR_ERR_OOM (-3)
+#define GBR_ERR_HIP (-4)
+#define GBR_ERR_STATE (-5)      /* e.g. backward without a preceding render */
+#define GBR_ERR_OVERFLOW (-6)   /* device-detected entry overflow in the last pass */
+
+typedef struct gbr_ctx gbr_ctx;
+typedef struct gbr_graph gbr_graph;
+
+/* Pinhole camera of one frame.  R, t: world->camera (row-major), OpenCV axes
+   (+z forward, +x right, +y down); pixel (j, i) is sampled at (j+0.5, i+0.5).
+   A Gaussian whose camera-space z <= near_z is culled.  bg: background colour
+   composited behind the Gaussians (the random background of Sec. 3.2). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float near_z;
+  float bg[3];
+} gbr_camera;
+
+/* tile: 8, 16 or 32 px.  chunk: 64, 128 or 256 entries staged in LDS per
+   compositing step.  max_*: capacities the context allocates at creation
+   (frames per call, sum of per-frame Gaussian counts, sum of per-frame pixel
+   counts, tile-Gaussian entries).  max_entries grows with gbr_reserve. */
+typedef struct {
+  int32_t tile;
+  int32_t chunk;
+  int32_t device;
+  int32_t max_frames;
+  int64_t max_splats;
+  int64_t max_pixels;
+  int64_t max_entries;
+} gbr_config;
+
+typedef struct {
+  int64_t entries;           /* tile-Gaussian entries of the last pass */
+  int64_t entries_capacity;
+  int32_t overflow;          /* nonzero: the last pass overflowed, outputs invalid */
+  int32_t adam_steps[4];     /* Adam steps applied per parameter group */
+  float loss;                /* last value computed by gbr_loss */
+} gbr_status;
+
+const char* gbr_strerror(int code);
+
+/* Create a context on cfg->device: allocates every workspace from the
+   capacities in cfg.  Out: *out owns the workspace until gbr_destroy. */
+int gbr_create(const gbr_config* cfg, gbr_ctx** out);
+int gbr_destroy(gbr_ctx* ctx);
+/* Grow the entry capacity to at least max_entries (synchronises the device;
+   not allowed during graph capture).  Invalidates graphs captured before. */
+int gbr_reserve(gbr_ctx* ctx, int64_t max_entries);
+/* Switch tile size / LDS chunk depth (validated as in gbr_config). */
+int gbr_set_tiling(gbr_ctx* ctx, int32_t tile, int32_t chunk);
+
+/* Eq. 1.  raw[b] = bases[0] + sum_k weights[b][k-1] * bases[k] for B frames
+   that share one Gaussian set of N.  Accumulates in float64 on the matrix
+   cores and rounds once to float32, so the result does not depend on B.
+   bases [(K+1)][N][16], weights [B][K], raw [B][N][16]. */
+int gbr_blend(gbr_ctx* ctx, const float* bases, const float* weights, int32_t B, int32_t K, int64_t N, float* raw,
+              void* stream);
+
+/* Render B frames (Sec. 3.2 batch-parallel rasterization: preprocess, then
+   rasterize, with no host synchronisation in between).
+   raw: packed [sum_b N_b][16] blended Gaussians; frame b uses rows
+   gauss_offsets[b] .. gauss_offsets[b+1]-1 (host array [B+1], starting at 0).
+   cams: host array [B].  images: packed CHW frames (see above).
+   The context keeps what the backward pass needs until the next render. */
+int gbr_render(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B,
+               float* images, void* stream);
+/* The two halves of gbr_render, for callers that want the paper's per-frame
+   scheme (Fig. 4a/4b): gbr_preprocess, then gbr_entry_count (a host
+   synchronisation that returns the number of tile entries, and grows the
+   capacity if needed), then gbr_rasterize. */
+int gbr_preprocess(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B,
+                   void* stream);
+int gbr_entry_count(gbr_ctx* ctx, void* stream, int64_t* entries);
+int gbr_rasterize(gbr_ctx* ctx, float* images, void* stream);
+
+/* Adjoint of the last gbr_render: dimages (same packing as images) ->
+   draw [sum_b N_b][16] = dL/draw (pads written 0).  Deterministic: no
+   floating-point atomics, fixed summation order. */
+int gbr_render_backward(gbr_ctx* ctx, const float* dimages, float* draw, void* stream);
+
+/* Adjoint of gbr_blend.  draw [B][N][16] -> dbases [(K+1)][N][16] and
+   dweights [B][K]; accumulate != 0 adds into the outputs. */
+int gbr_blend_backward(gbr_ctx* ctx, const float* draw, const float* bases, const float* weights, int32_t B,
+                       int32_t K, int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream);
+
+/* gbr_render_backward followed by gbr_blend_backward for a batch rendered
+   from one blend (all frames share N = gauss_offsets[1]); draw lives in the
+   context's workspace. */
+int gbr_backward(gbr_ctx* ctx, const float* dimages, const float* bases, const float* weights, int32_t K,
+                 float* dbases, float* dweights, void* stream);
+
+/* Photometric loss over the frames of the last render (Sec. 3.2: L1 colour
+   loss; kind 1 = L1, 2 = L2), mean over every channel of every pixel.
+   Writes dimages (same packing) and keeps the loss value for
+   gbr_query_status.  Deterministic reduction order. */
+int gbr_loss(gbr_ctx* ctx, const float* images, const float* targets, int32_t kind, float* dimages, void* stream);
+
+/* Eq. 2, psi = F(theta): linear(d_in->hidden) + ReLU + linear(hidden->hidden)
+   + ReLU + linear(hidden->K).  params packed: W1 [hidden][d_in], b1 [hidden],
+   W2 [hidden][hidden], b2 [hidden], W3 [K][hidden], b3 [K].  theta [B][d_in],
+   psi [B][K].  Keeps activations for gbr_mlp_backward.
+   Limits: d_in <= 1024, hidden <= 1024, K <= 64. */
+int gbr_mlp_forward(gbr_ctx* ctx, const float* params, const float* theta, int32_t B, int32_t d_in, int32_t hidden,
+                    int32_t K, float* psi, void* stream);
+/* dpsi [B][K] -> dparams (same packing as params, overwritten). */
+int gbr_mlp_backward(gbr_ctx* ctx, const float* params, const float* dpsi, float* dparams, void* stream);
+
+/* Adam (Sec. A.3) on n parameters, in place on params/m/v.  Learning rate
+   of element i: lr_table[(i >= split) * 16 + (i % 16)] (host array [32]),
+   i.e. one 16-entry per-feature table for the first `split` elements (the
+   base model G_0) and one for the rest (the deltas); pass equal rows for a
+   uniform rate.  group (0..3) selects the device step counter used for the
+   bias correction; the counter advances only when the pass did not
+   overflow, and the update is skipped on overflow. */
+int gbr_adam_step(gbr_ctx* ctx, int32_t group, float* params, const float* grads, float* m, float* v, int64_t n,
+                  int64_t split, const float* lr_table, float beta1, float beta2, float eps, void* stream);
+
+/* The one host synchronisation per step: waits for `stream` and reads the
+   device status (entries, overflow flag, Adam step counters, loss). */
+int gbr_query_status(gbr_ctx* ctx, void* stream, gbr_status* out);
+
+/* Re-stage the per-frame table (cameras, Gaussian offsets) of the last
+   render without enqueueing work, so that a graph captured around gbr_render
+   replays with new cameras.  B and every frame's size must match the
+   captured call.  Call only when the previous replay has completed. */
+int gbr_stage_frames(gbr_ctx* ctx, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B);
+
+/* Graph capture of the work enqueued on `stream` between begin and end
+   (one captured training step replayed with a single launch). */
+int gbr_graph_begin(gbr_ctx* ctx, void* stream);
+int gbr_graph_end(gbr_ctx* ctx, void* stream, gbr_graph** out);
+int gbr_graph_launch(gbr_graph* g, void* stream);
+int gbr_graph_destroy(gbr_graph* g);
+
+/* Autotuner: renders and back-propagates the given frames once per
+   (tile, chunk) in {8,16,32} x {64,128,256}, times each on `stream`, keeps
+   the fastest in the context and reports it (times_ms: host [9], may be
+   NULL; entries beyond capacity grow it).  Synchronises. */
+int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B,
+                 float* images_scratch, float* dimages_scratch, float* draw_scratch, void* stream,
+                 int32_t* best_tile, int32_t* best_chunk, float* times_ms);
+
+/* Copy an internal buffer of the last pass to host memory (synchronises).
+   what: 1 splat records [S][12] f32 (mx, my, ca, cb, cc, opacity, r, g, b,
+   depth, -, -; ca, cb, cc = -log2(e) * (A/2, B, C/2) of the conic
+   q = A dx^2 + 2B dx dy + C dy^2), 2 tile rects [S][4] i32 (inclusive
+   tx0, ty0, tx1, ty1), 3 tile starts [tiles+1] u32 (tile g's entries are
+   [start[g], start[g+1]) of the sorted list), 4 sorted entries [entries] u32
+   (global splat index),
+   5 per-pixel contributor counts [pixels] u32, 6 per-pixel final
+   transmittance [pixels] f32, 7 per-tile last entry used [tiles] u32.
+   *bytes in: capacity of dst; out: bytes written. */
+int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBR_H */

@@ -1,0 +1,619 @@
+// C ABI of libgbr: context and workspace management, host-side validation,
+// and the enqueue order of the batch-parallel pass (preprocess and rasterize
+// of a whole batch of frames with no host synchronisation in between; the
+// only synchronisation of a training step is gbr_query_status).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "gbr.h"
+#include "gbr_internal.h"
+
+using namespace gbr;
+
+namespace {
+
+constexpr int kSlots = 5;          // pinned frame-table slots; the last one is used under graph capture
+constexpr int kCaptureSlot = kSlots - 1;
+constexpr int kMaxK = 63;
+constexpr int kMaxFramesHard = 4096;
+
+#define GBR_HIP(x)                           \
+  do {                                       \
+    hipError_t e_ = (x);                     \
+    if (e_ != hipSuccess) return GBR_ERR_HIP; \
+  } while (0)
+
+template <typename T>
+int dalloc(T** p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)count) != hipSuccess) return GBR_ERR_OOM;
+  return GBR_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+__global__ void begin_pass_kernel(uint32_t* tile_count, uint32_t* tile_cursor, int n_tiles, StatusDev* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_tiles) { tile_count[i] = 0u; tile_cursor[i] = 0u; }
+  if (i == 0) { status->overflow = 0u; status->entries = 0ull; }
+}
+
+__global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u; }
+
+}  // namespace
+
+struct gbr_ctx {
+  gbr_config cfg;
+  int tile = 16, chunk = 128;
+  int64_t cap_entries = 0, cap_splats = 0, cap_pixels = 0, cap_tiles = 0;
+  int cap_frames = 0;
+  // device workspace
+  FrameDev* d_frames = nullptr;
+  StatusDev* d_status = nullptr;
+  float* rec = nullptr;
+  int4* rect = nullptr;
+  uint32_t *cnt = nullptr, *soff = nullptr;
+  uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_cursor = nullptr, *tile_last = nullptr;
+  unsigned long long *keys = nullptr, *keys_alt = nullptr;
+  uint32_t *sorted = nullptr, *pos = nullptr;
+  float* part = nullptr;
+  uint32_t* n_iter = nullptr;
+  float* t_final = nullptr;
+  uint32_t* scan_scratch = nullptr;
+  float* draw_scratch = nullptr;
+  float* loss_part = nullptr;
+  float* blend_part = nullptr;
+  int64_t blend_part_n = 0;
+  float *mlp_z1 = nullptr, *mlp_z2 = nullptr, *mlp_dz1 = nullptr, *mlp_dz2 = nullptr;
+  // host staging
+  FrameDev* h_frames = nullptr;    // [kSlots][cap_frames] pinned
+  hipEvent_t slot_ev[kSlots] = {};
+  bool slot_used[kSlots] = {};
+  int next_slot = 0;
+  StatusDev* h_status = nullptr;   // pinned
+  // pass state
+  bool capturing = false;
+  bool have_pre = false, have_raster = false;
+  int B = 0;
+  int64_t n_splats = 0, n_pixels = 0, max_frame_splats = 0;
+  int n_tiles = 0;
+  const float* last_raw = nullptr;
+  std::vector<FrameDev> frames_host;
+  // MLP state
+  const float* mlp_theta = nullptr;
+  int mlp_B = 0, mlp_din = 0, mlp_hidden = 0, mlp_K = 0;
+  bool have_mlp = false;
+};
+
+struct gbr_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+PassArgs make_args(gbr_ctx* c) {
+  PassArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.frames = c->d_frames;
+  a.B = c->B;
+  a.tile = c->tile;
+  a.n_tiles = c->n_tiles;
+  a.n_splats = c->n_splats;
+  a.n_pixels = c->n_pixels;
+  a.cap_entries = c->cap_entries;
+  a.status = c->d_status;
+  a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff;
+  a.tile_count = c->tile_count; a.tile_start = c->tile_start; a.tile_cursor = c->tile_cursor;
+  a.tile_last = c->tile_last;
+  a.keys = c->keys; a.keys_alt = c->keys_alt; a.sorted = c->sorted; a.pos = c->pos;
+  a.n_iter = c->n_iter; a.t_final = c->t_final; a.part = c->part;
+  return a;
+}
+
+bool finite(float x) { return std::isfinite(x); }
+
+int check_tiling(int tile, int chunk) {
+  if (tile != 8 && tile != 16 && tile != 32) return GBR_ERR_INVALID_ARG;
+  if (chunk != 64 && chunk != 128 && chunk != 256) return GBR_ERR_INVALID_ARG;
+  return GBR_OK;
+}
+
+int alloc_entries(gbr_ctx* c, int64_t cap) {
+  dfree(c->keys); dfree(c->keys_alt); dfree(c->sorted); dfree(c->pos); dfree(c->part);
+  int rc = GBR_OK;
+  if ((rc = dalloc(&c->keys, cap))) return rc;
+  if ((rc = dalloc(&c->keys_alt, cap))) return rc;
+  if ((rc = dalloc(&c->sorted, cap))) return rc;
+  if ((rc = dalloc(&c->pos, cap))) return rc;
+  if ((rc = dalloc(&c->part, cap * 9))) return rc;
+  c->cap_entries = cap;
+  return GBR_OK;
+}
+
+void free_all(gbr_ctx* c) {
+  dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff);
+  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_cursor); dfree(c->tile_last);
+  dfree(c->keys); dfree(c->keys_alt); dfree(c->sorted); dfree(c->pos); dfree(c->part);
+  dfree(c->n_iter); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
+  dfree(c->loss_part); dfree(c->blend_part);
+  dfree(c->mlp_z1); dfree(c->mlp_z2); dfree(c->mlp_dz1); dfree(c->mlp_dz2);
+  if (c->h_frames) (void)hipHostFree(c->h_frames);
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  c->h_frames = nullptr; c->h_status = nullptr;
+  for (int i = 0; i < kSlots; ++i)
+    if (c->slot_ev[i]) (void)hipEventDestroy(c->slot_ev[i]);
+}
+
+// Validates the frame list and fills the device frame table (host copy).
+int build_frames(gbr_ctx* c, const int64_t* goff, const gbr_camera* cams, int B, std::vector<FrameDev>& out,
+                 int* n_tiles, int64_t* n_pix, int64_t* n_spl, int64_t* max_fs) {
+  if (B < 1 || !goff || !cams) return GBR_ERR_INVALID_ARG;
+  if (B > c->cap_frames) return GBR_ERR_CAPACITY;
+  if (goff[0] != 0) return GBR_ERR_INVALID_ARG;
+  out.resize(B);
+  int64_t tiles = 0, pix = 0, mfs = 0;
+  for (int b = 0; b < B; ++b) {
+    const gbr_camera& k = cams[b];
+    if (goff[b + 1] < goff[b]) return GBR_ERR_INVALID_ARG;
+    if (k.width < 1 || k.height < 1 || k.width > 16384 || k.height > 16384) return GBR_ERR_INVALID_ARG;
+    if (!finite(k.fx) || !finite(k.fy) || !finite(k.cx) || !finite(k.cy) || k.fx == 0.f || k.fy == 0.f)
+      return GBR_ERR_INVALID_ARG;
+    for (int i = 0; i < 9; ++i) if (!finite(k.R[i])) return GBR_ERR_INVALID_ARG;
+    for (int i = 0; i < 3; ++i) if (!finite(k.t[i]) || !finite(k.bg[i])) return GBR_ERR_INVALID_ARG;
+    if (!finite(k.near_z) || k.near_z < 0.f) return GBR_ERR_INVALID_ARG;
+    FrameDev& F = out[b];
+    F.fx = k.fx; F.fy = k.fy; F.cx = k.cx; F.cy = k.cy;
+    std::memcpy(F.R, k.R, sizeof(F.R));
+    std::memcpy(F.t, k.t, sizeof(F.t));
+    F.near_z = k.near_z;
+    std::memcpy(F.bg, k.bg, sizeof(F.bg));
+    F.W = k.width; F.H = k.height;
+    F.ntx = (k.width + c->tile - 1) / c->tile;
+    F.nty = (k.height + c->tile - 1) / c->tile;
+    F.n_tiles = F.ntx * F.nty;
+    F.tile_base = (int32_t)tiles;
+    F.pix_base = pix;
+    F.gauss_base = goff[b];
+    F.gauss_count = goff[b + 1] - goff[b];
+    tiles += F.n_tiles;
+    pix += (int64_t)k.width * k.height;
+    mfs = std::max(mfs, F.gauss_count);
+  }
+  if (goff[B] > c->cap_splats || pix > c->cap_pixels || tiles > c->cap_tiles) return GBR_ERR_CAPACITY;
+  *n_tiles = (int)tiles; *n_pix = pix; *n_spl = goff[B]; *max_fs = mfs;
+  return GBR_OK;
+}
+
+int stage_and_upload(gbr_ctx* c, hipStream_t s) {
+  int slot;
+  if (c->capturing) {
+    slot = kCaptureSlot;
+  } else {
+    slot = c->next_slot;
+    c->next_slot = (c->next_slot + 1) % (kSlots - 1);
+    if (c->slot_used[slot]) GBR_HIP(hipEventSynchronize(c->slot_ev[slot]));
+  }
+  FrameDev* h = c->h_frames + (int64_t)slot * c->cap_frames;
+  std::memcpy(h, c->frames_host.data(), sizeof(FrameDev) * c->B);
+  GBR_HIP(hipMemcpyAsync(c->d_frames, h, sizeof(FrameDev) * c->B, hipMemcpyHostToDevice, s));
+  if (!c->capturing) {
+    GBR_HIP(hipEventRecord(c->slot_ev[slot], s));
+    c->slot_used[slot] = true;
+  }
+  return GBR_OK;
+}
+
+int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
+  int rc = stage_and_upload(c, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(begin_pass_kernel, dim3(div_up(std::max(c->n_tiles, 1), 256)), dim3(256), 0, s, c->tile_count,
+                     c->tile_cursor, c->n_tiles, c->d_status);
+  PassArgs a = make_args(c);
+  launch_preprocess(a, raw, c->max_frame_splats, s);
+  launch_scan_u32(c->tile_count, c->tile_start, c->n_tiles, c->scan_scratch, c->d_status, c->cap_entries,
+                  &c->d_status->entries, s);
+  GBR_HIP(hipGetLastError());
+  c->last_raw = raw;
+  c->have_pre = true;
+  c->have_raster = false;
+  return GBR_OK;
+}
+
+int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
+  PassArgs a = make_args(c);
+  launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
+  launch_scatter(a, c->max_frame_splats, s);
+  launch_tile_sort(a, s);
+  launch_composite_fwd(a, images, c->chunk, s);
+  GBR_HIP(hipGetLastError());
+  c->have_raster = true;
+  return GBR_OK;
+}
+
+int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int B) {
+  if (!raw) return GBR_ERR_INVALID_ARG;
+  std::vector<FrameDev> fr;
+  int nt; int64_t np, ns, mfs;
+  int rc = build_frames(c, goff, cams, B, fr, &nt, &np, &ns, &mfs);
+  if (rc) return rc;
+  c->frames_host.swap(fr);
+  c->B = B; c->n_tiles = nt; c->n_pixels = np; c->n_splats = ns; c->max_frame_splats = mfs;
+  return GBR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gbr_strerror(int code) {
+  switch (code) {
+    case GBR_OK: return "ok";
+    case GBR_ERR_INVALID_ARG: return "invalid argument";
+    case GBR_ERR_CAPACITY: return "capacity exceeded (frames, splats, pixels or tiles)";
+    case GBR_ERR_OOM: return "device out of memory";
+    case GBR_ERR_HIP: return "HIP runtime error";
+    case GBR_ERR_STATE: return "call out of order (no preceding render/forward)";
+    case GBR_ERR_OVERFLOW: return "tile-entry capacity overflowed in the last pass";
+    default: return "unknown error";
+  }
+}
+
+int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
+  if (!cfg || !out) return GBR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (check_tiling(cfg->tile, cfg->chunk)) return GBR_ERR_INVALID_ARG;
+  if (cfg->max_frames < 1 || cfg->max_frames > kMaxFramesHard || cfg->max_splats < 1 || cfg->max_pixels < 1 ||
+      cfg->max_entries < 1 || cfg->max_splats >= (int64_t)UINT32_MAX || cfg->max_entries >= (int64_t)UINT32_MAX)
+    return GBR_ERR_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return GBR_ERR_HIP;
+  if (hipSetDevice(cfg->device) != hipSuccess) return GBR_ERR_HIP;
+  gbr_ctx* c = new gbr_ctx();
+  c->cfg = *cfg;
+  c->tile = cfg->tile; c->chunk = cfg->chunk;
+  c->cap_frames = cfg->max_frames;
+  c->cap_splats = cfg->max_splats;
+  c->cap_pixels = cfg->max_pixels;
+  // tiles at the smallest tile size, plus partial edge tiles of every frame
+  const int64_t edge = 2 * (int64_t)std::ceil(std::sqrt((double)cfg->max_pixels)) / 8 + 1;
+  c->cap_tiles = cfg->max_pixels / 64 + (int64_t)cfg->max_frames * (2 * edge + 1);
+  int rc = GBR_OK;
+#define TRY(x) do { if ((rc = (x))) { free_all(c); delete c; return rc; } } while (0)
+  TRY(dalloc(&c->d_frames, c->cap_frames));
+  TRY(dalloc(&c->d_status, 1));
+  TRY(dalloc(&c->rec, c->cap_splats * kRecF));
+  TRY(dalloc(&c->rect, c->cap_splats));
+  TRY(dalloc(&c->cnt, c->cap_splats));
+  TRY(dalloc(&c->soff, c->cap_splats + 1));
+  TRY(dalloc(&c->tile_count, c->cap_tiles));
+  TRY(dalloc(&c->tile_start, c->cap_tiles + 1));
+  TRY(dalloc(&c->tile_cursor, c->cap_tiles));
+  TRY(dalloc(&c->tile_last, c->cap_tiles));
+  TRY(dalloc(&c->n_iter, c->cap_pixels));
+  TRY(dalloc(&c->t_final, c->cap_pixels));
+  TRY(dalloc(&c->scan_scratch, scan_scratch_words(std::max(c->cap_splats, c->cap_tiles))));
+  TRY(dalloc(&c->draw_scratch, c->cap_splats * kNF));
+  TRY(dalloc(&c->loss_part, 2 * loss_partials(3 * c->cap_pixels) + 2));
+  c->blend_part_n = c->cap_splats + 256LL * c->cap_frames + 64LL * 64 * 8;
+  TRY(dalloc(&c->blend_part, c->blend_part_n));
+  TRY(dalloc(&c->mlp_z1, (int64_t)c->cap_frames * 1024));
+  TRY(dalloc(&c->mlp_z2, (int64_t)c->cap_frames * 1024));
+  TRY(dalloc(&c->mlp_dz1, (int64_t)c->cap_frames * 1024));
+  TRY(dalloc(&c->mlp_dz2, (int64_t)c->cap_frames * 1024));
+  TRY(alloc_entries(c, cfg->max_entries));
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_frames), sizeof(FrameDev) * kSlots * c->cap_frames,
+                    hipHostMallocDefault) != hipSuccess) TRY(GBR_ERR_OOM);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(StatusDev), hipHostMallocDefault) != hipSuccess)
+    TRY(GBR_ERR_OOM);
+  for (int i = 0; i < kSlots; ++i)
+    if (hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming) != hipSuccess) TRY(GBR_ERR_HIP);
+  StatusDev zero;
+  std::memset(&zero, 0, sizeof(zero));
+  if (hipMemcpy(c->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) TRY(GBR_ERR_HIP);
+#undef TRY
+  *out = c;
+  return GBR_OK;
+}
+
+int gbr_destroy(gbr_ctx* c) {
+  if (!c) return GBR_ERR_INVALID_ARG;
+  (void)hipSetDevice(c->cfg.device);
+  (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return GBR_OK;
+}
+
+int gbr_reserve(gbr_ctx* c, int64_t max_entries) {
+  if (!c || max_entries < 1 || max_entries >= (int64_t)UINT32_MAX) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  if (max_entries <= c->cap_entries) return GBR_OK;
+  GBR_HIP(hipDeviceSynchronize());
+  int rc = alloc_entries(c, max_entries);
+  c->have_raster = false;
+  return rc;
+}
+
+int gbr_set_tiling(gbr_ctx* c, int32_t tile, int32_t chunk) {
+  if (!c || check_tiling(tile, chunk)) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  c->tile = tile; c->chunk = chunk;
+  c->have_pre = c->have_raster = false;
+  return GBR_OK;
+}
+
+int gbr_blend(gbr_ctx* c, const float* bases, const float* weights, int32_t B, int32_t K, int64_t N, float* raw,
+              void* stream) {
+  if (!c || !bases || !raw || B < 1 || K < 0 || K > kMaxK || N < 1 || (K > 0 && !weights)) return GBR_ERR_INVALID_ARG;
+  launch_blend_fwd(bases, weights, B, K, N, raw, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_preprocess(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B,
+                   void* stream) {
+  if (!c) return GBR_ERR_INVALID_ARG;
+  int rc = set_pass(c, raw, goff, cams, B);
+  if (rc) return rc;
+  return enqueue_preprocess(c, raw, (hipStream_t)stream);
+}
+
+int gbr_entry_count(gbr_ctx* c, void* stream, int64_t* entries) {
+  if (!c || !entries) return GBR_ERR_INVALID_ARG;
+  if (!c->have_pre) return GBR_ERR_STATE;
+  if (c->capturing) return GBR_ERR_STATE;
+  hipStream_t s = (hipStream_t)stream;
+  GBR_HIP(hipMemcpyAsync(c->h_status, c->d_status, sizeof(StatusDev), hipMemcpyDeviceToHost, s));
+  GBR_HIP(hipStreamSynchronize(s));
+  *entries = (int64_t)c->h_status->entries;
+  if (*entries > c->cap_entries) {
+    int rc = gbr_reserve(c, *entries + *entries / 4 + 1024);
+    if (rc) return rc;
+    hipLaunchKernelGGL(clear_overflow_kernel, dim3(1), dim3(1), 0, s, c->d_status);
+    GBR_HIP(hipGetLastError());
+  }
+  return GBR_OK;
+}
+
+int gbr_rasterize(gbr_ctx* c, float* images, void* stream) {
+  if (!c || !images) return GBR_ERR_INVALID_ARG;
+  if (!c->have_pre) return GBR_ERR_STATE;
+  return enqueue_rasterize(c, images, (hipStream_t)stream);
+}
+
+int gbr_render(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B, float* images,
+               void* stream) {
+  if (!c || !images) return GBR_ERR_INVALID_ARG;
+  int rc = gbr_preprocess(c, raw, goff, cams, B, stream);
+  if (rc) return rc;
+  return enqueue_rasterize(c, images, (hipStream_t)stream);
+}
+
+int gbr_render_backward(gbr_ctx* c, const float* dimages, float* draw, void* stream) {
+  if (!c || !dimages || !draw) return GBR_ERR_INVALID_ARG;
+  if (!c->have_raster) return GBR_ERR_STATE;
+  hipStream_t s = (hipStream_t)stream;
+  PassArgs a = make_args(c);
+  launch_composite_bwd(a, dimages, nullptr, c->chunk, s);
+  launch_gather_bwd(a, c->last_raw, draw, s);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_blend_backward(gbr_ctx* c, const float* draw, const float* bases, const float* weights, int32_t B,
+                       int32_t K, int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream) {
+  if (!c || !draw || !bases || !dbases || B < 1 || B > 64 || K < 0 || K > kMaxK || N < 1) return GBR_ERR_INVALID_ARG;
+  if (K > 0 && (!weights || !dweights)) return GBR_ERR_INVALID_ARG;
+  if ((int64_t)B * N > c->cap_splats) return GBR_ERR_CAPACITY;
+  if (blend_bwd_partials(B, K, N) > c->blend_part_n) return GBR_ERR_CAPACITY;
+  launch_blend_bwd(draw, bases, weights, B, K, N, dbases, dweights, c->blend_part, c->blend_part_n, accumulate,
+                   (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_backward(gbr_ctx* c, const float* dimages, const float* bases, const float* weights, int32_t K,
+                 float* dbases, float* dweights, void* stream) {
+  if (!c) return GBR_ERR_INVALID_ARG;
+  if (!c->have_raster) return GBR_ERR_STATE;
+  const int64_t N = c->frames_host.empty() ? 0 : c->frames_host[0].gauss_count;
+  for (int b = 0; b < c->B; ++b)
+    if (c->frames_host[b].gauss_count != N || c->frames_host[b].gauss_base != (int64_t)b * N)
+      return GBR_ERR_INVALID_ARG;
+  int rc = gbr_render_backward(c, dimages, c->draw_scratch, stream);
+  if (rc) return rc;
+  return gbr_blend_backward(c, c->draw_scratch, bases, weights, c->B, K, N, dbases, dweights, 0, stream);
+}
+
+int gbr_loss(gbr_ctx* c, const float* images, const float* targets, int32_t kind, float* dimages, void* stream) {
+  if (!c || !images || !targets || !dimages || (kind != 1 && kind != 2)) return GBR_ERR_INVALID_ARG;
+  if (!c->have_pre) return GBR_ERR_STATE;
+  PassArgs a = make_args(c);
+  launch_loss(a, images, targets, kind, dimages, c->loss_part, 0, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_mlp_forward(gbr_ctx* c, const float* params, const float* theta, int32_t B, int32_t d_in, int32_t hidden,
+                    int32_t K, float* psi, void* stream) {
+  if (!c || !params || !theta || !psi || B < 1 || d_in < 1 || d_in > 1024 || hidden < 1 || hidden > 1024 || K < 1 ||
+      K > 64)
+    return GBR_ERR_INVALID_ARG;
+  if (B > c->cap_frames) return GBR_ERR_CAPACITY;
+  launch_mlp_fwd(params, theta, B, d_in, hidden, K, psi, c->mlp_z1, c->mlp_z2, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  c->mlp_theta = theta; c->mlp_B = B; c->mlp_din = d_in; c->mlp_hidden = hidden; c->mlp_K = K;
+  c->have_mlp = true;
+  return GBR_OK;
+}
+
+int gbr_mlp_backward(gbr_ctx* c, const float* params, const float* dpsi, float* dparams, void* stream) {
+  if (!c || !params || !dpsi || !dparams) return GBR_ERR_INVALID_ARG;
+  if (!c->have_mlp) return GBR_ERR_STATE;
+  launch_mlp_bwd(params, c->mlp_theta, c->mlp_z1, c->mlp_z2, dpsi, c->mlp_B, c->mlp_din, c->mlp_hidden, c->mlp_K,
+                 c->mlp_dz1, c->mlp_dz2, dparams, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_adam_step(gbr_ctx* c, int32_t group, float* params, const float* grads, float* m, float* v, int64_t n,
+                  int64_t split, const float* lr_table, float beta1, float beta2, float eps, void* stream) {
+  if (!c || group < 0 || group > 3 || n < 0 || !lr_table || (n > 0 && (!params || !grads || !m || !v)))
+    return GBR_ERR_INVALID_ARG;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return GBR_ERR_INVALID_ARG;
+  for (int i = 0; i < 32; ++i)
+    if (!finite(lr_table[i])) return GBR_ERR_INVALID_ARG;
+  launch_adam(c->d_status, group, params, grads, m, v, n, split, lr_table, beta1, beta2, eps, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_query_status(gbr_ctx* c, void* stream, gbr_status* out) {
+  if (!c || !out) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  hipStream_t s = (hipStream_t)stream;
+  GBR_HIP(hipMemcpyAsync(c->h_status, c->d_status, sizeof(StatusDev), hipMemcpyDeviceToHost, s));
+  GBR_HIP(hipStreamSynchronize(s));
+  const StatusDev& h = *c->h_status;
+  out->entries = (int64_t)h.entries;
+  out->entries_capacity = c->cap_entries;
+  out->overflow = (int32_t)h.overflow;
+  for (int i = 0; i < 4; ++i) out->adam_steps[i] = h.adam_step[i];
+  out->loss = h.loss;
+  return GBR_OK;
+}
+
+int gbr_stage_frames(gbr_ctx* c, const int64_t* goff, const gbr_camera* cams, int32_t B) {
+  if (!c) return GBR_ERR_INVALID_ARG;
+  if (!c->have_pre || B != c->B) return GBR_ERR_STATE;
+  std::vector<FrameDev> fr;
+  int nt; int64_t np, ns, mfs;
+  int rc = build_frames(c, goff, cams, B, fr, &nt, &np, &ns, &mfs);
+  if (rc) return rc;
+  for (int b = 0; b < B; ++b) {
+    const FrameDev &x = fr[b], &y = c->frames_host[b];
+    if (x.W != y.W || x.H != y.H || x.gauss_base != y.gauss_base || x.gauss_count != y.gauss_count)
+      return GBR_ERR_INVALID_ARG;
+  }
+  c->frames_host.swap(fr);
+  std::memcpy(c->h_frames + (int64_t)kCaptureSlot * c->cap_frames, c->frames_host.data(), sizeof(FrameDev) * B);
+  return GBR_OK;
+}
+
+int gbr_graph_begin(gbr_ctx* c, void* stream) {
+  if (!c || c->capturing) return GBR_ERR_STATE;
+  GBR_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed));
+  c->capturing = true;
+  return GBR_OK;
+}
+
+int gbr_graph_end(gbr_ctx* c, void* stream, gbr_graph** out) {
+  if (!c || !out || !c->capturing) return GBR_ERR_STATE;
+  c->capturing = false;
+  gbr_graph* g = new gbr_graph();
+  if (hipStreamEndCapture((hipStream_t)stream, &g->graph) != hipSuccess) { delete g; return GBR_ERR_HIP; }
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return GBR_ERR_HIP;
+  }
+  *out = g;
+  return GBR_OK;
+}
+
+int gbr_graph_launch(gbr_graph* g, void* stream) {
+  if (!g) return GBR_ERR_INVALID_ARG;
+  GBR_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return GBR_OK;
+}
+
+int gbr_graph_destroy(gbr_graph* g) {
+  if (!g) return GBR_ERR_INVALID_ARG;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return GBR_OK;
+}
+
+int gbr_autotune(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B,
+                 float* images, float* dimages, float* draw, void* stream, int32_t* best_tile, int32_t* best_chunk,
+                 float* times_ms) {
+  if (!c || !raw || !images || !dimages || !draw) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  hipStream_t s = (hipStream_t)stream;
+  const int tiles[3] = {8, 16, 32}, chunks[3] = {64, 128, 256};
+  hipEvent_t e0, e1;
+  GBR_HIP(hipEventCreate(&e0));
+  GBR_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bt = c->tile, bc = c->chunk;
+  int rc = GBR_OK;
+  for (int ti = 0; ti < 3 && !rc; ++ti)
+    for (int ci = 0; ci < 3 && !rc; ++ci) {
+      rc = gbr_set_tiling(c, tiles[ti], chunks[ci]);
+      if (rc) break;
+      // make sure the entry buffers fit this tile size
+      rc = gbr_preprocess(c, raw, goff, cams, B, stream);
+      if (rc) break;
+      int64_t e = 0;
+      rc = gbr_entry_count(c, stream, &e);
+      if (rc) break;
+      float ms = 0.f;
+      for (int rep = 0; rep < 3 && !rc; ++rep) {
+        (void)hipEventRecord(e0, s);
+        rc = gbr_render(c, raw, goff, cams, B, images, stream);
+        if (!rc) rc = gbr_render_backward(c, dimages, draw, stream);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        if (rep == 0 || t < ms) ms = t;
+      }
+      if (times_ms) times_ms[ti * 3 + ci] = ms;
+      if (!rc && ms < best) { best = ms; bt = tiles[ti]; bc = chunks[ci]; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = gbr_set_tiling(c, bt, bc);
+  if (best_tile) *best_tile = bt;
+  if (best_chunk) *best_chunk = bc;
+  return rc;
+}
+
+int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
+  if (!c || !dst || !bytes) return GBR_ERR_INVALID_ARG;
+  if (!c->have_pre) return GBR_ERR_STATE;
+  GBR_HIP(hipDeviceSynchronize());
+  const void* src = nullptr;
+  int64_t n = 0;
+  StatusDev st;
+  GBR_HIP(hipMemcpy(&st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
+  const int64_t entries = std::min<int64_t>((int64_t)st.entries, c->cap_entries);
+  switch (what) {
+    case 1: src = c->rec; n = c->n_splats * kRecF * 4; break;
+    case 2: src = c->rect; n = c->n_splats * 16; break;
+    case 3: src = c->tile_start; n = ((int64_t)c->n_tiles + 1) * 4; break;
+    case 4: src = c->sorted; n = entries * 4; break;
+    case 5: src = c->n_iter; n = c->n_pixels * 4; break;
+    case 6: src = c->t_final; n = c->n_pixels * 4; break;
+    case 7: src = c->tile_last; n = (int64_t)c->n_tiles * 4; break;
+    default: return GBR_ERR_INVALID_ARG;
+  }
+  if ((what >= 4) && !c->have_raster) return GBR_ERR_STATE;
+  if (*bytes < n) return GBR_ERR_CAPACITY;
+  if (n > 0) GBR_HIP(hipMemcpy(dst, src, (size_t)n, hipMemcpyDeviceToHost));
+  *bytes = n;
+  return GBR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal definitions shared by the libgbr kernels and the host side of the
+// library (device structs, launch helpers, wave-level primitives).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbr {
+
+constexpr int kNF = 16;                    // stored floats per blended Gaussian
+constexpr float kAlphaMin = 1.0f / 255.0f; // contribution threshold
+constexpr float kAlphaMax = 0.99f;         // opacity clamp
+constexpr float kTMin = 1e-4f;             // transmittance stop
+constexpr double kLowPass = 0.3;           // px^2 added to the 2D covariance
+constexpr double kBoxPad = 0.01;           // px added to the alpha-support box
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+constexpr int kRecF = 12;                  // floats per splat record
+constexpr int kMaxFrameTilesLds = 4096;    // per-frame tile histogram kept in LDS
+
+// Per-frame table entry, built on the host for every render and uploaded
+// with the pass.
+struct FrameDev {
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float near_z;
+  float bg[3];
+  int32_t W, H, ntx, nty;
+  int32_t tile_base;   // first global tile id of the frame
+  int32_t n_tiles;
+  int64_t pix_base;    // first pixel of the frame in the packed pixel space
+  int64_t gauss_base;  // first splat of the frame
+  int64_t gauss_count;
+};
+
+// Device-side status of a pass; read once per step by gbr_query_status.
+struct StatusDev {
+  unsigned long long entries;
+  unsigned int overflow;
+  unsigned int pad0;
+  int32_t adam_step[4];
+  float loss;
+  float adam_bc[2];        // bias corrections 1 - beta^t of the last Adam step
+  float pad1;
+};
+
+// Everything the pass kernels need, passed by value.
+struct PassArgs {
+  const FrameDev* frames;
+  int32_t B;
+  int32_t tile;
+  int32_t n_tiles;          // total tiles of the pass
+  int32_t pad;
+  int64_t n_splats;
+  int64_t n_pixels;
+  int64_t cap_entries;
+  StatusDev* status;
+  // splat stage
+  float* rec;               // [S][12]: mx my ca cb | cc o r g | b depth - -
+  int4* rect;               // [S] inclusive tile rect (tx0, ty0, tx1, ty1)
+  uint32_t* cnt;            // [S] tiles touched
+  uint32_t* soff;           // [S] exclusive scan of cnt (emission offsets)
+  // tile stage
+  uint32_t* tile_count;     // [tiles]
+  uint32_t* tile_start;     // [tiles + 1]
+  uint32_t* tile_cursor;    // [tiles]
+  uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel
+  unsigned long long* keys; // [E] (depth bits << 32) | splat
+  unsigned long long* keys_alt; // [E] ping-pong for oversized tiles
+  uint32_t* sorted;         // [E] splat index in tile order
+  uint32_t* pos;            // [E] emission slot -> sorted position
+  // pixel stage
+  uint32_t* n_iter;         // [pixels]
+  float* t_final;           // [pixels]
+  float* part;              // [E][9] per-entry gradient partials
+};
+
+__device__ __forceinline__ int frame_of_tile(const FrameDev* frames, int B, int g) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (frames[mid].tile_base <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int frame_of_splat(const FrameDev* frames, int B, int64_t s) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (frames[mid].gauss_base <= s) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// popcount(mask & lanes below this one)
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float,
+      __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK, BANK_MASK, BOUND_CTRL));
+}
+
+// Sum over the 64 lanes of a wave in a fixed order; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to63(float v) {
+  v += dpp_mov<0x111, 0xf, 0xf, true>(v);   // row_shr:1
+  v += dpp_mov<0x112, 0xf, 0xf, true>(v);   // row_shr:2
+  v += dpp_mov<0x114, 0xf, 0xe, false>(v);  // row_shr:4, banks 1-3
+  v += dpp_mov<0x118, 0xf, 0xc, false>(v);  // row_shr:8, banks 2-3
+  v += dpp_mov<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1, 3
+  v += dpp_mov<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace gbr
+
+// Kernel launchers (defined in the .hip files).
+namespace gbr {
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+void launch_blend_fwd(const float* bases, const float* weights, int B, int K, int64_t N, float* raw, hipStream_t s);
+void launch_blend_bwd(const float* draw, const float* bases, const float* weights, int B, int K, int64_t N,
+                      float* dbases, float* dweights, float* partials, int64_t n_partials, int accumulate,
+                      hipStream_t s);
+int64_t blend_bwd_partials(int B, int K, int64_t N);
+void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums, StatusDev* status,
+                     int64_t cap_check, unsigned long long* total_out, hipStream_t s);
+int64_t scan_scratch_words(int64_t n);
+void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
+void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s);
+void launch_tile_sort(const PassArgs& a, hipStream_t s);
+void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
+void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
+void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s);
+void launch_loss(const PassArgs& a, const float* images, const float* targets, int kind, float* dimages,
+                 float* partials, int64_t n_partials, hipStream_t s);
+int64_t loss_partials(int64_t n_floats);
+void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, int hidden, int K, float* psi,
+                    float* z1, float* z2, hipStream_t s);
+void launch_mlp_bwd(const float* params, const float* theta, const float* z1, const float* z2, const float* dpsi,
+                    int B, int d_in, int hidden, int K, float* dz1, float* dz2, float* dparams, hipStream_t s);
+void launch_adam(StatusDev* status, int group, float* p, const float* g, float* m, float* v, int64_t n,
+                 int64_t split, const float* lr_table_host, float b1, float b2, float eps, hipStream_t s);
+}  // namespace gbr

@@ -1,0 +1,361 @@
+// Backward half of the batch-parallel rasterizer: per-tile reverse traversal
+// of the compositing recurrence, per-entry partial gradients reduced across
+// the tile's pixels without atomics, a fixed-order gather per splat, and the
+// adjoint of activation + EWA projection.  Also the photometric loss.
+#include "gbr_internal.h"
+
+namespace gbr {
+
+template <int T> struct TileShapeB {
+  static constexpr int NT = (T == 8) ? 64 : 256;
+  static constexpr int PXW = (T == 32) ? 2 : 1;
+  static constexpr int PX = PXW * PXW;
+  static constexpr int TPR = T / PXW;
+  static constexpr int NW = NT / 64;
+};
+
+// Must stay bit-identical to the forward kernel's alpha.
+__device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, float py, float& dx, float& dy,
+                                               float& pw_raw, float& g2) {
+#pragma clang fp contract(off)
+  dx = px - r0.x;
+  dy = py - r0.y;
+  float pw = (r0.z * dx) * dx;
+  pw = __builtin_fmaf(r0.w * dx, dy, pw);
+  pw = __builtin_fmaf(r1.x * dy, dy, pw);
+  pw_raw = pw;
+  pw = fminf(pw, 0.0f);
+  g2 = __builtin_amdgcn_exp2f(pw);
+  return r1.y * g2;
+}
+
+// Per-entry partial, summed over the tile's pixels:
+//   (d mx, d my, d ca, d cb, d cc, d opacity, d r, d g, d b)
+// where ca, cb, cc are the log2-scaled conic coefficients of the record.
+template <int T, int CHUNK>
+__global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassArgs a,
+                                                                         const float* __restrict__ dimages) {
+  using S = TileShapeB<T>;
+  __shared__ float4 s0[CHUNK];
+  __shared__ float4 s1[CHUNK];
+  __shared__ float s2[CHUNK];
+  __shared__ float red[CHUNK][S::NW][9];
+  if (a.status->overflow) return;
+  const int g = blockIdx.x;
+  const uint32_t L = a.tile_last[g];
+  if (L == 0) return;
+  const int b = frame_of_tile(a.frames, a.B, g);
+  const FrameDev& F = a.frames[b];
+  const int lt = g - F.tile_base;
+  const int tx = lt % F.ntx, ty = lt / F.ntx;
+  const uint32_t start = a.tile_start[g];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lx0 = (threadIdx.x % S::TPR) * S::PXW, ly0 = (threadIdx.x / S::TPR) * S::PXW;
+  float T_[S::PX], R0[S::PX], R1[S::PX], R2[S::PX], G0[S::PX], G1[S::PX], G2[S::PX];
+  uint32_t nit[S::PX];
+  float pxf[S::PX], pyf[S::PX];
+  const float* img_g = dimages + F.pix_base * 3;
+  const int64_t hw = (int64_t)F.W * F.H;
+#pragma unroll
+  for (int p = 0; p < S::PX; ++p) {
+    const int px = tx * T + lx0 + (p % S::PXW), py = ty * T + ly0 + (p / S::PXW);
+    pxf[p] = (float)px + 0.5f;
+    pyf[p] = (float)py + 0.5f;
+    nit[p] = 0; T_[p] = 1.0f; R0[p] = R1[p] = R2[p] = 0.0f; G0[p] = G1[p] = G2[p] = 0.0f;
+    if (px < F.W && py < F.H) {
+      const int64_t pix = (int64_t)py * F.W + px;
+      nit[p] = a.n_iter[F.pix_base + pix];
+      T_[p] = a.t_final[F.pix_base + pix];
+      G0[p] = img_g[pix]; G1[p] = img_g[hw + pix]; G2[p] = img_g[2 * hw + pix];
+      // suffix colour behind the current entry, starts as T_end * background
+      R0[p] = T_[p] * F.bg[0]; R1[p] = T_[p] * F.bg[1]; R2[p] = T_[p] * F.bg[2];
+    }
+  }
+  for (int ce = (int)L; ce > 0; ce -= CHUNK) {
+    const int cbeg = max(0, ce - CHUNK);
+    const int n = ce - cbeg;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += S::NT) {
+      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[start + cbeg + i] * kRecF);
+      s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+    }
+    __syncthreads();
+    for (int i = n - 1; i >= 0; --i) {
+      const uint32_t li = (uint32_t)(cbeg + i);
+      const float4 r0 = s0[i], r1 = s1[i];
+      const float cbl = s2[i];
+      float acc[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+      bool any = false;
+#pragma unroll
+      for (int p = 0; p < S::PX; ++p) {
+        if (li >= nit[p]) continue;
+        float dx, dy, pwr, g2;
+        const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr, g2);
+        if (a0 < kAlphaMin) continue;
+        any = true;
+        const float al = fminf(a0, kAlphaMax);
+        const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+        const float Ti = T_[p] * inv;                     // transmittance in front of this entry
+        const float wgt = al * Ti;
+        acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
+        const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];
+        const float rg = R0[p] * G0[p] + R1[p] * G1[p] + R2[p] * G2[p];
+        const float dal = Ti * cg - rg * inv;             // d out / d alpha
+        R0[p] += wgt * r1.z; R1[p] += wgt * r1.w; R2[p] += wgt * cbl;
+        T_[p] = Ti;
+        const float da = (a0 < kAlphaMax) ? dal : 0.0f;   // min(0.99, .) passes the gradient only below the clamp
+        acc[5] += g2 * da;
+        const float dpw = (pwr > 0.0f) ? 0.0f : da * a0 * (float)kLn2;
+        acc[2] += dpw * dx * dx;
+        acc[3] += dpw * dx * dy;
+        acc[4] += dpw * dy * dy;
+        acc[0] -= dpw * (2.0f * r0.z * dx + r0.w * dy);
+        acc[1] -= dpw * (r0.w * dx + 2.0f * r1.x * dy);
+      }
+      if (__ballot(any) != 0ull) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] = wave_sum_to63(acc[c]);
+      }
+      if (lane == 63) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) red[i][w][c] = acc[c];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += S::NT) {
+      float* dst = a.part + (int64_t)(start + cbeg + i) * 9;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        float v = red[i][0][c];
+#pragma unroll
+        for (int ww = 1; ww < S::NW; ++ww) v += red[i][ww][c];
+        dst[c] = v;
+      }
+    }
+  }
+}
+
+void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s) {
+  (void)images;
+  if (a.n_tiles == 0) return;
+  const dim3 grid(a.n_tiles);
+#define GBR_BWD(TT, CC) \
+  hipLaunchKernelGGL((composite_bwd_kernel<TT, CC>), grid, dim3(TileShapeB<TT>::NT), 0, s, a, dimages)
+#define GBR_BWD_T(TT)                      \
+  if (chunk == 64) GBR_BWD(TT, 64);        \
+  else if (chunk == 128) GBR_BWD(TT, 128); \
+  else GBR_BWD(TT, 256);
+  if (a.tile == 8) { GBR_BWD_T(8) }
+  else if (a.tile == 16) { GBR_BWD_T(16) }
+  else { GBR_BWD_T(32) }
+#undef GBR_BWD_T
+#undef GBR_BWD
+}
+
+// ---------------------------------------------------------------- gather + projection adjoint
+// One thread per splat: sums its entries' partials in row-major tile order
+// (entries past a tile's last used position were never written and are
+// zero by definition), then chains back through the conic, the EWA
+// projection and the activations in float64.
+__global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float* __restrict__ raw,
+                                                         float* __restrict__ draw) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= a.n_splats) return;
+  float4* out = reinterpret_cast<float4*>(draw + s * kNF);
+  const uint32_t c = a.cnt[s];
+  if (a.status->overflow || c == 0) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    out[0] = z; out[1] = z; out[2] = z; out[3] = z;
+    return;
+  }
+  const int b = frame_of_splat(a.frames, a.B, s);
+  const FrameDev& F = a.frames[b];
+  const int4 r = a.rect[s];
+  const uint32_t off = a.soff[s];
+  float acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+  uint32_t j = 0;
+  for (int ty = r.y; ty <= r.w; ++ty)
+    for (int tx = r.x; tx <= r.z; ++tx, ++j) {
+      const int gt = F.tile_base + ty * F.ntx + tx;
+      const uint32_t p = a.pos[off + j];
+      if (p - a.tile_start[gt] < a.tile_last[gt]) {
+        const float* q = a.part + (int64_t)p * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += q[k];
+      }
+    }
+
+  // ---- recompute the forward quantities (float64) ----
+  const float* gp = raw + s * kNF;
+  const double mu0 = gp[0], mu1 = gp[1], mu2 = gp[2];
+  double R[9], tcam[3];
+  for (int i = 0; i < 9; ++i) R[i] = F.R[i];
+  for (int i = 0; i < 3; ++i) tcam[i] = R[3 * i] * mu0 + R[3 * i + 1] * mu1 + R[3 * i + 2] * mu2 + (double)F.t[i];
+  const double tx = tcam[0], ty = tcam[1], tz = tcam[2];
+  const double qraw[4] = {gp[3], gp[4], gp[5], gp[6]};
+  const double qn2 = qraw[0] * qraw[0] + qraw[1] * qraw[1] + qraw[2] * qraw[2] + qraw[3] * qraw[3];
+  const double qlen = sqrt(qn2);
+  const double qw = qraw[0] / qlen, qx = qraw[1] / qlen, qy = qraw[2] / qlen, qz = qraw[3] / qlen;
+  const double sc[3] = {exp((double)gp[7]), exp((double)gp[8]), exp((double)gp[9])};
+  const double o = 1.0 / (1.0 + exp(-(double)gp[10]));
+  double Rq[9];
+  Rq[0] = 1.0 - 2.0 * (qy * qy + qz * qz); Rq[1] = 2.0 * (qx * qy - qw * qz); Rq[2] = 2.0 * (qx * qz + qw * qy);
+  Rq[3] = 2.0 * (qx * qy + qw * qz); Rq[4] = 1.0 - 2.0 * (qx * qx + qz * qz); Rq[5] = 2.0 * (qy * qz - qw * qx);
+  Rq[6] = 2.0 * (qx * qz - qw * qy); Rq[7] = 2.0 * (qy * qz + qw * qx); Rq[8] = 1.0 - 2.0 * (qx * qx + qy * qy);
+  double M[9];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) M[3 * i + k] = Rq[3 * i + k] * sc[k];
+  const double iz = 1.0 / tz;
+  const double fx = F.fx, fy = F.fy;
+  const double jx = fx * iz, jy = fy * iz, ux = -fx * tx * iz * iz, uy = -fy * ty * iz * iz;
+  double Wm[6];
+  for (int k = 0; k < 3; ++k) {
+    Wm[k] = jx * R[k] + ux * R[6 + k];
+    Wm[3 + k] = jy * R[3 + k] + uy * R[6 + k];
+  }
+  double V[6];
+  for (int i = 0; i < 2; ++i)
+    for (int k = 0; k < 3; ++k) V[3 * i + k] = Wm[3 * i] * M[k] + Wm[3 * i + 1] * M[3 + k] + Wm[3 * i + 2] * M[6 + k];
+  const double sa = V[0] * V[0] + V[1] * V[1] + V[2] * V[2] + kLowPass;
+  const double sb = V[0] * V[3] + V[1] * V[4] + V[2] * V[5];
+  const double scc = V[3] * V[3] + V[4] * V[4] + V[5] * V[5] + kLowPass;
+  const double det = sa * scc - sb * sb;
+  const double QA = scc / det, QB = -sb / det, QC = sa / det;
+
+  // ---- record-space gradient -> conic coefficients of q = A dx^2 + 2B dx dy + C dy^2 ----
+  const double dA = (double)acc[2] * (-0.5 * kLog2e);
+  const double dB = (double)acc[3] * (-kLog2e);      // cb = -log2e * B  (coefficient of dx dy is 2B)
+  const double dC = (double)acc[4] * (-0.5 * kLog2e);
+  // conic -> Sigma2 (symmetric):  dS = -Q dQ Q with dQ = [[dA, dB/2], [dB/2, dC]]
+  const double h = 0.5 * dB;
+  const double t00 = QA * dA + QB * h, t01 = QA * h + QB * dC;
+  const double t10 = QB * dA + QC * h, t11 = QB * h + QC * dC;
+  const double g00 = -(t00 * QA + t01 * QB);
+  const double g01 = -(t00 * QB + t01 * QC);
+  const double g11 = -(t10 * QB + t11 * QC);
+  // Sigma2 = V V^T + c I:  dV = 2 G V
+  double dV[6];
+  for (int k = 0; k < 3; ++k) {
+    dV[k] = 2.0 * (g00 * V[k] + g01 * V[3 + k]);
+    dV[3 + k] = 2.0 * (g01 * V[k] + g11 * V[3 + k]);
+  }
+  // V = W M:  dW = dV M^T,  dM = W^T dV
+  double dW[6], dM[9];
+  for (int i = 0; i < 2; ++i)
+    for (int k = 0; k < 3; ++k)
+      dW[3 * i + k] = dV[3 * i] * M[3 * k] + dV[3 * i + 1] * M[3 * k + 1] + dV[3 * i + 2] * M[3 * k + 2];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) dM[3 * i + k] = Wm[i] * dV[k] + Wm[3 + i] * dV[3 + k];
+  // W rows: jx R0 + ux R2, jy R1 + uy R2  ->  d(jx), d(ux), d(jy), d(uy)
+  double djx = 0, dux = 0, djy = 0, duy = 0;
+  for (int k = 0; k < 3; ++k) {
+    djx += dW[k] * R[k]; dux += dW[k] * R[6 + k];
+    djy += dW[3 + k] * R[3 + k]; duy += dW[3 + k] * R[6 + k];
+  }
+  // jx = fx/tz, ux = -fx tx/tz^2, jy = fy/tz, uy = -fy ty/tz^2; mean = (fx tx/tz + cx, fy ty/tz + cy)
+  const double dmx = acc[0], dmy = acc[1];
+  double dtx = dux * (-fx * iz * iz) + dmx * fx * iz;
+  double dty = duy * (-fy * iz * iz) + dmy * fy * iz;
+  double dtz = djx * (-fx * iz * iz) + dux * (2.0 * fx * tx * iz * iz * iz) + djy * (-fy * iz * iz) +
+               duy * (2.0 * fy * ty * iz * iz * iz) - dmx * fx * tx * iz * iz - dmy * fy * ty * iz * iz;
+  float res[16];
+  for (int k = 0; k < 3; ++k) res[k] = (float)(R[k] * dtx + R[3 + k] * dty + R[6 + k] * dtz);
+  // M = Rq diag(s):  dRq = dM diag(s),  ds_k = sum_i dM_ik Rq_ik
+  double dRq[9], ds[3];
+  for (int k = 0; k < 3; ++k) {
+    ds[k] = dM[k] * Rq[k] + dM[3 + k] * Rq[3 + k] + dM[6 + k] * Rq[6 + k];
+    for (int i = 0; i < 3; ++i) dRq[3 * i + k] = dM[3 * i + k] * sc[k];
+  }
+  // d Rq / d (w, x, y, z) of the unit quaternion
+  double dq[4];
+  dq[0] = 2.0 * (qz * (dRq[3] - dRq[1]) + qy * (dRq[2] - dRq[6]) + qx * (dRq[7] - dRq[5]));
+  dq[1] = 2.0 * (qy * (dRq[1] + dRq[3]) + qz * (dRq[2] + dRq[6]) + qw * (dRq[7] - dRq[5]) - 2.0 * qx * (dRq[4] + dRq[8]));
+  dq[2] = 2.0 * (qx * (dRq[1] + dRq[3]) + qw * (dRq[2] - dRq[6]) + qz * (dRq[5] + dRq[7]) - 2.0 * qy * (dRq[0] + dRq[8]));
+  dq[3] = 2.0 * (qw * (dRq[3] - dRq[1]) + qx * (dRq[2] + dRq[6]) + qy * (dRq[5] + dRq[7]) - 2.0 * qz * (dRq[0] + dRq[4]));
+  const double dotq = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+  const double qh[4] = {qw, qx, qy, qz};
+  for (int k = 0; k < 4; ++k) res[3 + k] = (float)((dq[k] - qh[k] * dotq) / qlen);
+  for (int k = 0; k < 3; ++k) res[7 + k] = (float)(ds[k] * sc[k]);
+  res[10] = (float)((double)acc[5] * o * (1.0 - o));
+  res[11] = acc[6]; res[12] = acc[7]; res[13] = acc[8];
+  res[14] = 0.0f; res[15] = 0.0f;
+  out[0] = make_float4(res[0], res[1], res[2], res[3]);
+  out[1] = make_float4(res[4], res[5], res[6], res[7]);
+  out[2] = make_float4(res[8], res[9], res[10], res[11]);
+  out[3] = make_float4(res[12], res[13], res[14], res[15]);
+}
+
+void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s) {
+  if (a.n_splats == 0) return;
+  hipLaunchKernelGGL(gather_bwd_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, raw, draw);
+}
+
+// ---------------------------------------------------------------- loss
+// kind 1: mean |x - y| (Sec. 3.2 L1 colour loss), kind 2: mean (x - y)^2.
+// Per-block float64 partial sums, then one block sums them in order.
+constexpr int kLossThreads = 256;
+constexpr int kLossPerBlock = kLossThreads * 16;
+
+__global__ __launch_bounds__(kLossThreads) void loss_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                                                             int64_t n, int kind, float* __restrict__ dx,
+                                                             double* __restrict__ partials,
+                                                             const StatusDev* status) {
+  __shared__ double sm[kLossThreads];
+  const int64_t base = (int64_t)blockIdx.x * kLossPerBlock;
+  const float inv = 1.0f / (float)n;
+  double s = 0.0;
+  for (int i = 0; i < 16; ++i) {
+    const int64_t k = base + (int64_t)i * kLossThreads + threadIdx.x;
+    if (k < n) {
+      const float d = x[k] - y[k];
+      if (kind == 1) {
+        s += fabs((double)d);
+        dx[k] = (d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f));
+      } else {
+        s += (double)d * (double)d;
+        dx[k] = 2.0f * d * inv;
+      }
+    }
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kLossThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+  (void)status;
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ partials, int nb, int64_t n, StatusDev* status) {
+  __shared__ double sm[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += partials[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) status->loss = (float)(sm[0] / (double)n);
+}
+
+int64_t loss_partials(int64_t n_floats) { return div_up(n_floats, kLossPerBlock); }
+
+void launch_loss(const PassArgs& a, const float* images, const float* targets, int kind, float* dimages,
+                 float* partials, int64_t n_partials, hipStream_t s) {
+  const int64_t n = a.n_pixels * 3;
+  if (n == 0) return;
+  const int nb = div_up(n, kLossPerBlock);
+  (void)n_partials;
+  double* part = reinterpret_cast<double*>(partials);
+  hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(kLossThreads), 0, s, images, targets, n, kind, dimages, part,
+                     a.status);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, part, nb, n, a.status);
+}
+
+}  // namespace gbr

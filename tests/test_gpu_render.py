@@ -1,0 +1,214 @@
+"""GPU parity of the rasterizer forward pass against the float64 oracle:
+projection records, tile lists (bit-exact), images (1e-4 max-abs outside the
+oracle's ambiguity margins), plus the invariances the batch-parallel design
+promises (tile size, chunk depth, batch composition, run-to-run)."""
+import numpy as np
+import pytest
+
+from oracle import blendshape as bs
+from oracle import raster
+from paper_2503_12886_amd import gbr, synth
+from gpu_util import IMAGE_TOL, compare_image, dev, host, make_ctx, render
+
+pytestmark = pytest.mark.gpu
+
+
+def tiny_case():
+    """The tiny workload: N=2000, K=8, one 128x128 frame at z=0.5, fx=fy=150, weights U[0,1]."""
+    bases = synth.make_scene(2000, 8, seed=0)
+    w = synth.make_weights(1, 8, seed=2)
+    cam = synth.fixed_camera(128, 128, 150.0, 0.5, bg=(0.2, 0.3, 0.4))
+    raw = bs.blend(bases, w).astype(np.float32)[0]
+    return raw, cam
+
+
+def batch_case(B=5, N=3000, seed=0, res=((64, 48), (96, 96), (80, 72))):
+    bases = synth.make_scene(N, 6, seed=seed)
+    w = synth.make_weights(B, 6, seed=seed + 1)
+    cams = synth.make_cameras(B, seed=seed + 2, resolutions=list(res), dist=(0.4, 0.7))
+    raw = bs.blend(bases, w).astype(np.float32).reshape(B * N, 16)
+    return raw, cams, N
+
+
+def test_tiny_image_parity():
+    raw, cam = tiny_case()
+    ctx = make_ctx()
+    imgs, _, _ = render(ctx, raw, [cam])
+    ref, Te, nc, fl = raster.render(raw, cam)
+    err, masked = compare_image(imgs[0], ref, fl)
+    assert err <= IMAGE_TOL, err
+    assert masked < 0.02, masked
+    tfin = gbr.gbr_inspect(ctx, "t_final", 128 * 128).reshape(128, 128)
+    assert np.abs(tfin - Te)[fl == 0].max() <= 1e-4
+
+
+def test_projection_records_and_rects():
+    raw, cams, N = batch_case()
+    ctx = make_ctx(tile=16)
+    render(ctx, raw, cams)
+    rec = gbr.gbr_inspect(ctx, "records", raw.shape[0])
+    rect = gbr.gbr_inspect(ctx, "rects", raw.shape[0])
+    log2e = 1.0 / np.log(2.0)
+    for b, cam in enumerate(cams):
+        p = raster.project(raw[b * N:(b + 1) * N], cam)
+        r = rec[b * N:(b + 1) * N]
+        rc = rect[b * N:(b + 1) * N]
+        v = p["valid"] > 0
+        # integer decisions: identical
+        exp_rect = raster.tile_rects(p, cam.width, cam.height, 16)
+        assert np.array_equal(rc[v], exp_rect[v].astype(np.int32))
+        assert np.all(rc[~v][:, 2] < rc[~v][:, 0])           # culled: empty rect
+        # depth key: the binary32 rounding of the camera-space depth
+        assert np.array_equal(r[v, 9], p["key"][v].astype(np.float32))
+        # float32 records of float64 quantities
+        for col, ref in ((0, p["mx"]), (1, p["my"]), (2, -0.5 * log2e * p["A"]), (3, -log2e * p["B"]),
+                         (4, -0.5 * log2e * p["C"]), (5, p["opacity"])):
+            assert np.allclose(r[v, col], ref[v], rtol=2e-7, atol=1e-30), col
+
+
+def test_tile_lists_bit_exact():
+    raw, cams, N = batch_case(B=4, N=2500, seed=3)
+    for tile in (8, 16, 32):
+        ctx = make_ctx(tile=tile)
+        render(ctx, raw, cams)
+        projs = [raster.project(raw[b * N:(b + 1) * N], c) for b, c in enumerate(cams)]
+        ranges, sf, sg, tile_base = raster.bin_and_sort(projs, cams, tile)
+        n_tiles = len(ranges)
+        ts = gbr.gbr_inspect(ctx, "tile_start", n_tiles + 1)
+        assert np.array_equal(ts[:-1].astype(np.int64), ranges[:, 0])
+        assert np.array_equal(ts[1:].astype(np.int64), ranges[:, 1])
+        srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
+        assert np.array_equal(srt, sf * N + sg)
+        ctx.close()
+
+
+def test_batch_images_with_uneven_sizes_and_gaussian_sets():
+    # frames with their own Gaussian sets and resolutions, one pass
+    rng = np.random.default_rng(0)
+    sizes = [1200, 37, 2500, 0, 900]
+    cams = synth.make_cameras(5, seed=4, resolutions=[(64, 48), (50, 70), (96, 96), (33, 17)], dist=(0.45, 0.6))
+    raws, offs = [], [0]
+    for i, n in enumerate(sizes):
+        bases = synth.make_scene(max(n, 1), 4, seed=10 + i)[:, :n]
+        raws.append(bs.blend(bases, synth.make_weights(1, 4, seed=i)).astype(np.float32)[0])
+        offs.append(offs[-1] + n)
+    raw = np.concatenate(raws, axis=0)
+    ctx = make_ctx()
+    imgs, _, _ = render(ctx, raw, cams, offs)
+    for b, cam in enumerate(cams):
+        ref, _, _, fl = raster.render(raw[offs[b]:offs[b + 1]], cam)
+        err, masked = compare_image(imgs[b], ref, fl)
+        assert err <= IMAGE_TOL, (b, err)
+        assert masked < 0.02
+
+
+def test_tile_size_and_chunk_invariance_bit_exact():
+    raw, cams, N = batch_case(B=3, N=3000, seed=5)
+    base = None
+    for tile in (8, 16, 32):
+        for chunk in (64, 128, 256):
+            ctx = make_ctx(tile=tile, chunk=chunk)
+            imgs, _, _ = render(ctx, raw, cams)
+            flat = np.concatenate([i.ravel() for i in imgs])
+            if base is None:
+                base = flat
+            assert np.array_equal(flat, base), (tile, chunk)
+            ctx.close()
+
+
+def test_frame_alone_equals_frame_in_batch():
+    raw, cams, N = batch_case(B=6, N=2000, seed=6)
+    ctx = make_ctx()
+    imgs, _, _ = render(ctx, raw, cams)
+    for b in (0, 3, 5):
+        one, _, _ = render(ctx, raw[b * N:(b + 1) * N], [cams[b]])
+        assert np.array_equal(one[0], imgs[b])
+
+
+def test_run_to_run_deterministic():
+    raw, cams, N = batch_case(B=4, N=4000, seed=7)
+    ctx = make_ctx()
+    a, _, _ = render(ctx, raw, cams)
+    b, _, _ = render(ctx, raw, cams)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_degenerate_inputs():
+    ctx = make_ctx()
+    cam = synth.fixed_camera(37, 21, 60.0, 0.5, bg=(0.1, 0.7, 0.3))
+    # every Gaussian behind the camera -> background everywhere
+    r = np.zeros((10, 16), np.float32)
+    r[:, 2] = -1.0; r[:, 3] = 1.0
+    imgs, _, _ = render(ctx, r, [cam])
+    assert np.array_equal(imgs[0], np.broadcast_to(np.float32([0.1, 0.7, 0.3])[:, None, None], (3, 21, 37)))
+    # a single Gaussian far off screen, and a 1x1 image
+    r = np.zeros((1, 16), np.float32)
+    r[0, 0] = 5.0; r[0, 3] = 1.0; r[0, 7:10] = -5.0
+    imgs, _, _ = render(ctx, r, [cam])
+    assert np.allclose(imgs[0][1], 0.7)
+    cam1 = synth.fixed_camera(1, 1, 60.0, 0.5, bg=(0, 0, 0))
+    r = np.zeros((1, 16), np.float32)
+    r[0, 3] = 1.0; r[0, 7:10] = -4.0; r[0, 10] = 3.0; r[0, 11:14] = 1.0
+    imgs, _, _ = render(ctx, r, [cam1])
+    ref, _, _, _ = raster.render(r, cam1)
+    assert np.abs(imgs[0] - ref).max() <= IMAGE_TOL
+
+
+def test_overflow_is_reported_and_recoverable():
+    raw, cams, N = batch_case(B=2, N=3000, seed=8)
+    import torch
+    ctx = make_ctx(max_entries=1000)
+    rw = dev(raw)
+    out = torch.zeros(gbr.image_numel(cams), device="cuda")
+    gbr.gbr_render(ctx, rw, [0, N, 2 * N], cams, out)
+    st = gbr.gbr_query_status(ctx)
+    assert st.overflow and st.entries > 1000
+    gbr.gbr_reserve(ctx, st.entries)
+    gbr.gbr_render(ctx, rw, [0, N, 2 * N], cams, out)
+    st2 = gbr.gbr_query_status(ctx)
+    assert not st2.overflow and st2.entries == st.entries
+    ref_ctx = make_ctx()
+    ref, _, _ = render(ref_ctx, raw, cams)
+    assert np.array_equal(host(out), np.concatenate([i.ravel() for i in ref]))
+
+
+def test_per_frame_scheme_matches_batched():
+    """preprocess -> host sync on the entry count -> rasterize (Fig. 4a)."""
+    import torch
+    raw, cams, N = batch_case(B=3, N=2000, seed=9)
+    ctx = make_ctx(max_entries=64)
+    rw = dev(raw)
+    outs = []
+    for b in range(3):
+        out = torch.zeros(gbr.image_numel([cams[b]]), device="cuda")
+        gbr.gbr_preprocess(ctx, rw[b * N:(b + 1) * N], [0, N], [cams[b]])
+        e = gbr.gbr_entry_count(ctx)
+        assert e > 64
+        gbr.gbr_rasterize(ctx, out)
+        outs.append(host(out))
+    ref_ctx = make_ctx()
+    ref, _, _ = render(ref_ctx, raw, cams)
+    assert np.array_equal(np.concatenate(outs), np.concatenate([i.ravel() for i in ref]))
+
+
+def test_invalid_arguments_are_rejected():
+    ctx = make_ctx(max_frames=2)
+    import torch
+    raw = torch.zeros(32, device="cuda")
+    cams = synth.make_cameras(3, 16, 16)
+    out = torch.zeros(gbr.image_numel(cams), device="cuda")
+    with pytest.raises(gbr.GbrError) as e:
+        gbr.gbr_render(ctx, raw, [0, 1, 2, 2], cams, out)
+    assert e.value.code == -2
+    with pytest.raises(gbr.GbrError) as e:
+        gbr.gbr_render(ctx, raw, [0, 2, 1], cams[:2], out)      # decreasing offsets
+    assert e.value.code == -1
+    bad = synth.make_cameras(1, 16, 16)
+    bad[0].width = 0
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr_render(ctx, raw, [0, 1], bad, out)
+    fresh = make_ctx()
+    with pytest.raises(gbr.GbrError) as e:
+        gbr.gbr_render_backward(fresh, out, raw)
+    assert e.value.code == -5
