@@ -1,0 +1,245 @@
+"""Training-throughput benchmark of the batch-parallel blendshape-avatar step.
+
+Workload (one step): N = 50,000 Gaussians, K = 20 blendshapes, B = 16 frames
+of 512 x 512, weight MLP 56 -> 256 -> 256 -> 20, L1 loss against random
+targets with random backgrounds, full backward to the bases and the MLP, Adam
+on both -- in float32.  Synthetic inputs (see paper_2503_12886_amd/synth.py).
+
+Reports the batched, graph-captured step (one host synchronisation per
+step) in images/s, next to the per-frame scheme (one frame per optimisation
+step, host synchronisation between preprocess and rasterize) on the same
+GPU, the dominant kernel's roofline position measured with HIP events over
+the timed region, a per-kernel time breakdown, and the float64 CPU
+reference timed on a bounded sample.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")   # the CPU reference leg is single-threaded
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "train img/s (fwd+bwd, 50k Gaussians, 512²) batched vs per-frame; serve p99 ms"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FLOP/clk (packed dual FMA)
+
+# Algorithmic work per unit, see DESIGN.md ("Measurement"):
+#  composite forward: FP32 operations per contributing (pixel, Gaussian) pair
+#  composite backward: FP32 operations per contributing pair, excluding the
+#  cross-lane reduction (not algorithmic)
+FWD_FLOP_PER_PAIR = 21
+BWD_FLOP_PER_PAIR = 58
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--per-frame-frames", type=int, default=48)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=128)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--quick", action="store_true", help="few steps, no per-frame/CPU legs (for profilers)")
+    return ap.parse_args()
+
+
+def source_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(seed=0):
+    from paper_2503_12886_amd import synth
+    from paper_2503_12886_amd.trainer import StepConfig, mlp_pack
+    cfg = StepConfig(N=50_000, K=20, B=16, width=512, height=512)
+    bases = synth.make_scene(cfg.N, cfg.K, seed=seed)
+    mlp = mlp_pack(synth.make_mlp(K=cfg.K, seed=5))
+    theta = synth.make_tracking(cfg.B, seed=2)
+    cams = synth.make_cameras(cfg.B, cfg.width, cfg.height, seed=1, yaw_deg=10.0)
+    targets = np.stack(synth.make_targets(cams, seed=3))
+    return cfg, bases, mlp, theta, cams, targets
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import torch
+    from paper_2503_12886_amd import gbr
+    from paper_2503_12886_amd.trainer import Trainer
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg, bases, mlp, theta, cams, targets = make_workload()
+    cfg.tile, cfg.chunk = args.tile, args.chunk
+    tr = Trainer(cfg, bases, mlp)
+    tr.set_batch(theta, targets, cams)
+
+    # warm-up (sizes the tile-entry buffers), then per-kernel breakdown of one eager step
+    for _ in range(3):
+        tr.step()
+    breakdown = {}
+    for k in range(len(gbr.KERNEL_NAMES)):
+        gbr.gbr_timing(tr.ctx, k, True)
+    st = tr.step()
+    for k, name in enumerate(gbr.KERNEL_NAMES):
+        try:
+            breakdown[name] = round(gbr.gbr_timing_read(tr.ctx, k), 4)
+        except gbr.GbrError:
+            pass
+        gbr.gbr_timing(tr.ctx, k, False)
+    entries = int(st.entries)
+    n_contrib = gbr.gbr_inspect(tr.ctx, "n_contrib", cfg.B * cfg.width * cfg.height).astype(np.int64)
+    X = int(n_contrib.sum())
+    dominant = max(("composite_fwd", "composite_bwd", "tile_sort", "binning", "gather_bwd", "adam", "blend",
+                    "blend_bwd", "preprocess"), key=lambda k: breakdown.get(k, 0.0))
+    dom_id = gbr.KERNEL_NAMES.index(dominant)
+
+    # timed region: graph-captured batched steps, one status read per step;
+    # the dominant kernel is bracketed by HIP events on the launch stream
+    gbr.gbr_timing(tr.ctx, dom_id, True)
+    if not args.no_graph:
+        tr.capture()
+    steps = 5 if args.quick else args.steps
+    for _ in range(2 if args.quick else args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    dom_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = tr.step()
+        dom_ms.append(gbr.gbr_timing_read(tr.ctx, dom_id))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gbr.gbr_timing(tr.ctx, dom_id, False)
+    ms_step = (t1 - t0) * 1e3 / steps
+    value = cfg.B * steps / (t1 - t0)
+    dom_avg = float(np.mean(dom_ms))
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "img/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "reduced Gaussian blendshape avatar training step: N=50000 Gaussians, K=20, "
+                               "B=16 frames 512x512, weight MLP 56-256-256-20, L1 loss, Adam; batched, "
+                               "graph-captured, one host sync per step",
+                   "N": cfg.N, "K": cfg.K, "B": cfg.B, "resolution": [cfg.width, cfg.height],
+                   "tile": cfg.tile, "chunk": cfg.chunk, "graph": not args.no_graph},
+        "entries_per_step": entries, "contributing_pairs_per_step": X,
+        "kernels_ms": breakdown,
+    }
+
+    # roofline of the dominant kernel
+    if dominant in ("composite_fwd", "composite_bwd"):
+        per = FWD_FLOP_PER_PAIR if dominant == "composite_fwd" else BWD_FLOP_PER_PAIR
+        achieved = X * per / (dom_avg * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "work_per_launch": f"{X} contributing pairs x {per} FLOP", "avg_ms": round(dom_avg, 4)}
+    else:
+        per_entry = {"tile_sort": 8 + 8 + 4 + 4, "binning": 8 + 4}.get(dominant, 0)
+        achieved = entries * per_entry / (dom_avg * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "work_per_launch": f"{entries} entries x {per_entry} B", "avg_ms": round(dom_avg, 4)}
+    prof = os.path.join(ROOT, "profiles", f"{dominant}_traffic.json")
+    roof["traffic"] = None
+    if os.path.exists(prof):
+        meta = json.load(open(prof))
+        if meta.get("source_hash") == source_hash(meta.get("sources", [])):
+            roof["traffic"] = meta.get("bytes_per_launch")
+    out["roofline"] = roof
+
+    # per-frame scheme on the same GPU
+    if not args.quick:
+        if tr.graph is not None:
+            gbr.gbr_graph_destroy(tr.graph)
+            tr.graph = None
+        nf = args.per_frame_frames
+        tr.per_frame_steps(range(cfg.B))          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < nf:
+            k = min(cfg.B, nf - done)
+            tr.per_frame_steps(range(k))
+            done += k
+        torch.cuda.synchronize()
+        pf = nf / (time.perf_counter() - t0)
+        out["per_frame"] = {"value": round(pf, 2), "unit": "img/s", "frames": nf,
+                            "ms_per_frame": round(1e3 / pf, 4), "batched_over_per_frame": round(value / pf, 3)}
+
+    tr.close()
+
+    if not args.quick and not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(budget_s: float) -> dict:
+    """The float64 oracle on this host, one thread, on a bounded sample of the
+    same workload: whole frames of the batch (blend, render, L1 loss
+    gradient, render adjoint, blend adjoint) until the budget is used, plus
+    one Adam update of every parameter amortised over the 16-frame batch."""
+    from oracle import blendshape as bs
+    from oracle import raster
+    cfg, bases, mlp, theta, cams, targets = make_workload()
+    from paper_2503_12886_amd import synth
+    p = synth.make_mlp(K=cfg.K, seed=5)
+    t0 = time.perf_counter()
+    psi, cache = bs.mlp_forward(p, theta)
+    frames = 0
+    dpsi = np.zeros_like(psi)
+    while True:
+        b = frames % cfg.B
+        raw = bs.blend(bases, psi[b:b + 1])[0].astype(np.float32)
+        img, _, _, _ = raster.render(raw, cams[b])
+        _, G = bs.loss_l1([img], [targets[b]])
+        draw, _ = raster.render_grad(raw, cams[b], G[0])
+        _, dps = bs.blend_adjoint(draw[None], bases, psi[b:b + 1])
+        dpsi[b] = dps[0]
+        frames += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t_frames = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    bs.mlp_backward(p, cache, dpsi)
+    flat = bases.astype(np.float64).ravel()
+    bs.adam_step(flat, flat * 1e-3, np.zeros_like(flat), np.zeros_like(flat), 1, 1e-3)
+    t_adam = time.perf_counter() - t1
+    per_img = t_frames / frames + t_adam / cfg.B
+    return {"value": round(1.0 / per_img, 5), "unit": "img/s", "cores": 1, "kind": "oracle",
+            "sample": f"{frames} of the 16 frames (N=50000, K=20, 512x512): float64 blend + render + L1 gradient + "
+                      f"render adjoint + blend adjoint, {t_frames:.1f} s; plus one MLP backward and Adam update of "
+                      f"all {flat.size} base parameters ({t_adam:.1f} s) amortised over 16 frames",
+            "cpu": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical cores visible)"
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

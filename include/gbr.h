@@ -208,10 +208,33 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
    tx0, ty0, tx1, ty1), 3 tile starts [tiles+1] u32 (tile g's entries are
    [start[g], start[g+1]) of the sorted list), 4 sorted entries [entries] u32
    (global splat index),
-   5 per-pixel contributor counts [pixels] u32, 6 per-pixel final
-   transmittance [pixels] f32, 7 per-tile last entry used [tiles] u32.
+   5 per-pixel list position after the last contributor [pixels] u32,
+   6 per-pixel final transmittance [pixels] f32, 7 per-tile entries used
+   [tiles] u32, 8 per-pixel number of contributing Gaussians [pixels] u32.
    *bytes in: capacity of dst; out: bytes written. */
 int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
+
+/* Kernel timing for measurement tools.  which: GBR_K_* below.  While
+   enabled, the library records a pair of HIP events on the launch stream
+   around every launch of that kernel (also inside a captured graph);
+   gbr_timing_read returns the duration of the most recent launch in ms
+   (call after the stream has been synchronised, e.g. by gbr_query_status). */
+#define GBR_K_BLEND 0
+#define GBR_K_PREPROCESS 1
+#define GBR_K_BINNING 2      /* splat-offset scan + scatter of tile entries */
+#define GBR_K_TILE_SORT 3
+#define GBR_K_COMPOSITE_FWD 4
+#define GBR_K_COMPOSITE_BWD 5
+#define GBR_K_GATHER_BWD 6
+#define GBR_K_BLEND_BWD 7
+#define GBR_K_ADAM 8
+#define GBR_K_LOSS 9
+#define GBR_K_MLP 10         /* forward and backward */
+#define GBR_K_TILE_SCAN 11
+#define GBR_K_DEPTH_ORDER 12  /* per-frame depth ranks of the visible splats */
+#define GBR_K_COUNT 13
+int gbr_timing(gbr_ctx* ctx, int32_t which, int32_t enable);
+int gbr_timing_read(gbr_ctx* ctx, int32_t which, float* ms);
 
 #ifdef __cplusplus
 }

@@ -185,13 +185,21 @@ __global__ __launch_bounds__(256) void blend_dweights_kernel(const float* __rest
         }
 }
 
-__global__ void reduce_partials_kernel(const float* __restrict__ partials, int64_t n_part, int BK,
-                                       float* __restrict__ out, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= BK) return;
+// One block per output: each thread sums a fixed stride of the partials,
+// then a fixed-shape tree over the block.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partials, int64_t n_part,
+                                                              int BK, float* __restrict__ out, int accumulate) {
+  __shared__ float sm[256];
+  const int i = blockIdx.x;
   float s = 0.0f;
-  for (int64_t p = 0; p < n_part; ++p) s += partials[p * BK + i];
-  out[i] = accumulate ? out[i] + s : s;
+  for (int64_t p = threadIdx.x; p < n_part; p += 256) s += partials[p * BK + i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + sm[0] : sm[0];
 }
 
 int64_t blend_bwd_partials(int B, int K, int64_t N) {
@@ -217,8 +225,8 @@ void launch_blend_bwd(const float* draw, const float* bases, const float* weight
     hipLaunchKernelGGL((blend_dweights_kernel<4, 4>), g2, dim3(256), 0, s, draw, bases, B, K, N, partials);
   const int64_t n_part = (int64_t)g2.x * 4;
   (void)n_partials;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(div_up((int64_t)B * K, 256)), dim3(256), 0, s, partials,
-                     n_part, B * K, dweights, accumulate);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(B * K), dim3(256), 0, s, partials, n_part, B * K, dweights,
+                     accumulate);
 }
 
 }  // namespace gbr

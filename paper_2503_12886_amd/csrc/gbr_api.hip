@@ -19,6 +19,7 @@ constexpr int kSlots = 5;          // pinned frame-table slots; the last one is 
 constexpr int kCaptureSlot = kSlots - 1;
 constexpr int kMaxK = 63;
 constexpr int kMaxFramesHard = 4096;
+constexpr int64_t kMaxBitmapWords = 32768;   // 128 KB of LDS: frames of up to 1,048,576 Gaussians
 
 #define GBR_HIP(x)                           \
   do {                                       \
@@ -40,10 +41,14 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-__global__ void begin_pass_kernel(uint32_t* tile_count, uint32_t* tile_cursor, int n_tiles, StatusDev* status) {
+// Clears the per-pass counters: tile counts/cursors, depth-bucket
+// counts/cursors, per-frame depth ranges, the large-bucket list, the status.
+__global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_tiles) { tile_count[i] = 0u; tile_cursor[i] = 0u; }
-  if (i == 0) { status->overflow = 0u; status->entries = 0ull; }
+  if (i < a.n_tiles) { a.tile_count[i] = 0u; a.tile_cursor[i] = 0u; }
+  if (i < n_bkt) { a.bkt_count[i] = 0u; a.bkt_cursor[i] = 0u; }
+  if (i < a.B) { a.minmax[2 * i] = 0xffffffffu; a.minmax[2 * i + 1] = 0u; }
+  if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
 }
 
 __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u; }
@@ -62,10 +67,21 @@ struct gbr_ctx {
   int4* rect = nullptr;
   uint32_t *cnt = nullptr, *soff = nullptr;
   uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_cursor = nullptr, *tile_last = nullptr;
-  unsigned long long *keys = nullptr, *keys_alt = nullptr;
-  uint32_t *sorted = nullptr, *pos = nullptr;
+  uint32_t* keys = nullptr;
+  uint32_t *sorted = nullptr, *emis = nullptr;
+  uint32_t *order_fwd = nullptr, *order_bwd = nullptr;
+  uint8_t* part_flag = nullptr;
+  uint8_t* cmask = nullptr;
+  // per-frame depth order
+  uint32_t *minmax = nullptr, *bkt_count = nullptr, *bkt_start = nullptr, *bkt_cursor = nullptr;
+  uint32_t *big_list = nullptr, *big_count = nullptr;
+  unsigned long long *bkeys = nullptr, *bkeys_alt = nullptr;
+  uint32_t *depth_sorted = nullptr, *rank = nullptr;
+  int64_t cap_bkt = 0;
+  int nbk = 64;
   float* part = nullptr;
   uint32_t* n_iter = nullptr;
+  uint32_t* n_contrib = nullptr;
   float* t_final = nullptr;
   uint32_t* scan_scratch = nullptr;
   float* draw_scratch = nullptr;
@@ -87,6 +103,9 @@ struct gbr_ctx {
   int n_tiles = 0;
   const float* last_raw = nullptr;
   std::vector<FrameDev> frames_host;
+  // kernel timing
+  bool timing_on[GBR_K_COUNT] = {};
+  hipEvent_t t_ev[GBR_K_COUNT][2] = {};
   // MLP state
   const float* mlp_theta = nullptr;
   int mlp_B = 0, mlp_din = 0, mlp_hidden = 0, mlp_K = 0;
@@ -114,10 +133,28 @@ PassArgs make_args(gbr_ctx* c) {
   a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff;
   a.tile_count = c->tile_count; a.tile_start = c->tile_start; a.tile_cursor = c->tile_cursor;
   a.tile_last = c->tile_last;
-  a.keys = c->keys; a.keys_alt = c->keys_alt; a.sorted = c->sorted; a.pos = c->pos;
-  a.n_iter = c->n_iter; a.t_final = c->t_final; a.part = c->part;
+  a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd;
+  a.keys = c->keys; a.sorted = c->sorted; a.emis = c->emis; a.part_flag = c->part_flag; a.cmask = c->cmask;
+  a.nbk = c->nbk;
+  a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
+  a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_start = c->bkt_start; a.bkt_cursor = c->bkt_cursor;
+  a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
+  a.big_list = c->big_list; a.big_count = c->big_count;
+  a.n_iter = c->n_iter; a.n_contrib = c->n_contrib; a.t_final = c->t_final; a.part = c->part;
   return a;
 }
+
+// Events recorded around one kernel's launch when its timing is enabled.
+struct KTimer {
+  gbr_ctx* c; int k; hipStream_t s; bool on;
+  KTimer(gbr_ctx* c_, int k_, hipStream_t s_)
+      : c(c_), k(k_), s(s_), on(k_ >= 0 && k_ < GBR_K_COUNT && c_->timing_on[k_]) {
+    if (on) (void)hipEventRecord(c->t_ev[k][0], s);
+  }
+  ~KTimer() {
+    if (on) (void)hipEventRecord(c->t_ev[k][1], s);
+  }
+};
 
 bool finite(float x) { return std::isfinite(x); }
 
@@ -128,22 +165,37 @@ int check_tiling(int tile, int chunk) {
 }
 
 int alloc_entries(gbr_ctx* c, int64_t cap) {
-  dfree(c->keys); dfree(c->keys_alt); dfree(c->sorted); dfree(c->pos); dfree(c->part);
+  dfree(c->keys); dfree(c->sorted); dfree(c->emis); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   int rc = GBR_OK;
   if ((rc = dalloc(&c->keys, cap))) return rc;
-  if ((rc = dalloc(&c->keys_alt, cap))) return rc;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
-  if ((rc = dalloc(&c->pos, cap))) return rc;
+  if ((rc = dalloc(&c->emis, cap))) return rc;
+  if ((rc = dalloc(&c->part_flag, cap + 16))) return rc;
+  if ((rc = dalloc(&c->cmask, cap))) return rc;
   if ((rc = dalloc(&c->part, cap * 9))) return rc;
   c->cap_entries = cap;
+  return GBR_OK;
+}
+
+int alloc_buckets(gbr_ctx* c, int64_t n) {
+  dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
+  int rc = GBR_OK;
+  if ((rc = dalloc(&c->bkt_count, n))) return rc;
+  if ((rc = dalloc(&c->bkt_start, n + 1))) return rc;
+  if ((rc = dalloc(&c->bkt_cursor, n))) return rc;
+  if ((rc = dalloc(&c->big_list, n))) return rc;
+  c->cap_bkt = n;
   return GBR_OK;
 }
 
 void free_all(gbr_ctx* c) {
   dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff);
   dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_cursor); dfree(c->tile_last);
-  dfree(c->keys); dfree(c->keys_alt); dfree(c->sorted); dfree(c->pos); dfree(c->part);
-  dfree(c->n_iter); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
+  dfree(c->order_fwd); dfree(c->order_bwd);
+  dfree(c->keys); dfree(c->sorted); dfree(c->emis); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
+  dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
+  dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
+  dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
   dfree(c->loss_part); dfree(c->blend_part);
   dfree(c->mlp_z1); dfree(c->mlp_z2); dfree(c->mlp_dz1); dfree(c->mlp_dz2);
   if (c->h_frames) (void)hipHostFree(c->h_frames);
@@ -151,6 +203,9 @@ void free_all(gbr_ctx* c) {
   c->h_frames = nullptr; c->h_status = nullptr;
   for (int i = 0; i < kSlots; ++i)
     if (c->slot_ev[i]) (void)hipEventDestroy(c->slot_ev[i]);
+  for (int k = 0; k < GBR_K_COUNT; ++k)
+    for (int j = 0; j < 2; ++j)
+      if (c->t_ev[k][j]) (void)hipEventDestroy(c->t_ev[k][j]);
 }
 
 // Validates the frame list and fills the device frame table (host copy).
@@ -215,12 +270,19 @@ int stage_and_upload(gbr_ctx* c, hipStream_t s) {
 int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
   int rc = stage_and_upload(c, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(begin_pass_kernel, dim3(div_up(std::max(c->n_tiles, 1), 256)), dim3(256), 0, s, c->tile_count,
-                     c->tile_cursor, c->n_tiles, c->d_status);
   PassArgs a = make_args(c);
-  launch_preprocess(a, raw, c->max_frame_splats, s);
-  launch_scan_u32(c->tile_count, c->tile_start, c->n_tiles, c->scan_scratch, c->d_status, c->cap_entries,
-                  &c->d_status->entries, s);
+  const int n_bkt = c->B * c->nbk;
+  hipLaunchKernelGGL(begin_pass_kernel, dim3(div_up(std::max(std::max(c->n_tiles, n_bkt), c->B), 256)), dim3(256), 0,
+                     s, a, n_bkt);
+  {
+    KTimer t(c, GBR_K_PREPROCESS, s);
+    launch_preprocess(a, raw, c->max_frame_splats, s);
+  }
+  {
+    KTimer t(c, GBR_K_TILE_SCAN, s);
+    launch_scan_u32(c->tile_count, c->tile_start, c->n_tiles, c->scan_scratch, c->d_status, c->cap_entries,
+                    &c->d_status->entries, s);
+  }
   GBR_HIP(hipGetLastError());
   c->last_raw = raw;
   c->have_pre = true;
@@ -230,10 +292,25 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
 
 int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
   PassArgs a = make_args(c);
-  launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
-  launch_scatter(a, c->max_frame_splats, s);
-  launch_tile_sort(a, s);
-  launch_composite_fwd(a, images, c->chunk, s);
+  {
+    KTimer t(c, GBR_K_DEPTH_ORDER, s);
+    launch_depth_order(a, c->max_frame_splats, c->scan_scratch, s);
+  }
+  {
+    KTimer t(c, GBR_K_BINNING, s);
+    launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
+    launch_scatter(a, c->max_frame_splats, s);
+  }
+  {
+    KTimer t(c, GBR_K_TILE_SORT, s);
+    launch_tile_order(a, false, s);
+    launch_tile_sort(a, s);
+  }
+  {
+    KTimer t(c, GBR_K_COMPOSITE_FWD, s);
+    launch_composite_fwd(a, images, c->chunk, s);
+  }
+  launch_tile_order(a, true, s);
   GBR_HIP(hipGetLastError());
   c->have_raster = true;
   return GBR_OK;
@@ -245,8 +322,18 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   int nt; int64_t np, ns, mfs;
   int rc = build_frames(c, goff, cams, B, fr, &nt, &np, &ns, &mfs);
   if (rc) return rc;
+  if ((mfs + 31) / 32 > kMaxBitmapWords) return GBR_ERR_CAPACITY;
+  int nbk = 64;
+  while (nbk < 8192 && (int64_t)nbk * 16 < mfs) nbk *= 2;
+  if ((int64_t)B * nbk > c->cap_bkt) {
+    if (c->capturing) return GBR_ERR_STATE;
+    GBR_HIP(hipDeviceSynchronize());
+    rc = alloc_buckets(c, (int64_t)B * nbk);
+    if (rc) return rc;
+  }
   c->frames_host.swap(fr);
   c->B = B; c->n_tiles = nt; c->n_pixels = np; c->n_splats = ns; c->max_frame_splats = mfs;
+  c->nbk = nbk;
   return GBR_OK;
 }
 
@@ -298,9 +385,21 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->tile_start, c->cap_tiles + 1));
   TRY(dalloc(&c->tile_cursor, c->cap_tiles));
   TRY(dalloc(&c->tile_last, c->cap_tiles));
+  TRY(dalloc(&c->order_fwd, c->cap_tiles));
+  TRY(dalloc(&c->order_bwd, c->cap_tiles));
+  TRY(dalloc(&c->minmax, 2LL * c->cap_frames));
+  TRY(dalloc(&c->big_count, 1));
+  TRY(dalloc(&c->bkeys, c->cap_splats));
+  TRY(dalloc(&c->bkeys_alt, c->cap_splats));
+  TRY(dalloc(&c->depth_sorted, c->cap_splats));
+  TRY(dalloc(&c->rank, c->cap_splats));
+  TRY(alloc_buckets(c, 64LL * c->cap_frames));
   TRY(dalloc(&c->n_iter, c->cap_pixels));
+  TRY(dalloc(&c->n_contrib, c->cap_pixels));
   TRY(dalloc(&c->t_final, c->cap_pixels));
-  TRY(dalloc(&c->scan_scratch, scan_scratch_words(std::max(c->cap_splats, c->cap_tiles))));
+  TRY(dalloc(&c->scan_scratch,
+             scan_scratch_words(std::max<int64_t>(std::max<int64_t>(c->cap_splats, c->cap_tiles),
+                                                  (int64_t)8192 * c->cap_frames))));
   TRY(dalloc(&c->draw_scratch, c->cap_splats * kNF));
   TRY(dalloc(&c->loss_part, 2 * loss_partials(3 * c->cap_pixels) + 2));
   c->blend_part_n = c->cap_splats + 256LL * c->cap_frames + 64LL * 64 * 8;
@@ -354,7 +453,10 @@ int gbr_set_tiling(gbr_ctx* c, int32_t tile, int32_t chunk) {
 int gbr_blend(gbr_ctx* c, const float* bases, const float* weights, int32_t B, int32_t K, int64_t N, float* raw,
               void* stream) {
   if (!c || !bases || !raw || B < 1 || K < 0 || K > kMaxK || N < 1 || (K > 0 && !weights)) return GBR_ERR_INVALID_ARG;
-  launch_blend_fwd(bases, weights, B, K, N, raw, (hipStream_t)stream);
+  {
+    KTimer t(c, GBR_K_BLEND, (hipStream_t)stream);
+    launch_blend_fwd(bases, weights, B, K, N, raw, (hipStream_t)stream);
+  }
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }
@@ -403,8 +505,15 @@ int gbr_render_backward(gbr_ctx* c, const float* dimages, float* draw, void* str
   if (!c->have_raster) return GBR_ERR_STATE;
   hipStream_t s = (hipStream_t)stream;
   PassArgs a = make_args(c);
-  launch_composite_bwd(a, dimages, nullptr, c->chunk, s);
-  launch_gather_bwd(a, c->last_raw, draw, s);
+  {
+    KTimer t(c, GBR_K_COMPOSITE_BWD, s);
+    launch_clear_flags(a, s);
+    launch_composite_bwd(a, dimages, nullptr, c->chunk, s);
+  }
+  {
+    KTimer t(c, GBR_K_GATHER_BWD, s);
+    launch_gather_bwd(a, c->last_raw, draw, s);
+  }
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }
@@ -415,8 +524,11 @@ int gbr_blend_backward(gbr_ctx* c, const float* draw, const float* bases, const 
   if (K > 0 && (!weights || !dweights)) return GBR_ERR_INVALID_ARG;
   if ((int64_t)B * N > c->cap_splats) return GBR_ERR_CAPACITY;
   if (blend_bwd_partials(B, K, N) > c->blend_part_n) return GBR_ERR_CAPACITY;
-  launch_blend_bwd(draw, bases, weights, B, K, N, dbases, dweights, c->blend_part, c->blend_part_n, accumulate,
-                   (hipStream_t)stream);
+  {
+    KTimer t(c, GBR_K_BLEND_BWD, (hipStream_t)stream);
+    launch_blend_bwd(draw, bases, weights, B, K, N, dbases, dweights, c->blend_part, c->blend_part_n, accumulate,
+                     (hipStream_t)stream);
+  }
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }
@@ -438,7 +550,10 @@ int gbr_loss(gbr_ctx* c, const float* images, const float* targets, int32_t kind
   if (!c || !images || !targets || !dimages || (kind != 1 && kind != 2)) return GBR_ERR_INVALID_ARG;
   if (!c->have_pre) return GBR_ERR_STATE;
   PassArgs a = make_args(c);
-  launch_loss(a, images, targets, kind, dimages, c->loss_part, 0, (hipStream_t)stream);
+  {
+    KTimer t(c, GBR_K_LOSS, (hipStream_t)stream);
+    launch_loss(a, images, targets, kind, dimages, c->loss_part, 0, (hipStream_t)stream);
+  }
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }
@@ -449,7 +564,10 @@ int gbr_mlp_forward(gbr_ctx* c, const float* params, const float* theta, int32_t
       K > 64)
     return GBR_ERR_INVALID_ARG;
   if (B > c->cap_frames) return GBR_ERR_CAPACITY;
-  launch_mlp_fwd(params, theta, B, d_in, hidden, K, psi, c->mlp_z1, c->mlp_z2, (hipStream_t)stream);
+  {
+    KTimer t(c, GBR_K_MLP, (hipStream_t)stream);
+    launch_mlp_fwd(params, theta, B, d_in, hidden, K, psi, c->mlp_z1, c->mlp_z2, (hipStream_t)stream);
+  }
   GBR_HIP(hipGetLastError());
   c->mlp_theta = theta; c->mlp_B = B; c->mlp_din = d_in; c->mlp_hidden = hidden; c->mlp_K = K;
   c->have_mlp = true;
@@ -459,8 +577,11 @@ int gbr_mlp_forward(gbr_ctx* c, const float* params, const float* theta, int32_t
 int gbr_mlp_backward(gbr_ctx* c, const float* params, const float* dpsi, float* dparams, void* stream) {
   if (!c || !params || !dpsi || !dparams) return GBR_ERR_INVALID_ARG;
   if (!c->have_mlp) return GBR_ERR_STATE;
-  launch_mlp_bwd(params, c->mlp_theta, c->mlp_z1, c->mlp_z2, dpsi, c->mlp_B, c->mlp_din, c->mlp_hidden, c->mlp_K,
-                 c->mlp_dz1, c->mlp_dz2, dparams, (hipStream_t)stream);
+  {
+    KTimer t(c, GBR_K_MLP, (hipStream_t)stream);
+    launch_mlp_bwd(params, c->mlp_theta, c->mlp_z1, c->mlp_z2, dpsi, c->mlp_B, c->mlp_din, c->mlp_hidden,
+                   c->mlp_K, c->mlp_dz1, c->mlp_dz2, dparams, (hipStream_t)stream);
+  }
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }
@@ -472,7 +593,11 @@ int gbr_adam_step(gbr_ctx* c, int32_t group, float* params, const float* grads, 
   if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return GBR_ERR_INVALID_ARG;
   for (int i = 0; i < 32; ++i)
     if (!finite(lr_table[i])) return GBR_ERR_INVALID_ARG;
-  launch_adam(c->d_status, group, params, grads, m, v, n, split, lr_table, beta1, beta2, eps, (hipStream_t)stream);
+  {
+    KTimer t(c, group == 0 ? GBR_K_ADAM : GBR_K_COUNT, (hipStream_t)stream);
+    launch_adam(c->d_status, group, params, grads, m, v, n, split, lr_table, beta1, beta2, eps,
+                (hipStream_t)stream);
+  }
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }
@@ -607,12 +732,32 @@ int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
     case 5: src = c->n_iter; n = c->n_pixels * 4; break;
     case 6: src = c->t_final; n = c->n_pixels * 4; break;
     case 7: src = c->tile_last; n = (int64_t)c->n_tiles * 4; break;
+    case 8: src = c->n_contrib; n = c->n_pixels * 4; break;
     default: return GBR_ERR_INVALID_ARG;
   }
   if ((what >= 4) && !c->have_raster) return GBR_ERR_STATE;
   if (*bytes < n) return GBR_ERR_CAPACITY;
   if (n > 0) GBR_HIP(hipMemcpy(dst, src, (size_t)n, hipMemcpyDeviceToHost));
   *bytes = n;
+  return GBR_OK;
+}
+
+int gbr_timing(gbr_ctx* c, int32_t which, int32_t enable) {
+  if (!c || which < 0 || which >= GBR_K_COUNT) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  if (enable && !c->t_ev[which][0]) {
+    GBR_HIP(hipEventCreate(&c->t_ev[which][0]));
+    GBR_HIP(hipEventCreate(&c->t_ev[which][1]));
+  }
+  c->timing_on[which] = enable != 0;
+  return GBR_OK;
+}
+
+int gbr_timing_read(gbr_ctx* c, int32_t which, float* ms) {
+  if (!c || !ms || which < 0 || which >= GBR_K_COUNT) return GBR_ERR_INVALID_ARG;
+  if (!c->t_ev[which][0]) return GBR_ERR_STATE;
+  GBR_HIP(hipEventSynchronize(c->t_ev[which][1]));
+  GBR_HIP(hipEventElapsedTime(ms, c->t_ev[which][0], c->t_ev[which][1]));
   return GBR_OK;
 }
 

@@ -57,7 +57,8 @@ struct PassArgs {
   int64_t cap_entries;
   StatusDev* status;
   // splat stage
-  float* rec;               // [S][12]: mx my ca cb | cc o r g | b depth - -
+  float* rec;               // [S][12]: mx my ca cb | cc o r g | b depth box_x box_y
+                            //   box_x = x0 | x1 << 16, box_y = y0 | y1 << 16 (pixel box, as bits)
   int4* rect;               // [S] inclusive tile rect (tx0, ty0, tx1, ty1)
   uint32_t* cnt;            // [S] tiles touched
   uint32_t* soff;           // [S] exclusive scan of cnt (emission offsets)
@@ -66,14 +67,31 @@ struct PassArgs {
   uint32_t* tile_start;     // [tiles + 1]
   uint32_t* tile_cursor;    // [tiles]
   uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel
-  unsigned long long* keys; // [E] (depth bits << 32) | splat
-  unsigned long long* keys_alt; // [E] ping-pong for oversized tiles
+  uint32_t* keys;           // [E] frame-local depth rank of each entry's splat (unsorted)
   uint32_t* sorted;         // [E] splat index in tile order
-  uint32_t* pos;            // [E] emission slot -> sorted position
+  uint32_t* order_fwd;      // [tiles] tiles by descending list length (scheduling only)
+  uint32_t* order_bwd;      // [tiles] tiles by descending entries used by the forward pass
+  uint32_t* emis;           // [E] sorted position -> emission slot (splat offset + tile index in its rect)
+  // per-frame depth order
+  int32_t nbk;              // depth buckets per frame
+  int32_t bitmap_words;     // LDS words of the per-tile rank bitmap (max frame size / 32)
+  uint32_t* minmax;         // [B][2] min / max binary32 depth bits of the frame's valid splats
+  uint32_t* bkt_count;      // [B * nbk]
+  uint32_t* bkt_start;      // [B * nbk + 1] exclusive scan; frame b's valid splats start at bkt_start[b * nbk]
+  uint32_t* bkt_cursor;     // [B * nbk]
+  unsigned long long* bkeys;      // [S] (depth bits << 32) | splat, grouped by bucket
+  unsigned long long* bkeys_alt;  // [S] ping-pong for large buckets
+  uint32_t* depth_sorted;   // [S] valid splats of each frame in (depth, index) order
+  uint32_t* rank;           // [S] frame-local position of a valid splat in that order
+  uint32_t* big_list;       // [B * nbk] buckets too large for one wave
+  uint32_t* big_count;      // [1]
   // pixel stage
-  uint32_t* n_iter;         // [pixels]
+  uint32_t* n_iter;         // [pixels] list position after the last contributor
+  uint32_t* n_contrib;      // [pixels] number of contributors
   float* t_final;           // [pixels]
-  float* part;              // [E][9] per-entry gradient partials
+  float* part;              // [E][9] per-entry gradient partials, by emission slot
+  uint8_t* part_flag;       // [E] 1 where the entry's partial is non-zero and written
+  uint8_t* cmask;           // [E] bit w: some pixel of wave w of the tile took this entry (forward)
 };
 
 __device__ __forceinline__ int frame_of_tile(const FrameDev* frames, int B, int g) {
@@ -135,9 +153,12 @@ int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
 void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s);
 void launch_tile_sort(const PassArgs& a, hipStream_t s);
+void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);
+void launch_tile_order(const PassArgs& a, bool backward, hipStream_t s);
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s);
+void launch_clear_flags(const PassArgs& a, hipStream_t s);
 void launch_loss(const PassArgs& a, const float* images, const float* targets, int kind, float* dimages,
                  float* partials, int64_t n_partials, hipStream_t s);
 int64_t loss_partials(int64_t n_floats);

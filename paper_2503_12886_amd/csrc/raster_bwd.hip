@@ -32,6 +32,13 @@ __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, f
 // Per-entry partial, summed over the tile's pixels:
 //   (d mx, d my, d ca, d cb, d cc, d opacity, d r, d g, d b)
 // where ca, cb, cc are the log2-scaled conic coefficients of the record.
+// A wave's sum over its lanes is taken in a fixed order: lane by lane through
+// the scalar unit when at most kSparseLanes lanes contribute (the common
+// case: a splat reaches few pixels of a tile), else a DPP tree.  The block
+// then adds its waves in order and writes the entry's partial, by emission
+// slot, only if some pixel contributed; a byte flag marks it.
+constexpr int kSparseLanes = 4;
+
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
@@ -40,8 +47,10 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   __shared__ float4 s1[CHUNK];
   __shared__ float s2[CHUNK];
   __shared__ float red[CHUNK][S::NW][9];
+  __shared__ uint8_t wany[CHUNK][S::NW];
+  __shared__ uint8_t cm[CHUNK];
   if (a.status->overflow) return;
-  const int g = blockIdx.x;
+  const int g = (int)a.order_bwd[blockIdx.x];
   const uint32_t L = a.tile_last[g];
   if (L == 0) return;
   const int b = frame_of_tile(a.frames, a.B, g);
@@ -78,9 +87,15 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     for (int i = threadIdx.x; i < n; i += S::NT) {
       const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[start + cbeg + i] * kRecF);
       s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+      cm[i] = a.cmask[start + cbeg + i];
     }
     __syncthreads();
     for (int i = n - 1; i >= 0; --i) {
+      // the forward pass recorded whether any pixel of this wave took the entry
+      if (!((__builtin_amdgcn_readfirstlane((int)cm[i]) >> w) & 1)) {
+        if (lane == 0) wany[i][w] = 0;
+        continue;
+      }
       const uint32_t li = (uint32_t)(cbeg + i);
       const float4 r0 = s0[i], r1 = s1[i];
       const float cbl = s2[i];
@@ -114,27 +129,74 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
         acc[0] -= dpw * (2.0f * r0.z * dx + r0.w * dy);
         acc[1] -= dpw * (r0.w * dx + 2.0f * r1.x * dy);
       }
-      if (__ballot(any) != 0ull) {
+      const unsigned long long who = __ballot(any);
+      if (who == 0ull) {
+        if (lane == 0) wany[i][w] = 0;
+        continue;
+      }
+      if (__popcll(who) <= kSparseLanes) {
+        float sum[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) sum[c] = 0.0f;
+        unsigned long long m = who;
+        while (m) {
+          const int l = __ffsll((long long)m) - 1;
+          m &= m - 1ull;
+#pragma unroll
+          for (int c = 0; c < 9; ++c)
+            sum[c] += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc[c]), l));
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) red[i][w][c] = sum[c];
+          wany[i][w] = 1;
+        }
+      } else {
 #pragma unroll
         for (int c = 0; c < 9; ++c) acc[c] = wave_sum_to63(acc[c]);
-      }
-      if (lane == 63) {
+        if (lane == 63) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) red[i][w][c] = acc[c];
+          for (int c = 0; c < 9; ++c) red[i][w][c] = acc[c];
+          wany[i][w] = 1;
+        }
       }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += S::NT) {
-      float* dst = a.part + (int64_t)(start + cbeg + i) * 9;
+      bool hit = false;
+      float v[9];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        float v = red[i][0][c];
+      for (int c = 0; c < 9; ++c) v[c] = 0.0f;
 #pragma unroll
-        for (int ww = 1; ww < S::NW; ++ww) v += red[i][ww][c];
-        dst[c] = v;
+      for (int ww = 0; ww < S::NW; ++ww) {
+        if (!wany[i][ww]) continue;
+        hit = true;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) v[c] += red[i][ww][c];
+      }
+      if (hit) {
+        const uint32_t e = a.emis[start + cbeg + i];
+        float* dst = a.part + (int64_t)e * 9;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dst[c] = v[c];
+        a.part_flag[e] = 1;
       }
     }
   }
+}
+
+// Zero the entry flags of the pass (the entry count lives on the device).
+__global__ void clear_flags_kernel(uint8_t* __restrict__ f, const StatusDev* status) {
+  if (status->overflow) return;
+  const uint64_t n = status->entries;
+  const uint64_t n16 = (n + 15) / 16;
+  uint4* f4 = reinterpret_cast<uint4*>(f);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+    f4[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+void launch_clear_flags(const PassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(clear_flags_kernel, dim3(1024), dim3(256), 0, s, a.part_flag, a.status);
 }
 
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s) {
@@ -156,8 +218,8 @@ void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* 
 
 // ---------------------------------------------------------------- gather + projection adjoint
 // One thread per splat: sums its entries' partials in row-major tile order
-// (entries past a tile's last used position were never written and are
-// zero by definition), then chains back through the conic, the EWA
+// (unflagged entries -- no contributing pixel, or past the tile's last used
+// position -- are zero), then chains back through the conic, the EWA
 // projection and the activations in float64.
 __global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float* __restrict__ raw,
                                                          float* __restrict__ draw) {
@@ -172,22 +234,19 @@ __global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float
   }
   const int b = frame_of_splat(a.frames, a.B, s);
   const FrameDev& F = a.frames[b];
-  const int4 r = a.rect[s];
   const uint32_t off = a.soff[s];
   float acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-  uint32_t j = 0;
-  for (int ty = r.y; ty <= r.w; ++ty)
-    for (int tx = r.x; tx <= r.z; ++tx, ++j) {
-      const int gt = F.tile_base + ty * F.ntx + tx;
-      const uint32_t p = a.pos[off + j];
-      if (p - a.tile_start[gt] < a.tile_last[gt]) {
-        const float* q = a.part + (int64_t)p * 9;
+  // the splat's entries are contiguous in emission order (tiles of its rect,
+  // row-major); unflagged entries are zero
+  for (uint32_t e = off; e < off + c; ++e) {
+    if (a.part_flag[e]) {
+      const float* q = a.part + (int64_t)e * 9;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += q[k];
-      }
+      for (int k = 0; k < 9; ++k) acc[k] += q[k];
     }
+  }
 
   // ---- recompute the forward quantities (float64) ----
   const float* gp = raw + s * kNF;

@@ -1,7 +1,7 @@
 // Forward half of the batch-parallel rasterizer (Sec. 3.2): preprocess of
 // every (frame, Gaussian), tile binning, per-tile depth order and front-to-back
 // compositing, for all frames of a batch with no host synchronisation.
-#include "gbr_internal.h"
+#include "gbr_device.h"
 
 namespace gbr {
 
@@ -31,36 +31,6 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kScanThreads * kScanItems;
-
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
-
-// Exclusive scan of one value per thread across a block of NT threads.
-template <int NT>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds_waves, uint32_t* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = NT / 64;
-  uint32_t inc = wave_incl_scan(v);
-  if (lane == 63) lds_waves[w] = inc;
-  __syncthreads();
-  uint32_t off = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) {
-    uint32_t x = lds_waves[i];
-    if (i < w) off += x;
-    tot += x;
-  }
-  __syncthreads();
-  if (total) *total = tot;
-  return off + inc - v;
-}
 
 __global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                     uint32_t* __restrict__ block_sums) {
@@ -220,6 +190,7 @@ __device__ __forceinline__ void project_gaussian(const float* __restrict__ g, co
 
 __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float* __restrict__ raw) {
   __shared__ uint32_t hist[kMaxFrameTilesLds];
+  __shared__ uint32_t dmin, dmax;
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -227,6 +198,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
   const bool lds = F.n_tiles <= kMaxFrameTilesLds;
   if (lds)
     for (int t = threadIdx.x; t < F.n_tiles; t += 256) hist[t] = 0u;
+  if (threadIdx.x == 0) { dmin = 0xffffffffu; dmax = 0u; }
   __syncthreads();
   int4 r = make_int4(0, 0, -1, -1);
   if (n < F.gauss_count) {
@@ -241,10 +213,15 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
       count = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
       const float4 r0 = make_float4((float)p.mx, (float)p.my, (float)(-0.5 * kLog2e * p.A), (float)(-kLog2e * p.Bq));
       const float4 r1 = make_float4((float)(-0.5 * kLog2e * p.C), (float)p.o, raw[s * kNF + 11], raw[s * kNF + 12]);
-      const float4 r2 = make_float4(raw[s * kNF + 13], (float)p.tz, 0.0f, 0.0f);
+      const float4 r2 = make_float4(raw[s * kNF + 13], (float)p.tz,
+                                    __uint_as_float((uint32_t)p.x0 | ((uint32_t)p.x1 << 16)),
+                                    __uint_as_float((uint32_t)p.y0 | ((uint32_t)p.y1 << 16)));
       reinterpret_cast<float4*>(rec)[0] = r0;
       reinterpret_cast<float4*>(rec)[1] = r1;
       reinterpret_cast<float4*>(rec)[2] = r2;
+      const uint32_t db = __float_as_uint(r2.y);
+      atomicMin(&dmin, db);
+      atomicMax(&dmax, db);
     } else {
       reinterpret_cast<float4*>(rec)[2] = make_float4(0.0f, (float)p.tz, 0.0f, 0.0f);
     }
@@ -263,6 +240,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
       const uint32_t c = hist[t];
       if (c) atomicAdd(&a.tile_count[F.tile_base + t], c);
     }
+  if (threadIdx.x == 0 && dmin <= dmax) {
+    atomicMin(&a.minmax[2 * b], dmin);
+    atomicMax(&a.minmax[2 * b + 1], dmax);
+  }
 }
 
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s) {
@@ -273,8 +254,9 @@ void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_sp
 // ---------------------------------------------------------------- scatter
 // Each block reserves, per tile, one contiguous range of slots for all its
 // Gaussians' entries (one global atomic per tile and block), then hands out
-// slots inside the range with LDS atomics.  The order inside a tile is
-// arbitrary here; the per-tile sort that follows makes it unique.
+// slots inside the range with LDS atomics.  An entry is its splat's
+// frame-local depth rank; the order inside a tile is arbitrary here and the
+// per-tile sort that follows makes it unique.
 __global__ __launch_bounds__(256) void scatter_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxFrameTilesLds];
   if (a.status->overflow) return;
@@ -288,10 +270,10 @@ __global__ __launch_bounds__(256) void scatter_kernel(PassArgs a) {
   __syncthreads();
   int4 r = make_int4(0, 0, -1, -1);
   int64_t s = F.gauss_base + n;
-  unsigned long long key_hi = 0;
+  uint32_t key = 0;
   if (n < F.gauss_count && a.cnt[s] > 0) {
     r = a.rect[s];
-    key_hi = (unsigned long long)__float_as_uint(a.rec[s * kRecF + 9]) << 32;
+    key = a.rank[s];
   }
   if (lds) {
     for (int ty = r.y; ty <= r.w; ++ty)
@@ -303,7 +285,6 @@ __global__ __launch_bounds__(256) void scatter_kernel(PassArgs a) {
     }
     __syncthreads();
   }
-  const unsigned long long key = key_hi | (unsigned long long)(uint32_t)s;
   for (int ty = r.y; ty <= r.w; ++ty)
     for (int tx = r.x; tx <= r.z; ++tx) {
       const int t = ty * F.ntx + tx;
@@ -317,140 +298,114 @@ void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s) 
   hipLaunchKernelGGL(scatter_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a);
 }
 
-// ---------------------------------------------------------------- per-tile sort
-// Stable LSD radix sort of a tile's 64-bit keys (binary32 depth bits << 32 |
-// splat index) with 8-bit digits, skipping digits on which all keys agree.
-// 8 waves; wave w owns a contiguous segment of the keys, so (wave, step,
-// lane) order is key order and the ranking below is stable.  Lists of up to
-// kSortCap keys live in LDS; longer ones ping-pong through global memory.
-constexpr int kSortThreads = 512;
-constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortCap = 8192;
-
-__device__ __forceinline__ unsigned long long digit_peers(uint32_t d, bool valid) {
-  unsigned long long peers = __ballot(valid);
-#pragma unroll
-  for (int bit = 0; bit < 8; ++bit) {
-    const bool on = (d >> bit) & 1u;
-    const unsigned long long m = __ballot(on);
-    peers &= on ? m : ~m;
+// ---------------------------------------------------------------- longest-first tile order
+// Workgroups are dispatched in blockIdx order, so visiting tiles through a
+// list sorted by descending work (classes of floor(log2(work))) starts the
+// long lists first instead of leaving them for the end.  Scheduling only:
+// every tile's result is independent of when it runs.
+__global__ __launch_bounds__(1024) void tile_order_kernel(PassArgs a, int backward) {
+  __shared__ uint32_t cnt[33], cur[33];
+  if (threadIdx.x < 33) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  uint32_t* order = backward ? a.order_bwd : a.order_fwd;
+  auto cls = [&](int g) -> int {
+    const uint32_t wk = backward ? a.tile_last[g] : a.tile_start[g + 1] - a.tile_start[g];
+    return wk ? 31 - __clz(wk) : 32;   // class 32 = empty, last
+  };
+  for (int g = threadIdx.x; g < a.n_tiles; g += 1024) atomicAdd(&cnt[cls(g)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int c = 31; c >= 0; --c) { cur[c] = run; run += cnt[c]; }
+    cur[32] = run;
   }
-  return peers;
+  __syncthreads();
+  for (int g = threadIdx.x; g < a.n_tiles; g += 1024) order[atomicAdd(&cur[cls(g)], 1u)] = (uint32_t)g;
 }
 
-template <typename SrcT, typename DstT>
-__device__ __forceinline__ void radix_pass(SrcT src, DstT dst, int n, int shift, uint32_t* hist,
-                                           uint32_t* lds_waves) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int seg = ((n + kSortThreads - 1) / kSortThreads) * 64;
-  const int lo = w * seg, hi = min(n, lo + seg);
-  for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortThreads) hist[i] = 0u;
-  __syncthreads();
-  for (int base = lo; base < hi; base += 64) {
-    const int k = base + lane;
-    const bool valid = k < hi;
-    const uint32_t d = valid ? (uint32_t)(src[k] >> shift) & 255u : 0u;
-    const unsigned long long peers = digit_peers(d, valid);
-    if (valid && lanes_below(peers) == 0) hist[w * 256 + d] += (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-  // offsets in (digit, wave) order
-  uint32_t tot = 0;
-  if (threadIdx.x < 256) {
-    for (int ww = 0; ww < kSortWaves; ++ww) {
-      const uint32_t c = hist[ww * 256 + threadIdx.x];
-      hist[ww * 256 + threadIdx.x] = tot;
-      tot += c;
-    }
-  }
-  __syncthreads();
-  const uint32_t dbase = block_excl_scan<kSortThreads>(threadIdx.x < 256 ? tot : 0u, lds_waves, nullptr);
-  if (threadIdx.x < 256)
-    for (int ww = 0; ww < kSortWaves; ++ww) hist[ww * 256 + threadIdx.x] += dbase;
-  __syncthreads();
-  for (int base = lo; base < hi; base += 64) {
-    const int k = base + lane;
-    const bool valid = k < hi;
-    const unsigned long long key = valid ? src[k] : 0ull;
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
-    const unsigned long long peers = digit_peers(d, valid);
-    const uint32_t below = lanes_below(peers);
-    uint32_t at = 0;
-    if (valid) at = hist[w * 256 + d];
-    if (valid) dst[at + below] = key;
-    if (valid && below == 0) hist[w * 256 + d] = at + (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
+void launch_tile_order(const PassArgs& a, bool backward, hipStream_t s) {
+  if (a.n_tiles == 0) return;
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, a, backward ? 1 : 0);
 }
 
-__global__ __launch_bounds__(kSortThreads) void tile_sort_kernel(PassArgs a) {
-  extern __shared__ unsigned long long smem_keys[];
-  unsigned long long* bufA = smem_keys;
-  unsigned long long* bufB = smem_keys + kSortCap;
-  uint32_t* hist = reinterpret_cast<uint32_t*>(smem_keys + 2 * kSortCap);
-  uint32_t* lds_waves = hist + kSortWaves * 256;
-  uint32_t* vary = lds_waves + kSortWaves;
+// ---------------------------------------------------------------- per-tile order
+// Every splat of a frame has a unique frame-local rank in (depth, index)
+// order (computed once per frame by the depth-order stage), and a tile's
+// list is a subset of its frame's splats.  Sorting the list is therefore set
+// membership: mark the tile's ranks in an LDS bitmap, prefix-count the set
+// bits, and read them back in ascending order.  O(frame size / 32 + entries)
+// per tile, exact and deterministic.
+__global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
+  extern __shared__ uint32_t bitmap[];
+  __shared__ uint32_t lw[4];
   if (a.status->overflow) return;
-  const int g = blockIdx.x;
+  const int g = (int)a.order_fwd[blockIdx.x];
   const uint32_t start = a.tile_start[g];
-  const int n = (int)(a.tile_start[g + 1] - start);
+  const uint32_t n = a.tile_start[g + 1] - start;
   if (n == 0) return;
-  unsigned long long* gkeys = a.keys + start;
-  unsigned long long* galt = a.keys_alt + start;
-  const bool in_lds = n <= kSortCap;
-  if (threadIdx.x < 2) vary[threadIdx.x] = 0u;
-  __syncthreads();
-  const unsigned long long k0 = gkeys[0];
-  uint32_t vlo = 0, vhi = 0;
-  for (int i = threadIdx.x; i < n; i += kSortThreads) {
-    const unsigned long long k = gkeys[i];
-    if (in_lds) bufA[i] = k;
-    const unsigned long long x = k ^ k0;
-    vlo |= (uint32_t)x; vhi |= (uint32_t)(x >> 32);
-  }
-  if (vlo) atomicOr(&vary[0], vlo);
-  if (vhi) atomicOr(&vary[1], vhi);
-  __syncthreads();
-  const unsigned long long varying = ((unsigned long long)vary[1] << 32) | vary[0];
-  int parity = 0;   // 0: data in A (or gkeys), 1: in B (or galt)
-  for (int shift = 0; shift < 64; shift += 8) {
-    if (((varying >> shift) & 255ull) == 0) continue;
-    if (in_lds) {
-      if (parity == 0) radix_pass(bufA, bufB, n, shift, hist, lds_waves);
-      else radix_pass(bufB, bufA, n, shift, hist, lds_waves);
-    } else {
-      if (parity == 0) radix_pass(gkeys, galt, n, shift, hist, lds_waves);
-      else radix_pass(galt, gkeys, n, shift, hist, lds_waves);
-    }
-    parity ^= 1;
-  }
-  const unsigned long long* out = in_lds ? (parity ? bufB : bufA) : (parity ? galt : gkeys);
-  // sorted splat indices, and the map from each entry's emission slot
-  // (splat's emission offset + row-major index of the tile in its rect) to
-  // its sorted position
   const int b = frame_of_tile(a.frames, a.B, g);
   const FrameDev& F = a.frames[b];
+  const uint32_t vbase = a.bkt_start[b * a.nbk];
+  const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
+  const int W = (int)((nv + 31) / 32);
+  for (int w = threadIdx.x; w < W; w += 256) bitmap[w] = 0u;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += 256) {
+    const uint32_t r = a.keys[start + i];
+    atomicOr(&bitmap[r >> 5], 1u << (r & 31u));
+  }
+  __syncthreads();
+  const int wpt = (W + 255) / 256;
+  const int w0 = threadIdx.x * wpt, w1 = min(W, w0 + wpt);
+  uint32_t c = 0;
+  for (int w = w0; w < w1; ++w) c += __popc(bitmap[w]);
+  uint32_t out = start + block_excl_scan<256>(c, lw, nullptr);
+  // ranks in ascending order (each thread writes the set bits of its words)
+  for (int w = w0; w < w1; ++w) {
+    uint32_t bits = bitmap[w];
+    while (bits) {
+      const uint32_t bit = __ffs(bits) - 1u;
+      bits &= bits - 1u;
+      a.sorted[out++] = (uint32_t)w * 32u + bit;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // rank -> splat, and each entry's emission slot (splat's offset + row-major
+  // index of this tile in its rect), one entry per thread
   const int lt = g - F.tile_base;
   const int tx = lt % F.ntx, ty = lt / F.ntx;
-  for (int i = threadIdx.x; i < n; i += kSortThreads) {
-    const uint32_t s = (uint32_t)out[i];
-    a.sorted[start + i] = s;
-    const int4 r = a.rect[s];
-    const uint32_t j = (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
-    a.pos[a.soff[s] + j] = start + i;
+  const uint32_t* __restrict__ ranks = a.sorted + start;
+  for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * 256) {
+    uint32_t sp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + u * 256;
+      sp[u] = (i < n) ? a.depth_sorted[vbase + ranks[i]] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t i = i0 + u * 256;
+      if (i < n) {
+        const int4 r = a.rect[sp[u]];
+        const uint32_t e = a.soff[sp[u]] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
+        a.sorted[start + i] = sp[u];
+        a.emis[start + i] = e;
+      }
+    }
   }
 }
 
 void launch_tile_sort(const PassArgs& a, hipStream_t s) {
   if (a.n_tiles == 0) return;
-  const size_t lds = 2 * kSortCap * sizeof(unsigned long long) + (kSortWaves * 256 + kSortWaves + 2) * sizeof(uint32_t);
+  const size_t lds = (size_t)std::max(a.bitmap_words, 1) * sizeof(uint32_t);
   static bool attr_set = false;   // more than 64 KB of dynamic LDS must be requested explicitly
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_sort_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 32768 * (int)sizeof(uint32_t));
     attr_set = true;
   }
-  hipLaunchKernelGGL(tile_sort_kernel, dim3(a.n_tiles), dim3(kSortThreads), lds, s, a);
+  hipLaunchKernelGGL(tile_sort_kernel, dim3(a.n_tiles), dim3(256), lds, s, a);
 }
 
 // ---------------------------------------------------------------- compositing
@@ -485,28 +440,33 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
-  __shared__ float4 s0[CHUNK];
-  __shared__ float4 s1[CHUNK];
-  __shared__ float s2[CHUNK];
+  constexpr int U = 4;                  // entries evaluated together (independent alphas)
+  __shared__ float4 s0[CHUNK + U];
+  __shared__ float4 s1[CHUNK + U];
+  __shared__ float s2[CHUNK + U];
+  __shared__ uint32_t wbits[S::NW][CHUNK / 32];
+  __shared__ uint8_t wact[S::NW];
   __shared__ uint32_t s_last;
   if (a.status->overflow) return;
-  const int g = blockIdx.x;
+  const int g = (int)a.order_fwd[blockIdx.x];
   const int b = frame_of_tile(a.frames, a.B, g);
   const FrameDev& F = a.frames[b];
   const int lt = g - F.tile_base;
   const int tx = lt % F.ntx, ty = lt / F.ntx;
   const uint32_t start = a.tile_start[g], end = a.tile_start[g + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lx0 = (threadIdx.x % S::TPR) * S::PXW, ly0 = (threadIdx.x / S::TPR) * S::PXW;
-  float T_[S::PX], C0[S::PX], C1[S::PX], C2[S::PX];
-  uint32_t last[S::PX];
-  bool done[S::PX];
-  int pxi[S::PX], pyi[S::PX];
+  float T_[S::PX], C0[S::PX], C1[S::PX], C2[S::PX], pxf[S::PX], pyf[S::PX];
+  uint32_t last[S::PX], ncon[S::PX];
+  bool done[S::PX], inside[S::PX];
 #pragma unroll
   for (int p = 0; p < S::PX; ++p) {
-    pxi[p] = tx * T + lx0 + (p % S::PXW);
-    pyi[p] = ty * T + ly0 + (p / S::PXW);
-    T_[p] = 1.0f; C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0;
-    done[p] = !(pxi[p] < F.W && pyi[p] < F.H);
+    const int px = tx * T + lx0 + (p % S::PXW), py = ty * T + ly0 + (p / S::PXW);
+    pxf[p] = (float)px + 0.5f;
+    pyf[p] = (float)py + 0.5f;
+    inside[p] = px < F.W && py < F.H;
+    T_[p] = 1.0f; C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0; ncon[p] = 0;
+    done[p] = !inside[p];
   }
   if (threadIdx.x == 0) s_last = 0;
   for (uint32_t cb = start; cb < end; cb += CHUNK) {
@@ -516,32 +476,73 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
       const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[cb + i] * kRecF);
       s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
     }
+    if (threadIdx.x < U) {                 // padding entries: opacity 0, never taken
+      s0[n + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      s1[n + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      s2[n + threadIdx.x] = 0.f;
+    }
     __syncthreads();
-    bool all_done = true;
+    bool mine = false;
 #pragma unroll
-    for (int p = 0; p < S::PX; ++p) all_done &= done[p];
-    if (!all_done) {
-      for (int i = 0; i < n; ++i) {
-        const float4 r0 = s0[i], r1 = s1[i];
+    for (int p = 0; p < S::PX; ++p) mine |= !done[p];
+    const bool wave_active = __ballot(mine) != 0ull;
+    if (lane == 0) wact[w] = wave_active ? 1 : 0;
+    if (wave_active) {
+      uint32_t bits = 0;                   // wave-uniform: entries of the current 32 some pixel took
+      for (int i0 = 0; i0 < n; i0 += U) {
+        float4 r0[U], r1[U];
+        float cb2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { r0[u] = s0[i0 + u]; r1[u] = s1[i0 + u]; cb2[u] = s2[i0 + u]; }
+        bool took[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) took[u] = false;
 #pragma unroll
         for (int p = 0; p < S::PX; ++p) {
-          if (done[p]) continue;
-          float dx, dy, pwr, g2;
-          const float al0 = splat_alpha(r0, r1, (float)pxi[p] + 0.5f, (float)pyi[p] + 0.5f, dx, dy, pwr, g2);
-          if (al0 < kAlphaMin) continue;
-          const float al = fminf(al0, kAlphaMax);
-          const float tn = T_[p] * (1.0f - al);
-          if (tn < kTMin) { done[p] = true; continue; }
-          const float w = al * T_[p];
-          C0[p] = __builtin_fmaf(w, r1.z, C0[p]);
-          C1[p] = __builtin_fmaf(w, r1.w, C1[p]);
-          C2[p] = __builtin_fmaf(w, s2[i], C2[p]);
-          T_[p] = tn;
-          last[p] = cb - start + i + 1;
+          float al[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            float dx, dy, pwr, g2;
+            al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr, g2);
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            // branch-free front-to-back step; the arithmetic of a taken entry is
+            // exactly that of the plain loop, an untaken one changes nothing
+            const bool ok = !done[p] && (i0 + u < n) && al[u] >= kAlphaMin;
+            const float alc = fminf(al[u], kAlphaMax);
+            const float tn = T_[p] * (1.0f - alc);
+            const bool stop = ok && tn < kTMin;
+            const bool take = ok && !stop;
+            done[p] = done[p] || stop;
+            const float wgt = take ? alc * T_[p] : 0.0f;
+            C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
+            C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
+            C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
+            T_[p] = take ? tn : T_[p];
+            last[p] = take ? (cb - start + (uint32_t)(i0 + u) + 1u) : last[p];
+            ncon[p] += take ? 1u : 0u;
+            took[u] = took[u] || take;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (__ballot(took[u]) != 0ull) bits |= 1u << ((i0 + u) & 31);
+        if (((i0 + U) & 31) == 0 || i0 + U >= n) {
+          if (lane == 0) wbits[w][i0 >> 5] = bits;
+          bits = 0;
         }
       }
     }
-    bool mine = false;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += S::NT) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int ww = 0; ww < S::NW; ++ww)
+        if (wact[ww] && ((wbits[ww][i >> 5] >> (i & 31)) & 1u)) m |= 1u << ww;
+      a.cmask[cb + i] = (uint8_t)m;
+    }
+    mine = false;
 #pragma unroll
     for (int p = 0; p < S::PX; ++p) mine |= !done[p];
     if (__syncthreads_count(mine) == 0) break;
@@ -549,14 +550,16 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   uint32_t my_last = 0;
 #pragma unroll
   for (int p = 0; p < S::PX; ++p) {
-    if (pxi[p] < F.W && pyi[p] < F.H) {
-      const int64_t pix = (int64_t)pyi[p] * F.W + pxi[p];
+    if (inside[p]) {
+      const int px = (int)pxf[p], py = (int)pyf[p];
+      const int64_t pix = (int64_t)py * F.W + px;
       const int64_t hw = (int64_t)F.W * F.H;
       float* img = images + F.pix_base * 3;
       img[pix] = C0[p] + T_[p] * F.bg[0];
       img[hw + pix] = C1[p] + T_[p] * F.bg[1];
       img[2 * hw + pix] = C2[p] + T_[p] * F.bg[2];
       a.n_iter[F.pix_base + pix] = last[p];
+      a.n_contrib[F.pix_base + pix] = ncon[p];
       a.t_final[F.pix_base + pix] = T_[p];
       my_last = max(my_last, last[p]);
     }

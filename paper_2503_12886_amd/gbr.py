@@ -82,7 +82,15 @@ _SIGS = {
     "gbr_autotune": ([_vp, _vp, ctypes.POINTER(_i64), ctypes.POINTER(gbr_camera), _i32, _vp, _vp, _vp, _vp,
                       ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_f32)], ctypes.c_int),
     "gbr_inspect": ([_vp, _i32, _vp, ctypes.POINTER(_i64)], ctypes.c_int),
+    "gbr_timing": ([_vp, _i32, _i32], ctypes.c_int),
+    "gbr_timing_read": ([_vp, _i32, ctypes.POINTER(_f32)], ctypes.c_int),
 }
+
+# kernel ids of gbr_timing (GBR_K_*)
+K_BLEND, K_PREPROCESS, K_BINNING, K_TILE_SORT, K_COMPOSITE_FWD, K_COMPOSITE_BWD, K_GATHER_BWD, K_BLEND_BWD, \
+    K_ADAM, K_LOSS, K_MLP, K_TILE_SCAN, K_DEPTH_ORDER = range(13)
+KERNEL_NAMES = ["blend", "preprocess", "binning", "tile_sort", "composite_fwd", "composite_bwd", "gather_bwd",
+                "blend_bwd", "adam", "loss", "mlp", "tile_scan", "depth_order"]
 
 
 def header_symbols() -> list:
@@ -347,7 +355,17 @@ def gbr_autotune(ctx: Context, raw, gauss_offsets, cams, images, dimages, draw, 
 
 INSPECT = {"records": (1, np.float32, 12), "rects": (2, np.int32, 4), "tile_start": (3, np.uint32, 1),
            "sorted": (4, np.uint32, 1), "n_iter": (5, np.uint32, 1), "t_final": (6, np.float32, 1),
-           "tile_last": (7, np.uint32, 1)}
+           "tile_last": (7, np.uint32, 1), "n_contrib": (8, np.uint32, 1)}
+
+
+def gbr_timing(ctx: Context, which: int, enable: bool) -> None:
+    _check(lib().gbr_timing(ctx.handle, int(which), int(bool(enable))), "gbr_timing")
+
+
+def gbr_timing_read(ctx: Context, which: int) -> float:
+    ms = _f32()
+    _check(lib().gbr_timing_read(ctx.handle, int(which), ctypes.byref(ms)), "gbr_timing_read")
+    return float(ms.value)
 
 
 def gbr_inspect(ctx: Context, what: str, count: int) -> np.ndarray:

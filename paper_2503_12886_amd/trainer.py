@@ -1,0 +1,203 @@
+"""Training-step driver: the sequence of library calls that makes one
+optimisation step of the reduced-Gaussian-blendshape avatar, in two schemes.
+
+* batched (Sec. 3.2, Fig. 4c): B frames per step -- weights MLP (Eq. 2),
+  blend (Eq. 1), one batch-parallel render, L1 loss with random backgrounds
+  (Sec. 3.2), backward to bases and MLP, Adam with per-attribute learning
+  rates (Sec. A.3); one host synchronisation (the status read) per step.
+  The whole step can be captured once as a graph and replayed.
+* per-frame (Fig. 4a, "w/o batch parallel"): one frame per optimisation
+  step, preprocess -> host synchronisation to size the tile lists ->
+  rasterize, and an Adam step per frame.
+
+This module only sequences calls into libgbr and owns the device buffers;
+every step of the computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import gbr
+
+# Adam learning rates of Sec. A.3: position 8e-4, opacity 0.25, scale 0.025,
+# rotation 5e-3, colour 0.0125; blendshape deltas of position, rotation and
+# colour at 0.05x, 0.5x and 0.5x of those (deltas of scale and opacity, which
+# the paper does not blend, keep the base rate here); MLP 1e-3.
+_BASE = {"pos": 8e-4, "rot": 5e-3, "scale": 0.025, "opacity": 0.25, "color": 0.0125}
+_DELTA = {"pos": 0.05, "rot": 0.5, "scale": 1.0, "opacity": 1.0, "color": 0.5}
+_GROUPS = ["pos"] * 3 + ["rot"] * 4 + ["scale"] * 3 + ["opacity"] + ["color"] * 3 + [None, None]
+MLP_LR = 1e-3
+ADAM_BETAS = (0.9, 0.999)
+ADAM_EPS = 1e-15
+
+
+def bases_lr_table() -> list:
+    base = [(_BASE[g] if g else 0.0) for g in _GROUPS]
+    delta = [(_BASE[g] * _DELTA[g] if g else 0.0) for g in _GROUPS]
+    return base + delta
+
+
+@dataclass
+class StepConfig:
+    N: int = 50_000
+    K: int = 20
+    B: int = 16
+    width: int = 512
+    height: int = 512
+    d_in: int = 56
+    hidden: int = 256
+    loss: int = 1            # 1 = L1 (paper), 2 = L2
+    tile: int = 16
+    chunk: int = 128
+
+
+def mlp_numel(d_in: int, hidden: int, K: int) -> int:
+    return hidden * d_in + hidden + hidden * hidden + hidden + K * hidden + K
+
+
+class Trainer:
+    def __init__(self, cfg: StepConfig, bases: np.ndarray, mlp_params: np.ndarray, max_entries: int = 0,
+                 device: int = 0):
+        import torch
+        self.cfg = cfg
+        self.torch = torch
+        N, K, B = cfg.N, cfg.K, cfg.B
+        dev = torch.device("cuda", device)
+        f32 = dict(device=dev, dtype=torch.float32)
+        self.bases = torch.from_numpy(np.ascontiguousarray(bases, dtype=np.float32)).to(dev)
+        assert tuple(self.bases.shape) == (K + 1, N, 16)
+        self.bases_m = torch.zeros_like(self.bases)
+        self.bases_v = torch.zeros_like(self.bases)
+        self.dbases = torch.zeros_like(self.bases)
+        nm = mlp_numel(cfg.d_in, cfg.hidden, K)
+        self.mlp = torch.from_numpy(np.ascontiguousarray(mlp_params, dtype=np.float32)).to(dev)
+        assert self.mlp.numel() == nm
+        self.mlp_m = torch.zeros_like(self.mlp)
+        self.mlp_v = torch.zeros_like(self.mlp)
+        self.dmlp = torch.zeros_like(self.mlp)
+        self.theta = torch.zeros(B, cfg.d_in, **f32)
+        self.psi = torch.zeros(B, K, **f32)
+        self.dpsi = torch.zeros(B, K, **f32)
+        self.raw = torch.zeros(B, N, 16, **f32)
+        npix = cfg.width * cfg.height
+        self.images = torch.zeros(B * 3 * npix, **f32)
+        self.dimages = torch.zeros_like(self.images)
+        self.targets = torch.zeros_like(self.images)
+        if max_entries <= 0:
+            max_entries = max(1 << 20, 40 * B * N)
+        self.ctx = gbr.Context(tile=cfg.tile, chunk=cfg.chunk, device=device, max_frames=max(B, 1),
+                               max_splats=B * N, max_pixels=B * npix, max_entries=max_entries)
+        self.lr_bases = bases_lr_table()
+        self.lr_mlp = [MLP_LR] * 32
+        self.cams = None
+        self.graph = None
+        self.offsets = [b * N for b in range(B + 1)]
+        # a stream of its own (default priority): the legacy null stream cannot be captured
+        self.stream = torch.cuda.Stream(device=dev)
+
+    # ---------------------------------------------------------------- inputs
+    def set_batch(self, theta: np.ndarray, targets: np.ndarray, cams: list) -> None:
+        """Copy one batch of (tracking vector, target image, camera) into the step's buffers."""
+        assert len(cams) == self.cfg.B
+        self.torch.cuda.synchronize()
+        self.theta.copy_(self.torch.from_numpy(np.ascontiguousarray(theta, dtype=np.float32)))
+        self.targets.copy_(self.torch.from_numpy(np.ascontiguousarray(targets, dtype=np.float32).ravel()))
+        self.torch.cuda.synchronize()
+        self.cams = list(cams)
+        if self.graph is not None:
+            gbr.gbr_stage_frames(self.ctx, self.offsets, self.cams)
+
+    # ---------------------------------------------------------------- one step
+    def enqueue_step(self) -> None:
+        """Every kernel of one batched optimisation step, enqueued on the trainer's stream."""
+        with self.torch.cuda.stream(self.stream):
+            self._enqueue_step()
+
+    def _enqueue_step(self) -> None:
+        c, cfg = self.ctx, self.cfg
+        gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
+        gbr.gbr_blend(c, self.bases, self.psi, self.raw)
+        gbr.gbr_render(c, self.raw, self.offsets, self.cams, self.images)
+        gbr.gbr_loss(c, self.images, self.targets, cfg.loss, self.dimages)
+        gbr.gbr_backward(c, self.dimages, self.bases, self.psi, self.dbases, self.dpsi)
+        gbr.gbr_mlp_backward(c, self.mlp, self.dpsi, self.dmlp)
+        gbr.gbr_adam_step(c, 0, self.bases, self.dbases, self.bases_m, self.bases_v, cfg.N * 16, self.lr_bases,
+                          ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+        gbr.gbr_adam_step(c, 1, self.mlp, self.dmlp, self.mlp_m, self.mlp_v, self.mlp.numel(), self.lr_mlp,
+                          ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+
+    def step(self) -> gbr.gbr_status:
+        """One batched step (graph replay if captured) and its single status read.
+        On entry overflow the step did not update anything: grow and replay."""
+        for _ in range(3):
+            if self.graph is not None:
+                gbr.gbr_graph_launch(self.graph, self.stream)
+            else:
+                self.enqueue_step()
+            st = gbr.gbr_query_status(self.ctx, self.stream)
+            if not st.overflow:
+                return st
+            self._grow(st.entries)
+        raise RuntimeError("tile-entry overflow persists after growing the capacity")
+
+    def _grow(self, entries: int) -> None:
+        gbr.gbr_reserve(self.ctx, entries + entries // 4 + 4096)
+        if self.graph is not None:      # buffers moved: capture again
+            gbr.gbr_graph_destroy(self.graph)
+            self.graph = None
+            self.capture()
+
+    def capture(self) -> None:
+        """Capture one step as a graph (after a warm-up step sized the buffers)."""
+        self.torch.cuda.synchronize()
+        gbr.gbr_graph_begin(self.ctx, self.stream)
+        try:
+            self.enqueue_step()
+        finally:
+            g = gbr.gbr_graph_end(self.ctx, self.stream)
+        self.graph = g
+
+    # ---------------------------------------------------------------- per-frame scheme
+    def per_frame_steps(self, frames) -> None:
+        """One optimisation step per frame (frames: indices into the current batch)."""
+        with self.torch.cuda.stream(self.stream):
+            self._per_frame_steps(frames)
+
+    def _per_frame_steps(self, frames) -> None:
+        c, cfg = self.ctx, self.cfg
+        npix = cfg.width * cfg.height
+        for b in frames:
+            th = self.theta[b:b + 1]
+            psi = self.psi[b:b + 1]
+            raw = self.raw[0:1]
+            img = self.images[:3 * npix]
+            dimg = self.dimages[:3 * npix]
+            tgt = self.targets[b * 3 * npix:(b + 1) * 3 * npix]
+            gbr.gbr_mlp_forward(c, self.mlp, th, cfg.d_in, cfg.hidden, cfg.K, psi)
+            gbr.gbr_blend(c, self.bases, psi, raw)
+            gbr.gbr_preprocess(c, raw, [0, cfg.N], [self.cams[b]])
+            gbr.gbr_entry_count(c)                      # the per-frame host synchronisation (Sec. 3.2)
+            gbr.gbr_rasterize(c, img)
+            gbr.gbr_loss(c, img, tgt, cfg.loss, dimg)
+            gbr.gbr_backward(c, dimg, self.bases, psi, self.dbases, self.dpsi[b:b + 1])
+            gbr.gbr_mlp_backward(c, self.mlp, self.dpsi[b:b + 1], self.dmlp)
+            gbr.gbr_adam_step(c, 0, self.bases, self.dbases, self.bases_m, self.bases_v, cfg.N * 16,
+                              self.lr_bases, ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+            gbr.gbr_adam_step(c, 1, self.mlp, self.dmlp, self.mlp_m, self.mlp_v, self.mlp.numel(), self.lr_mlp,
+                              ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+            st = gbr.gbr_query_status(c)
+            if st.overflow:
+                raise RuntimeError("unexpected overflow in the per-frame scheme")
+
+    def close(self) -> None:
+        if self.graph is not None:
+            gbr.gbr_graph_destroy(self.graph)
+            self.graph = None
+        self.ctx.close()
+
+
+def mlp_pack(p: dict) -> np.ndarray:
+    return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(), p["b3"]]).astype(
+        np.float32)
