@@ -23,7 +23,7 @@ constexpr int kBlendMaxSteps = 16;   // K + 1 <= 64
 // One wave per (16-frame group, run of Gaussians).  Grid: x over Gaussian runs,
 // y over frame groups.  256 threads = 4 waves, each walking kGaussPerWave
 // consecutive Gaussians.
-constexpr int kGaussPerWave = 16;
+constexpr int kGaussPerWave = 4;
 
 __global__ __launch_bounds__(256) void blend_fwd_kernel(const float* __restrict__ bases,
                                                          const float* __restrict__ weights, int B, int K,
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void blend_dbases_kernel(const float* __restri
 
 // dweights partials: wave w covers Gaussians [w*G, (w+1)*G) and writes a
 // [B][K] partial; frames in row tiles of 16, slices 1..K in column tiles of 16.
-constexpr int kDwGaussPerWave = 64;
+constexpr int kDwGaussPerWave = 16;
 
 template <int MAXBT, int MAXKT>
 __global__ __launch_bounds__(256) void blend_dweights_kernel(const float* __restrict__ draw,

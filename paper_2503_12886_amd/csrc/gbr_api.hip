@@ -68,7 +68,7 @@ struct gbr_ctx {
   uint32_t *cnt = nullptr, *soff = nullptr;
   uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_cursor = nullptr, *tile_last = nullptr;
   uint32_t* keys = nullptr;
-  uint32_t *sorted = nullptr, *emis = nullptr;
+  uint32_t* sorted = nullptr;
   uint32_t *order_fwd = nullptr, *order_bwd = nullptr;
   uint8_t* part_flag = nullptr;
   uint8_t* cmask = nullptr;
@@ -134,7 +134,7 @@ PassArgs make_args(gbr_ctx* c) {
   a.tile_count = c->tile_count; a.tile_start = c->tile_start; a.tile_cursor = c->tile_cursor;
   a.tile_last = c->tile_last;
   a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd;
-  a.keys = c->keys; a.sorted = c->sorted; a.emis = c->emis; a.part_flag = c->part_flag; a.cmask = c->cmask;
+  a.keys = c->keys; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
   a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
   a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_start = c->bkt_start; a.bkt_cursor = c->bkt_cursor;
@@ -165,11 +165,10 @@ int check_tiling(int tile, int chunk) {
 }
 
 int alloc_entries(gbr_ctx* c, int64_t cap) {
-  dfree(c->keys); dfree(c->sorted); dfree(c->emis); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
+  dfree(c->keys); dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   int rc = GBR_OK;
   if ((rc = dalloc(&c->keys, cap))) return rc;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
-  if ((rc = dalloc(&c->emis, cap))) return rc;
   if ((rc = dalloc(&c->part_flag, cap + 16))) return rc;
   if ((rc = dalloc(&c->cmask, cap))) return rc;
   if ((rc = dalloc(&c->part, cap * 9))) return rc;
@@ -192,7 +191,7 @@ void free_all(gbr_ctx* c) {
   dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff);
   dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_cursor); dfree(c->tile_last);
   dfree(c->order_fwd); dfree(c->order_bwd);
-  dfree(c->keys); dfree(c->sorted); dfree(c->emis); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
+  dfree(c->keys); dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
@@ -402,7 +401,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
                                                   (int64_t)8192 * c->cap_frames))));
   TRY(dalloc(&c->draw_scratch, c->cap_splats * kNF));
   TRY(dalloc(&c->loss_part, 2 * loss_partials(3 * c->cap_pixels) + 2));
-  c->blend_part_n = c->cap_splats + 256LL * c->cap_frames + 64LL * 64 * 8;
+  c->blend_part_n = 4 * c->cap_splats + 4096LL * c->cap_frames + 64LL * 64 * 8;
   TRY(dalloc(&c->blend_part, c->blend_part_n));
   TRY(dalloc(&c->mlp_z1, (int64_t)c->cap_frames * 1024));
   TRY(dalloc(&c->mlp_z2, (int64_t)c->cap_frames * 1024));

@@ -71,7 +71,6 @@ struct PassArgs {
   uint32_t* sorted;         // [E] splat index in tile order
   uint32_t* order_fwd;      // [tiles] tiles by descending list length (scheduling only)
   uint32_t* order_bwd;      // [tiles] tiles by descending entries used by the forward pass
-  uint32_t* emis;           // [E] sorted position -> emission slot (splat offset + tile index in its rect)
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
   int32_t bitmap_words;     // LDS words of the per-tile rank bitmap (max frame size / 32)

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   __shared__ float red[CHUNK][S::NW][9];
   __shared__ uint8_t wany[CHUNK][S::NW];
   __shared__ uint8_t cm[CHUNK];
+  __shared__ uint32_t sid[CHUNK];
   if (a.status->overflow) return;
   const int g = (int)a.order_bwd[blockIdx.x];
   const uint32_t L = a.tile_last[g];
@@ -85,9 +86,11 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     const int n = ce - cbeg;
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += S::NT) {
-      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[start + cbeg + i] * kRecF);
+      const uint32_t sp = a.sorted[start + cbeg + i];
+      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
       s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
       cm[i] = a.cmask[start + cbeg + i];
+      sid[i] = sp;
     }
     __syncthreads();
     for (int i = n - 1; i >= 0; --i) {
@@ -105,22 +108,23 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
       bool any = false;
 #pragma unroll
       for (int p = 0; p < S::PX; ++p) {
-        if (li >= nit[p]) continue;
+        // branch-free: lanes whose pixel does not take this entry add exact zeros
         float dx, dy, pwr, g2;
         const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr, g2);
-        if (a0 < kAlphaMin) continue;
-        any = true;
+        const bool take = li < nit[p] && a0 >= kAlphaMin;
+        any = any || take;
         const float al = fminf(a0, kAlphaMax);
         const float inv = __builtin_amdgcn_rcpf(1.0f - al);
         const float Ti = T_[p] * inv;                     // transmittance in front of this entry
-        const float wgt = al * Ti;
+        const float wgt = take ? al * Ti : 0.0f;
         acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
         const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];
         const float rg = R0[p] * G0[p] + R1[p] * G1[p] + R2[p] * G2[p];
         const float dal = Ti * cg - rg * inv;             // d out / d alpha
         R0[p] += wgt * r1.z; R1[p] += wgt * r1.w; R2[p] += wgt * cbl;
-        T_[p] = Ti;
-        const float da = (a0 < kAlphaMax) ? dal : 0.0f;   // min(0.99, .) passes the gradient only below the clamp
+        T_[p] = take ? Ti : T_[p];
+        // min(0.99, .) passes the gradient only below the clamp
+        const float da = (take && a0 < kAlphaMax) ? dal : 0.0f;
         acc[5] += g2 * da;
         const float dpw = (pwr > 0.0f) ? 0.0f : da * a0 * (float)kLn2;
         acc[2] += dpw * dx * dx;
@@ -175,7 +179,10 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
         for (int c = 0; c < 9; ++c) v[c] += red[i][ww][c];
       }
       if (hit) {
-        const uint32_t e = a.emis[start + cbeg + i];
+        // emission slot: the splat's offset + row-major index of this tile in its rect
+        const uint32_t sp = sid[i];
+        const int4 r = a.rect[sp];
+        const uint32_t e = a.soff[sp] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
         float* dst = a.part + (int64_t)e * 9;
 #pragma unroll
         for (int c = 0; c < 9; ++c) dst[c] = v[c];
@@ -240,11 +247,17 @@ __global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float
   for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
   // the splat's entries are contiguous in emission order (tiles of its rect,
   // row-major); unflagged entries are zero
-  for (uint32_t e = off; e < off + c; ++e) {
-    if (a.part_flag[e]) {
-      const float* q = a.part + (int64_t)e * 9;
+  for (uint32_t e0 = off; e0 < off + c; e0 += 8) {
+    uint8_t f[8];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc[k] += q[k];
+    for (int u = 0; u < 8; ++u) f[u] = (e0 + u < off + c) ? a.part_flag[e0 + u] : (uint8_t)0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (f[u]) {
+        const float* q = a.part + (int64_t)(e0 + u) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += q[k];
+      }
     }
   }
 

@@ -371,10 +371,7 @@ __global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
   }
   __threadfence_block();
   __syncthreads();
-  // rank -> splat, and each entry's emission slot (splat's offset + row-major
-  // index of this tile in its rect), one entry per thread
-  const int lt = g - F.tile_base;
-  const int tx = lt % F.ntx, ty = lt / F.ntx;
+  // rank -> splat, one entry per thread
   const uint32_t* __restrict__ ranks = a.sorted + start;
   for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * 256) {
     uint32_t sp[4];
@@ -386,12 +383,7 @@ __global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint32_t i = i0 + u * 256;
-      if (i < n) {
-        const int4 r = a.rect[sp[u]];
-        const uint32_t e = a.soff[sp[u]] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
-        a.sorted[start + i] = sp[u];
-        a.emis[start + i] = e;
-      }
+      if (i < n) a.sorted[start + i] = sp[u];
     }
   }
 }

@@ -6,88 +6,66 @@
 namespace gbr {
 
 // ---------------------------------------------------------------- MLP forward
-// One block per frame.  Each wave computes whole output units: the 64 lanes
-// split the input dimension (coalesced row reads), then a fixed-order DPP
-// reduction.  Pre-activations are kept for the backward pass.
-constexpr int kMlpThreads = 256;
-constexpr int kMlpMaxDim = 1024;
+// One launch per layer.  A block owns 16 output units for every frame: the 16
+// weight rows are staged in LDS once, each thread forms one (frame, unit) dot
+// product in input order.  The ReLU of the previous layer is applied when its
+// stored pre-activation is read.
+constexpr int kRowsPerBlock = 16;
+constexpr int kMlpMaxIn = 1024;
 
-__device__ __forceinline__ float row_dot(const float* __restrict__ wrow, const float* __restrict__ x, int len) {
-  const int lane = threadIdx.x & 63;
-  float s = 0.0f;
-  for (int i = lane; i < len; i += 64) s = __builtin_fmaf(wrow[i], x[i], s);
-  s = wave_sum_to63(s);
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, s), 63));
-}
-
-__global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(const float* __restrict__ P,
-                                                               const float* __restrict__ theta, int d_in,
-                                                               int hidden, int K, float* __restrict__ psi,
-                                                               float* __restrict__ z1, float* __restrict__ z2) {
-  __shared__ float x[kMlpMaxDim], h1[kMlpMaxDim], h2[kMlpMaxDim];
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = kMlpThreads / 64;
-  const float* W1 = P;
-  const float* b1 = W1 + (int64_t)hidden * d_in;
-  const float* W2 = b1 + hidden;
-  const float* b2 = W2 + (int64_t)hidden * hidden;
-  const float* W3 = b2 + hidden;
-  const float* b3 = W3 + (int64_t)K * hidden;
-  for (int i = threadIdx.x; i < d_in; i += kMlpThreads) x[i] = theta[(int64_t)b * d_in + i];
+__global__ __launch_bounds__(1024) void dense_fwd_kernel(const float* __restrict__ W, const float* __restrict__ bias,
+                                                         const float* __restrict__ in, int relu_in, int B, int n_in,
+                                                         int n_out, float* __restrict__ out) {
+  __shared__ float w[kRowsPerBlock * kMlpMaxIn];
+  const int j0 = blockIdx.x * kRowsPerBlock;
+  const int rows = min(kRowsPerBlock, n_out - j0);
+  for (int t = threadIdx.x; t < rows * n_in; t += blockDim.x) w[t] = W[(int64_t)j0 * n_in + t];
   __syncthreads();
-  for (int j = w; j < hidden; j += NW) {
-    const float z = row_dot(W1 + (int64_t)j * d_in, x, d_in) + b1[j];
-    if (lane == 0) { z1[(int64_t)b * hidden + j] = z; h1[j] = fmaxf(z, 0.0f); }
-  }
-  __syncthreads();
-  for (int j = w; j < hidden; j += NW) {
-    const float z = row_dot(W2 + (int64_t)j * hidden, h1, hidden) + b2[j];
-    if (lane == 0) { z2[(int64_t)b * hidden + j] = z; h2[j] = fmaxf(z, 0.0f); }
-  }
-  __syncthreads();
-  for (int k = w; k < K; k += NW) {
-    const float z = row_dot(W3 + (int64_t)k * hidden, h2, hidden) + b3[k];
-    if (lane == 0) psi[(int64_t)b * K + k] = z;
+  for (int q = threadIdx.x; q < B * rows; q += blockDim.x) {
+    const int b = q / rows, jj = q % rows;
+    const float* x = in + (int64_t)b * n_in;
+    const float* wr = w + jj * n_in;
+    float s = 0.0f;
+    if (relu_in) {
+      for (int i = 0; i < n_in; ++i) s = __builtin_fmaf(wr[i], fmaxf(x[i], 0.0f), s);
+    } else {
+      for (int i = 0; i < n_in; ++i) s = __builtin_fmaf(wr[i], x[i], s);
+    }
+    out[(int64_t)b * n_out + j0 + jj] = s + bias[j0 + jj];
   }
 }
 
 void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, int hidden, int K, float* psi,
                     float* z1, float* z2, hipStream_t s) {
   if (B == 0) return;
-  hipLaunchKernelGGL(mlp_fwd_kernel, dim3(B), dim3(kMlpThreads), 0, s, params, theta, d_in, hidden, K, psi, z1, z2);
+  const float* W1 = params;
+  const float* b1 = W1 + (int64_t)hidden * d_in;
+  const float* W2 = b1 + hidden;
+  const float* b2 = W2 + (int64_t)hidden * hidden;
+  const float* W3 = b2 + hidden;
+  const float* b3 = W3 + (int64_t)K * hidden;
+  const int thr = std::min(1024, std::max(64, ((B * kRowsPerBlock + 63) / 64) * 64));
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(hidden, kRowsPerBlock)), dim3(thr), 0, s, W1, b1, theta, 0, B,
+                     d_in, hidden, z1);
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(hidden, kRowsPerBlock)), dim3(thr), 0, s, W2, b2, z1, 1, B,
+                     hidden, hidden, z2);
+  hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(K, kRowsPerBlock)), dim3(thr), 0, s, W3, b3, z2, 1, B, hidden, K,
+                     psi);
 }
 
 // ---------------------------------------------------------------- MLP backward
-// Kernel 1 (one block per frame): dz2 = (W3^T dpsi) * [z2 > 0], dz1 = (W2^T dz2) * [z1 > 0].
-// Kernel 2 (one thread per parameter): weight/bias gradients summed over the
-// frames in frame order.
-__global__ __launch_bounds__(kMlpThreads) void mlp_bwd_act_kernel(const float* __restrict__ P,
-                                                                   const float* __restrict__ z1,
-                                                                   const float* __restrict__ z2,
-                                                                   const float* __restrict__ dpsi, int d_in,
-                                                                   int hidden, int K, float* __restrict__ dz1,
-                                                                   float* __restrict__ dz2) {
-  __shared__ float g[64];
-  __shared__ float d2[kMlpMaxDim];
-  const int b = blockIdx.x;
-  const float* W2 = P + (int64_t)hidden * d_in + hidden;
-  const float* W3 = W2 + (int64_t)hidden * hidden + hidden;
-  for (int k = threadIdx.x; k < K; k += kMlpThreads) g[k] = dpsi[(int64_t)b * K + k];
-  __syncthreads();
-  for (int i = threadIdx.x; i < hidden; i += kMlpThreads) {
-    float s = 0.0f;
-    for (int k = 0; k < K; ++k) s = __builtin_fmaf(W3[(int64_t)k * hidden + i], g[k], s);
-    const float v = z2[(int64_t)b * hidden + i] > 0.0f ? s : 0.0f;
-    d2[i] = v;
-    dz2[(int64_t)b * hidden + i] = v;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < hidden; i += kMlpThreads) {
-    float s = 0.0f;
-    for (int j = 0; j < hidden; ++j) s = __builtin_fmaf(W2[(int64_t)j * hidden + i], d2[j], s);
-    dz1[(int64_t)b * hidden + i] = z1[(int64_t)b * hidden + i] > 0.0f ? s : 0.0f;
-  }
+// dz2 = (W3^T dpsi) * [z2 > 0], dz1 = (W2^T dz2) * [z1 > 0]: one thread per
+// (frame, unit), reading a weight column (coalesced across threads); then one
+// thread per parameter sums over the frames in frame order.
+__global__ __launch_bounds__(256) void dense_bwd_act_kernel(const float* __restrict__ W,
+                                                            const float* __restrict__ g, const float* __restrict__ z,
+                                                            int B, int n_g, int n_x, float* __restrict__ dz) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= B * n_x) return;
+  const int b = q / n_x, i = q % n_x;
+  float s = 0.0f;
+  for (int k = 0; k < n_g; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[(int64_t)b * n_g + k], s);
+  dz[q] = z[q] > 0.0f ? s : 0.0f;
 }
 
 __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restrict__ theta,
@@ -128,8 +106,12 @@ __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restr
 void launch_mlp_bwd(const float* params, const float* theta, const float* z1, const float* z2, const float* dpsi,
                     int B, int d_in, int hidden, int K, float* dz1, float* dz2, float* dparams, hipStream_t s) {
   if (B == 0) return;
-  hipLaunchKernelGGL(mlp_bwd_act_kernel, dim3(B), dim3(kMlpThreads), 0, s, params, z1, z2, dpsi, d_in, hidden, K,
-                     dz1, dz2);
+  const float* W2 = params + (int64_t)hidden * d_in + hidden;
+  const float* W3 = W2 + (int64_t)hidden * hidden + hidden;
+  hipLaunchKernelGGL(dense_bwd_act_kernel, dim3(div_up((int64_t)B * hidden, 256)), dim3(256), 0, s, W3, dpsi, z2, B,
+                     K, hidden, dz2);
+  hipLaunchKernelGGL(dense_bwd_act_kernel, dim3(div_up((int64_t)B * hidden, 256)), dim3(256), 0, s, W2, dz2, z1, B,
+                     hidden, hidden, dz1);
   const int64_t total = (int64_t)hidden * d_in + hidden + (int64_t)hidden * hidden + hidden + (int64_t)K * hidden + K;
   hipLaunchKernelGGL(mlp_bwd_param_kernel, dim3(div_up(total, 256)), dim3(256), 0, s, theta, z1, z2, dz1, dz2, dpsi,
                      B, d_in, hidden, K, dparams);

@@ -135,6 +135,21 @@ def make_targets(cams: list, seed: int = 3) -> list:
     return [rng.uniform(0.0, 1.0, size=(3, c.height, c.width)).astype(np.float32) for c in cams]
 
 
+def perturb_scene(bases: np.ndarray, seed: int = 6, pos_std: float = 2e-3, rot_std: float = 0.05,
+                  logscale_std: float = 0.1, logit_std: float = 0.3, rgb_std: float = 0.05) -> np.ndarray:
+    """A starting point for fitting: the base model of `bases` with Gaussian
+    noise on every attribute (deltas unchanged)."""
+    rng = np.random.default_rng(seed)
+    out = bases.astype(np.float64).copy()
+    N = bases.shape[1]
+    out[0, :, 0:3] += rng.normal(0.0, pos_std, size=(N, 3))
+    out[0, :, 3:7] += rng.normal(0.0, rot_std, size=(N, 4))
+    out[0, :, 7:10] += rng.normal(0.0, logscale_std, size=(N, 3))
+    out[0, :, 10] += rng.normal(0.0, logit_std, size=N)
+    out[0, :, 11:14] += rng.normal(0.0, rgb_std, size=(N, 3))
+    return out.astype(np.float32)
+
+
 def make_request_stream(n: int, rate_per_s: float, n_avatars: int, seed: int = 4):
     """Poisson arrivals: (arrival times in s, avatar ids, tracking vectors, yaw degrees)."""
     rng = np.random.default_rng(seed)

@@ -109,6 +109,27 @@ class Trainer:
         if self.graph is not None:
             gbr.gbr_stage_frames(self.ctx, self.offsets, self.cams)
 
+    def render_targets(self) -> None:
+        """Targets = this model's own renders of the current batch (used to make
+        a ground-truth avatar's frames the training targets)."""
+        c, cfg = self.ctx, self.cfg
+        with self.torch.cuda.stream(self.stream):
+            gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
+            gbr.gbr_blend(c, self.bases, self.psi, self.raw)
+            gbr.gbr_render(c, self.raw, self.offsets, self.cams, self.targets)
+            st = gbr.gbr_query_status(c, self.stream)
+        if st.overflow:
+            gbr.gbr_reserve(c, st.entries + st.entries // 4 + 4096)
+            self.render_targets()
+
+    def load_bases(self, bases: np.ndarray) -> None:
+        """Replace the blendshape bases (Adam state restarts)."""
+        self.torch.cuda.synchronize()
+        self.bases.copy_(self.torch.from_numpy(np.ascontiguousarray(bases, dtype=np.float32)))
+        self.bases_m.zero_()
+        self.bases_v.zero_()
+        self.torch.cuda.synchronize()
+
     # ---------------------------------------------------------------- one step
     def enqueue_step(self) -> None:
         """Every kernel of one batched optimisation step, enqueued on the trainer's stream."""
