@@ -35,12 +35,18 @@ METRIC = "train img/s (fwd+bwd, 50k Gaussians, 512²) batched vs per-frame; serv
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # 256 CU x 2.4 GHz x 256 FLOP/clk (packed dual FMA)
 
-# Algorithmic work per unit, see DESIGN.md ("Measurement"):
-#  composite forward: FP32 operations per contributing (pixel, Gaussian) pair
-#  composite backward: FP32 operations per contributing pair, excluding the
-#  cross-lane reduction (not algorithmic)
-FWD_FLOP_PER_PAIR = 21
-BWD_FLOP_PER_PAIR = 58
+# Algorithmic work per contributing (pixel, Gaussian) pair, FP32 operations
+# with a fused multiply-add counted as 2:
+#  forward: alpha = o * exp(-q/2) with q the conic quadratic form of the
+#   offset (12), clamp, 1 - alpha, T (1 - alpha), alpha T (4), colour
+#   accumulation (6)  -> 22
+#  backward: alpha recomputed (12), T_i recovered (2), w_i = alpha_i T_i (1),
+#   dL/dc (3), residual colour update (6), <g, c> and <g, R> (10), dL/dalpha
+#   (3), dL/do and dL/dq (3), conic gradient (9), mean gradient (10) -> 59
+#  (the cross-lane reduction over a tile's pixels is not counted)
+WORKLOAD_TAG = "train_n50k_k20_b16_512"      # names the profiles/ summaries of this workload
+FWD_FLOP_PER_PAIR = 22
+BWD_FLOP_PER_PAIR = 59
 
 
 def parse():
@@ -57,6 +63,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="few steps, no per-frame/CPU legs (for profilers)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB on the device (a known-size "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -164,12 +173,12 @@ def main():
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "work_per_launch": f"{entries} entries x {per_entry} B", "avg_ms": round(dom_avg, 4)}
-    prof = os.path.join(ROOT, "profiles", f"{dominant}_traffic.json")
+    prof = os.path.join(ROOT, "profiles", f"{dominant}_{WORKLOAD_TAG}.traffic.json")
     roof["traffic"] = None
     if os.path.exists(prof):
         meta = json.load(open(prof))
-        if meta.get("source_hash") == source_hash(meta.get("sources", [])):
-            roof["traffic"] = meta.get("bytes_per_launch")
+        if meta.get("sources") and meta.get("source_hash") == source_hash(meta["sources"]):
+            roof["traffic"] = round(meta["bytes_per_launch"])
     out["roofline"] = roof
 
     # per-frame scheme on the same GPU
@@ -192,6 +201,15 @@ def main():
                             "ms_per_frame": round(1e3 / pf, 4), "batched_over_per_frame": round(value / pf, 3)}
 
     tr.close()
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     if not args.quick and not args.no_serve:
         out["serve"] = serve_leg(args.serve_seconds)

@@ -203,8 +203,10 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
 
 /* Copy an internal buffer of the last pass to host memory (synchronises).
    what: 1 splat records [S][12] f32 (mx, my, ca, cb, cc, opacity, r, g, b,
-   depth, -, -; ca, cb, cc = -log2(e) * (A/2, B, C/2) of the conic
-   q = A dx^2 + 2B dx dy + C dy^2), 2 tile rects [S][4] i32 (inclusive
+   depth, pixel box x, pixel box y; ca, cb, cc = -log2(e) * (A/2, B, C/2)
+   of the conic q = A dx^2 + 2B dx dy + C dy^2; the two pixel-box slots hold
+   the bits of u32 values x0 | x1 << 16 and y0 | y1 << 16, the inclusive
+   pixel range of the alpha >= 1/255 support), 2 tile rects [S][4] i32 (inclusive
    tx0, ty0, tx1, ty1), 3 tile starts [tiles+1] u32 (tile g's entries are
    [start[g], start[g+1]) of the sorted list), 4 sorted entries [entries] u32
    (global splat index),

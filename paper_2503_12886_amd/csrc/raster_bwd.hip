@@ -39,15 +39,68 @@ __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, f
 // slot, only if some pixel contributed; a byte flag marks it.
 constexpr int kSparseLanes = 4;
 
+// Folds one entry into a lane's back-to-front state (transmittance in front
+// of the entry, colour behind it) and returns its partial in acc.  Lanes
+// whose pixel did not take the entry add exact zeros and keep their state.
+template <int PX>
+__device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, const float cbl, const uint32_t li,
+                                           const float* pxf, const float* pyf, const uint32_t* nit, float* T_,
+                                           float* R0, float* R1, float* R2, const float* G0, const float* G1,
+                                           const float* G2, float* acc, bool& any) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+  any = false;
+#pragma unroll
+  for (int p = 0; p < PX; ++p) {
+    float dx, dy, pwr, g2;
+    const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr, g2);
+    const bool take = li < nit[p] && a0 >= kAlphaMin;
+    any = any || take;
+    const float al = fminf(a0, kAlphaMax);
+    const float inv = __builtin_amdgcn_rcpf(1.0f - al);
+    const float Ti = T_[p] * inv;                     // transmittance in front of this entry
+    const float wgt = take ? al * Ti : 0.0f;
+    acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
+    const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];
+    const float rg = R0[p] * G0[p] + R1[p] * G1[p] + R2[p] * G2[p];
+    const float dal = Ti * cg - rg * inv;             // d out / d alpha
+    R0[p] += wgt * r1.z; R1[p] += wgt * r1.w; R2[p] += wgt * cbl;
+    T_[p] = take ? Ti : T_[p];
+    // min(0.99, .) passes the gradient only below the clamp
+    const float da = (take && a0 < kAlphaMax) ? dal : 0.0f;
+    acc[5] += g2 * da;
+    const float dpw = (pwr > 0.0f) ? 0.0f : da * a0 * (float)kLn2;
+    acc[2] += dpw * dx * dx;
+    acc[3] += dpw * dx * dy;
+    acc[4] += dpw * dy * dy;
+    acc[0] -= dpw * (2.0f * r0.z * dx + r0.w * dy);
+    acc[1] -= dpw * (r0.w * dx + 2.0f * r1.x * dy);
+  }
+}
+
+// Lane-order sum of the (at most kSparseLanes) lanes in `who`, wave-uniform.
+__device__ __forceinline__ void sparse_sum(const float* acc, unsigned long long who, float* sum) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) sum[c] = 0.0f;
+  while (who) {
+    const int l = __ffsll((long long)who) - 1;
+    who &= who - 1ull;
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+      sum[c] += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc[c]), l));
+  }
+}
+
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
   using S = TileShapeB<T>;
+  constexpr int U = 2;                      // entries folded per step (independent alphas)
   __shared__ float4 s0[CHUNK];
   __shared__ float4 s1[CHUNK];
   __shared__ float s2[CHUNK];
   __shared__ float red[CHUNK][S::NW][9];
-  __shared__ uint8_t wany[CHUNK][S::NW];
+  __shared__ uint32_t wany[CHUNK];         // byte w: wave w wrote red[i][w]
   __shared__ uint8_t cm[CHUNK];
   __shared__ uint32_t sid[CHUNK];
   if (a.status->overflow) return;
@@ -81,6 +134,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
       R0[p] = T_[p] * F.bg[0]; R1[p] = T_[p] * F.bg[1]; R2[p] = T_[p] * F.bg[2];
     }
   }
+  uint8_t* wany8 = reinterpret_cast<uint8_t*>(wany);
   for (int ce = (int)L; ce > 0; ce -= CHUNK) {
     const int cbeg = max(0, ce - CHUNK);
     const int n = ce - cbeg;
@@ -91,103 +145,88 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
       s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
       cm[i] = a.cmask[start + cbeg + i];
       sid[i] = sp;
+      wany[i] = 0u;
     }
     __syncthreads();
-    for (int i = n - 1; i >= 0; --i) {
-      // the forward pass recorded whether any pixel of this wave took the entry
-      if (!((__builtin_amdgcn_readfirstlane((int)cm[i]) >> w) & 1)) {
-        if (lane == 0) wany[i][w] = 0;
-        continue;
-      }
-      const uint32_t li = (uint32_t)(cbeg + i);
-      const float4 r0 = s0[i], r1 = s1[i];
-      const float cbl = s2[i];
-      float acc[9];
+    // Entries this wave's pixels took in the forward pass (its contribution
+    // mask bit), visited back to front in pairs.
+    for (int gb = (n - 1) & ~63; gb >= 0; gb -= 64) {
+      const int idx = gb + lane;
+      unsigned long long m = __ballot(idx < n && ((cm[idx] >> w) & 1));
+      while (m) {
+        int e[U];
+        int cnt = 0;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-      bool any = false;
-#pragma unroll
-      for (int p = 0; p < S::PX; ++p) {
-        // branch-free: lanes whose pixel does not take this entry add exact zeros
-        float dx, dy, pwr, g2;
-        const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr, g2);
-        const bool take = li < nit[p] && a0 >= kAlphaMin;
-        any = any || take;
-        const float al = fminf(a0, kAlphaMax);
-        const float inv = __builtin_amdgcn_rcpf(1.0f - al);
-        const float Ti = T_[p] * inv;                     // transmittance in front of this entry
-        const float wgt = take ? al * Ti : 0.0f;
-        acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
-        const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];
-        const float rg = R0[p] * G0[p] + R1[p] * G1[p] + R2[p] * G2[p];
-        const float dal = Ti * cg - rg * inv;             // d out / d alpha
-        R0[p] += wgt * r1.z; R1[p] += wgt * r1.w; R2[p] += wgt * cbl;
-        T_[p] = take ? Ti : T_[p];
-        // min(0.99, .) passes the gradient only below the clamp
-        const float da = (take && a0 < kAlphaMax) ? dal : 0.0f;
-        acc[5] += g2 * da;
-        const float dpw = (pwr > 0.0f) ? 0.0f : da * a0 * (float)kLn2;
-        acc[2] += dpw * dx * dx;
-        acc[3] += dpw * dx * dy;
-        acc[4] += dpw * dy * dy;
-        acc[0] -= dpw * (2.0f * r0.z * dx + r0.w * dy);
-        acc[1] -= dpw * (r0.w * dx + 2.0f * r1.x * dy);
-      }
-      const unsigned long long who = __ballot(any);
-      if (who == 0ull) {
-        if (lane == 0) wany[i][w] = 0;
-        continue;
-      }
-      if (__popcll(who) <= kSparseLanes) {
-        float sum[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) sum[c] = 0.0f;
-        unsigned long long m = who;
-        while (m) {
-          const int l = __ffsll((long long)m) - 1;
-          m &= m - 1ull;
-#pragma unroll
-          for (int c = 0; c < 9; ++c)
-            sum[c] += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc[c]), l));
+        for (int u = 0; u < U; ++u) {
+          e[u] = -1;
+          if (m) {
+            const int hb = 63 - __clzll((long long)m);
+            m &= ~(1ull << hb);
+            e[u] = gb + hb;
+            ++cnt;
+          }
         }
-        if (lane == 0) {
+        float acc[U][9];
+        bool any[U];
+        unsigned long long who[U];
 #pragma unroll
-          for (int c = 0; c < 9; ++c) red[i][w][c] = sum[c];
-          wany[i][w] = 1;
+        for (int u = 0; u < U; ++u) {
+          // an absent second entry is folded as an untaken one (zeros, state kept)
+          const int i = e[u] < 0 ? e[0] : e[u];
+          const uint32_t li = e[u] < 0 ? 0xffffffffu : (uint32_t)(cbeg + i);
+          entry_grad<S::PX>(s0[i], s1[i], s2[i], li, pxf, pyf, nit, T_, R0, R1, R2, G0, G1, G2, acc[u], any[u]);
+          who[u] = __ballot(any[u]);
         }
-      } else {
+        bool dense = false;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) acc[c] = wave_sum_to63(acc[c]);
-        if (lane == 63) {
+        for (int u = 0; u < U; ++u) dense = dense || __popcll(who[u]) > kSparseLanes;
+        float dsum[U][9];
+        if (dense) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) red[i][w][c] = acc[c];
-          wany[i][w] = 1;
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) dsum[u][c] = wave_sum_to63(acc[u][c]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (u >= cnt || who[u] == 0ull) continue;
+          if (__popcll(who[u]) <= kSparseLanes) {
+            float sum[9];
+            sparse_sum(acc[u], who[u], sum);
+            if (lane == 0) {
+#pragma unroll
+              for (int c = 0; c < 9; ++c) red[e[u]][w][c] = sum[c];
+              wany8[e[u] * 4 + w] = 1;
+            }
+          } else if (lane == 63) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) red[e[u]][w][c] = dsum[u][c];
+            wany8[e[u] * 4 + w] = 1;
+          }
         }
       }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += S::NT) {
-      bool hit = false;
+      const uint32_t wa = wany[i];
+      if (wa == 0u) continue;
       float v[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) v[c] = 0.0f;
 #pragma unroll
       for (int ww = 0; ww < S::NW; ++ww) {
-        if (!wany[i][ww]) continue;
-        hit = true;
+        if (!((wa >> (8 * ww)) & 0xffu)) continue;
 #pragma unroll
         for (int c = 0; c < 9; ++c) v[c] += red[i][ww][c];
       }
-      if (hit) {
-        // emission slot: the splat's offset + row-major index of this tile in its rect
-        const uint32_t sp = sid[i];
-        const int4 r = a.rect[sp];
-        const uint32_t e = a.soff[sp] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
-        float* dst = a.part + (int64_t)e * 9;
+      // emission slot: the splat's offset + row-major index of this tile in its rect
+      const uint32_t sp = sid[i];
+      const int4 r = a.rect[sp];
+      const uint32_t e = a.soff[sp] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
+      float* dst = a.part + (int64_t)e * 9;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) dst[c] = v[c];
-        a.part_flag[e] = 1;
-      }
+      for (int c = 0; c < 9; ++c) dst[c] = v[c];
+      a.part_flag[e] = 1;
     }
   }
 }

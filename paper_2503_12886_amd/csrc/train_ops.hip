@@ -10,25 +10,28 @@ namespace gbr {
 // weight rows are staged in LDS once, each thread forms one (frame, unit) dot
 // product in input order.  The ReLU of the previous layer is applied when its
 // stored pre-activation is read.
-constexpr int kRowsPerBlock = 16;
+constexpr int kRowsPerBlock = 8;
 constexpr int kMlpMaxIn = 1024;
 
 __global__ __launch_bounds__(1024) void dense_fwd_kernel(const float* __restrict__ W, const float* __restrict__ bias,
                                                          const float* __restrict__ in, int relu_in, int B, int n_in,
                                                          int n_out, float* __restrict__ out) {
-  __shared__ float w[kRowsPerBlock * kMlpMaxIn];
+  __shared__ float w[kRowsPerBlock * (kMlpMaxIn + 1)];
+  const int ld = n_in | 1;   // odd row stride: the rows a wave reads at once sit in different LDS banks
   const int j0 = blockIdx.x * kRowsPerBlock;
   const int rows = min(kRowsPerBlock, n_out - j0);
-  for (int t = threadIdx.x; t < rows * n_in; t += blockDim.x) w[t] = W[(int64_t)j0 * n_in + t];
+  for (int t = threadIdx.x; t < rows * n_in; t += blockDim.x) w[(t / n_in) * ld + t % n_in] = W[(int64_t)j0 * n_in + t];
   __syncthreads();
   for (int q = threadIdx.x; q < B * rows; q += blockDim.x) {
     const int b = q / rows, jj = q % rows;
     const float* x = in + (int64_t)b * n_in;
-    const float* wr = w + jj * n_in;
+    const float* wr = w + jj * ld;
     float s = 0.0f;
     if (relu_in) {
+#pragma unroll 8
       for (int i = 0; i < n_in; ++i) s = __builtin_fmaf(wr[i], fmaxf(x[i], 0.0f), s);
     } else {
+#pragma unroll 8
       for (int i = 0; i < n_in; ++i) s = __builtin_fmaf(wr[i], x[i], s);
     }
     out[(int64_t)b * n_out + j0 + jj] = s + bias[j0 + jj];
@@ -44,7 +47,7 @@ void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, in
   const float* b2 = W2 + (int64_t)hidden * hidden;
   const float* W3 = b2 + hidden;
   const float* b3 = W3 + (int64_t)K * hidden;
-  const int thr = std::min(1024, std::max(64, ((B * kRowsPerBlock + 63) / 64) * 64));
+  const int thr = std::min(1024, std::max(64, ((B * kRowsPerBlock + 63) / 64) * 64));   // one thread per (frame, row)
   hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(hidden, kRowsPerBlock)), dim3(thr), 0, s, W1, b1, theta, 0, B,
                      d_in, hidden, z1);
   hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(hidden, kRowsPerBlock)), dim3(thr), 0, s, W2, b2, z1, 1, B,
@@ -54,18 +57,34 @@ void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, in
 }
 
 // ---------------------------------------------------------------- MLP backward
-// dz2 = (W3^T dpsi) * [z2 > 0], dz1 = (W2^T dz2) * [z1 > 0]: one thread per
-// (frame, unit), reading a weight column (coalesced across threads); then one
-// thread per parameter sums over the frames in frame order.
-__global__ __launch_bounds__(256) void dense_bwd_act_kernel(const float* __restrict__ W,
-                                                            const float* __restrict__ g, const float* __restrict__ z,
-                                                            int B, int n_g, int n_x, float* __restrict__ dz) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= B * n_x) return;
-  const int b = q / n_x, i = q % n_x;
+// dz2 = (W3^T dpsi) * [z2 > 0], dz1 = (W2^T dz2) * [z1 > 0].  A block owns 64
+// units of one frame (a lane per unit, weight rows read coalesced); its 8
+// waves each sum an eighth of the contraction, and the eighths are added in
+// wave order.  Then one thread per parameter sums over the frames in frame
+// order.
+constexpr int kActSplit = 8;
+
+__global__ __launch_bounds__(64 * kActSplit) void dense_bwd_act_kernel(const float* __restrict__ W,
+                                                                       const float* __restrict__ g,
+                                                                       const float* __restrict__ z, int B, int n_g,
+                                                                       int n_x, float* __restrict__ dz) {
+  __shared__ float part[kActSplit][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int b = blockIdx.y;
+  const int per = (n_g + kActSplit - 1) / kActSplit;
+  const int k0 = w * per, k1 = min(n_g, k0 + per);
   float s = 0.0f;
-  for (int k = 0; k < n_g; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[(int64_t)b * n_g + k], s);
-  dz[q] = z[q] > 0.0f ? s : 0.0f;
+  if (i < n_x)
+    for (int k = k0; k < k1; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[(int64_t)b * n_g + k], s);
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < n_x) {
+    float t = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kActSplit; ++q) t += part[q][lane];
+    dz[(int64_t)b * n_x + i] = z[(int64_t)b * n_x + i] > 0.0f ? t : 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restrict__ theta,
@@ -108,10 +127,9 @@ void launch_mlp_bwd(const float* params, const float* theta, const float* z1, co
   if (B == 0) return;
   const float* W2 = params + (int64_t)hidden * d_in + hidden;
   const float* W3 = W2 + (int64_t)hidden * hidden + hidden;
-  hipLaunchKernelGGL(dense_bwd_act_kernel, dim3(div_up((int64_t)B * hidden, 256)), dim3(256), 0, s, W3, dpsi, z2, B,
-                     K, hidden, dz2);
-  hipLaunchKernelGGL(dense_bwd_act_kernel, dim3(div_up((int64_t)B * hidden, 256)), dim3(256), 0, s, W2, dz2, z1, B,
-                     hidden, hidden, dz1);
+  const dim3 ga(div_up(hidden, 64), B);
+  hipLaunchKernelGGL(dense_bwd_act_kernel, ga, dim3(64 * kActSplit), 0, s, W3, dpsi, z2, B, K, hidden, dz2);
+  hipLaunchKernelGGL(dense_bwd_act_kernel, ga, dim3(64 * kActSplit), 0, s, W2, dz2, z1, B, hidden, hidden, dz1);
   const int64_t total = (int64_t)hidden * d_in + hidden + (int64_t)hidden * hidden + hidden + (int64_t)K * hidden + K;
   hipLaunchKernelGGL(mlp_bwd_param_kernel, dim3(div_up(total, 256)), dim3(256), 0, s, theta, z1, z2, dz1, dz2, dpsi,
                      B, d_in, hidden, K, dparams);
