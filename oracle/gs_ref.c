@@ -29,6 +29,7 @@
  *
  * Compile with -ffp-contract=off so that the arithmetic is what is written.
  */
+#define _GNU_SOURCE   /* qsort_r */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -175,10 +176,12 @@ int oracle_project(int64_t N, const double* raw, const double* camd, int W, int 
 }
 
 /* ---- depth order ------------------------------------------------------------- */
-static const proj_t* g_sort_proj;
-static int cmp_depth(const void* a, const void* b) {
+/* The projections are passed to the comparator as qsort_r's context, so
+   concurrent calls (one frame per thread) do not share any state. */
+static int cmp_depth(const void* a, const void* b, void* ctx) {
+  const proj_t* P = (const proj_t*)ctx;
   int64_t i = *(const int64_t*)a, j = *(const int64_t*)b;
-  float ki = g_sort_proj[i].key, kj = g_sort_proj[j].key;
+  float ki = P[i].key, kj = P[j].key;
   if (ki < kj) return -1;
   if (ki > kj) return 1;
   return (i < j) ? -1 : (i > j);
@@ -253,8 +256,7 @@ static int scene_build(int64_t N, const double* raw, const cam_t* cam, int W, in
     project_one(raw + NF * n, cam, W, H, &s->P[n]);
     if (s->P[n].valid) s->order[s->nvalid++] = n;
   }
-  g_sort_proj = s->P;
-  qsort(s->order, (size_t)s->nvalid, sizeof(int64_t), cmp_depth);
+  qsort_r(s->order, (size_t)s->nvalid, sizeof(int64_t), cmp_depth, s->P);
   s->nbx = (W + OB - 1) / OB; s->nby = (H + OB - 1) / OB;
   s->blocks = (list_t*)calloc((size_t)s->nbx * s->nby, sizeof(list_t));
   if (!s->blocks) return -1;

@@ -1,0 +1,250 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times, against the float64 reference:
+
+* training batch (N=50,000, K=20, B=16 frames of 512x512, MLP, L1 loss, one
+  graph-captured step, tile 16 / chunk 128): every frame's image, the whole
+  batch's tile lists and depth order bit-exact, and the step's gradients to
+  the bases, the weights and the MLP;
+* adjoint on a random subset (N=100,000, K=20, B=32 at 512x512): fp32 GPU
+  gradients of the bases on a 1 % random subset of the base entries, and all
+  weight gradients, against the float64 adjoint;
+* uneven batch (N=100,000, K=20, B=64 frames of 256/384/512 px squares,
+  camera distance U[0.4, 0.7], one pass): sampled frames' images and tile
+  lists, and the autotuner's pick rendering bit-identical images.
+
+The reference renders frames in parallel threads (its C functions release
+the interpreter lock); everything it is given comes from the seeded
+generators or from the GPU's own float32 inputs to the checked stage."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import blendshape as bs
+from oracle import raster
+from paper_2503_12886_amd import gbr, synth
+from gpu_util import IMAGE_TOL, compare_image, dev, grad_check, host, make_ctx, split_images
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def pmap(fn, items):
+    with ThreadPoolExecutor(WORKERS) as ex:
+        return list(ex.map(fn, items))
+
+
+def mlp_unpack(flat, d_in, hidden, K):
+    p, o = {}, 0
+    for name, shape in (("W1", (hidden, d_in)), ("b1", (hidden,)), ("W2", (hidden, hidden)), ("b2", (hidden,)),
+                        ("W3", (K, hidden)), ("b3", (K,))):
+        n = int(np.prod(shape))
+        p[name] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    assert o == len(flat)
+    return p
+
+
+def frame_ref(args):
+    """Reference image and ambiguity flags of one frame."""
+    raw_b, cam = args
+    ref, _, _, fl = raster.render(raw_b, cam)
+    return ref, fl
+
+
+def frame_adjoint(args):
+    raw_b, cam, dimg_b = args
+    return raster.render_grad(raw_b, cam, dimg_b)[0]
+
+
+def masked(dimg, flags):
+    """The image gradient with the pixels whose threshold decisions are
+    ambiguous between float32 and float64 set to zero: each pixel's
+    contribution to the adjoint is its own, so the rest must then agree
+    entry by entry."""
+    return [np.where(f[None] == 0, d, 0.0).astype(np.float32) for d, f in zip(dimg, flags)]
+
+
+def check_tile_lists(ctx, raw, cams, N, tile, frames):
+    """The GPU's per-tile lists of the given frames equal the reference's,
+    entry by entry (global splat index = frame * N + Gaussian)."""
+    ntiles = [((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams]
+    tile_base = np.concatenate([[0], np.cumsum(ntiles)])
+    ts = gbr.gbr_inspect(ctx, "tile_start", int(tile_base[-1]) + 1).astype(np.int64)
+    srt = gbr.gbr_inspect(ctx, "sorted", int(ts[-1])).astype(np.int64)
+    for b in frames:
+        proj = raster.project(raw[b], cams[b])
+        ranges, sf, sg, _ = raster.bin_and_sort([proj], [cams[b]], tile)
+        seg = ts[tile_base[b]:tile_base[b + 1] + 1]
+        assert np.array_equal(seg[:-1] - seg[0], ranges[:, 0]), b
+        assert np.array_equal(seg[1:] - seg[0], ranges[:, 1]), b
+        assert np.array_equal(srt[seg[0]:seg[-1]], b * N + sg), b
+
+
+def test_training_step_full_size():
+    import torch
+    import bench
+    from paper_2503_12886_amd.trainer import Trainer
+    cfg, bases, mlp, theta, cams, targets = bench.make_workload()
+    tr = Trainer(cfg, bases, mlp)
+    tr.set_batch(theta, targets, cams)
+    tr.render_targets()
+    tr.load_bases(synth.perturb_scene(bases))
+    tr.step()                                   # warm-up: sizes the tile-entry buffers
+    torch.cuda.synchronize()
+    bases0 = host(tr.bases).astype(np.float64)
+    mlp0 = host(tr.mlp)
+    tr.capture()
+    st = tr.step()                              # the timed configuration: one graph replay
+    assert not st.overflow
+    torch.cuda.synchronize()
+    B, N, K = cfg.B, cfg.N, cfg.K
+    raw = host(tr.raw).reshape(B, N, 16)
+    images = split_images(host(tr.images), cams)
+    dimg = split_images(host(tr.dimages), cams)
+    tgt = split_images(host(tr.targets), cams)
+
+    # MLP and blend (Eq. 2, Eq. 1)
+    params = mlp_unpack(mlp0, cfg.d_in, cfg.hidden, K)
+    psi_ref, cache = bs.mlp_forward(params, theta.astype(np.float32).astype(np.float64))
+    psi = host(tr.psi)
+    assert np.abs(psi - psi_ref).max() <= 1e-5 * max(1.0, np.abs(psi_ref).max())
+    raw_ref = bs.blend(bases0, psi.astype(np.float64))
+    ulp = np.abs(raw.view(np.int32).astype(np.int64) - raw_ref.astype(np.float32).view(np.int32))
+    assert ulp.max() <= 1
+
+    # L1 loss gradient (Sec. 3.2): sign(image - target) / number of values
+    n = sum(i.size for i in images)
+    for b in range(B):
+        assert np.array_equal(dimg[b], (np.sign(images[b] - tgt[b]) / np.float32(n)).astype(np.float32)), b
+
+    # images, all frames
+    res = pmap(frame_ref, [(raw[b], cams[b]) for b in range(B)])
+    flags = [r[1] for r in res]
+    for b, (ref, fl) in enumerate(res):
+        err, frac = compare_image(images[b], ref, fl)
+        assert err <= IMAGE_TOL and frac < 0.01, (b, err, frac)
+
+    # the step's gradients (graph replay) against the adjoint of its own image gradient
+    psi64 = psi.astype(np.float64)
+    draw = np.stack(pmap(frame_adjoint, [(raw[b], cams[b], dimg[b]) for b in range(B)]))
+    dbases_ref, dpsi_ref = bs.blend_adjoint(draw, bases0, psi64)
+    rel, _ = grad_check(host(tr.dbases)[..., :14], dbases_ref[..., :14])
+    assert rel <= 1e-3, rel
+    rel, _ = grad_check(host(tr.dpsi), dpsi_ref)
+    assert rel <= 1e-3, rel
+    g = bs.mlp_backward(params, cache, host(tr.dpsi).astype(np.float64))
+    dmlp_ref = np.concatenate([g[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    rel, _ = grad_check(host(tr.dmlp), dmlp_ref)
+    assert rel <= 1e-3, rel
+
+    # entry by entry, with the ambiguous pixels' image gradient set to zero on both sides
+    dm = masked(dimg, flags)
+    dB = torch.empty_like(tr.bases)
+    dpsi_m = torch.empty_like(tr.psi)
+    gbr.gbr_backward(tr.ctx, dev(np.concatenate([d.ravel() for d in dm])), dev(bases0.astype(np.float32)), tr.psi,
+                     dB, dpsi_m)
+    torch.cuda.synchronize()
+    draw = np.stack(pmap(frame_adjoint, [(raw[b], cams[b], dm[b]) for b in range(B)]))
+    dbases_ref, dpsi_ref = bs.blend_adjoint(draw, bases0, psi64)
+    rows = lambda a: np.transpose(a[..., :14], (1, 0, 2)).reshape(N, -1)
+    rel, worst = grad_check(rows(host(dB)), rows(dbases_ref))
+    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+    rel, worst = grad_check(host(dpsi_m), dpsi_ref)
+    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+
+    # tile lists and depth order of the whole batch, bit for bit
+    check_tile_lists(tr.ctx, raw, cams, N, cfg.tile, range(B))
+    tr.close()
+
+
+def test_adjoint_random_subset_full_size():
+    import torch
+    B, N, K = 32, 100_000, 20
+    bases = synth.make_scene(N, K, seed=11)
+    w = synth.make_weights(B, K, seed=12)
+    cams = synth.make_cameras(B, 512, 512, seed=13)
+    rng = np.random.default_rng(14)
+    dimg = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    ctx = make_ctx(max_frames=B, max_splats=B * N, max_pixels=B * 512 * 512, max_entries=40 * B * N)
+    Bt, Wt = dev(bases), dev(w)
+    raw_t = torch.empty(B, N, 16, device="cuda")
+    images = torch.empty(gbr.image_numel(cams), device="cuda")
+    gbr.gbr_blend(ctx, Bt, Wt, raw_t)
+    gbr.gbr_render(ctx, raw_t, [b * N for b in range(B + 1)], cams, images)
+    assert not gbr.gbr_query_status(ctx).overflow
+    torch.cuda.synchronize()
+    raw = host(raw_t)
+    imgs = split_images(host(images), cams)
+    res = pmap(frame_ref, [(raw[b], cams[b]) for b in range(B)])
+    for b, (ref, fl) in enumerate(res):
+        err, frac = compare_image(imgs[b], ref, fl)
+        assert err <= IMAGE_TOL and frac < 0.01, (b, err, frac)
+    dm = masked(dimg, [r[1] for r in res])
+    dB = torch.empty_like(Bt)
+    dW = torch.empty_like(Wt)
+    gbr.gbr_backward(ctx, dev(np.concatenate([d.ravel() for d in dm])), Bt, Wt, dB, dW)
+    torch.cuda.synchronize()
+    draw = np.stack(pmap(frame_adjoint, [(raw[b], cams[b], dm[b]) for b in range(B)]))
+    dbases_ref, dw_ref = bs.blend_adjoint(draw, bases.astype(np.float64), w.astype(np.float64))
+    del draw
+    # a 1 % random subset of the base entries (14 live features of every slice), entry by entry
+    got = host(dB)[..., :14].ravel()
+    ref = dbases_ref[..., :14].ravel()
+    pick = rng.choice(got.size, size=got.size // 100, replace=False)
+    rel, worst = grad_check(got[pick][:, None], ref[pick][:, None])
+    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+    rel, worst = grad_check(host(dW), dw_ref)
+    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+    ctx.close()
+
+
+def test_uneven_batch_full_size_and_autotune():
+    import torch
+    B, N, K = 64, 100_000, 20
+    bases = synth.make_scene(N, K, seed=21)
+    w = synth.make_weights(B, K, seed=22)
+    cams = synth.make_cameras(B, seed=23, resolutions=[(256, 256), (384, 384), (512, 512)], dist=(0.4, 0.7))
+    npx = sum(c.width * c.height for c in cams)
+    ctx = make_ctx(max_frames=B, max_splats=B * N, max_pixels=npx, max_entries=30 * B * N)
+    Bt, Wt = dev(bases), dev(w)
+    raw_t = torch.empty(B, N, 16, device="cuda")
+    gbr.gbr_blend(ctx, Bt, Wt, raw_t)
+    offs = [b * N for b in range(B + 1)]
+    images = torch.empty(gbr.image_numel(cams), device="cuda")
+    gbr.gbr_render(ctx, raw_t, offs, cams, images)
+    st = gbr.gbr_query_status(ctx)
+    if st.overflow:
+        gbr.gbr_reserve(ctx, st.entries + st.entries // 4)
+        gbr.gbr_render(ctx, raw_t, offs, cams, images)
+        assert not gbr.gbr_query_status(ctx).overflow
+    torch.cuda.synchronize()
+    raw = host(raw_t)
+    imgs = split_images(host(images), cams)
+    # two frames of each resolution
+    by_res = {}
+    for b, c in enumerate(cams):
+        by_res.setdefault(c.width, []).append(b)
+    sample = sorted(b for v in by_res.values() for b in v[:2])
+    assert len(by_res) == 3
+    res = pmap(frame_ref, [(raw[b], cams[b]) for b in sample])
+    for b, (ref, fl) in zip(sample, res):
+        err, frac = compare_image(imgs[b], ref, fl)
+        assert err <= IMAGE_TOL and frac < 0.01, (b, err, frac)
+    check_tile_lists(ctx, raw, cams, N, 16, sample)
+
+    # autotuner: a valid pick, and its images are the same bits
+    dimages = torch.zeros_like(images)
+    draw = torch.empty_like(raw_t)
+    tile, chunk, times = gbr.gbr_autotune(ctx, raw_t, offs, cams, torch.empty_like(images), dimages, draw)
+    assert tile in (8, 16, 32) and chunk in (64, 128, 256)
+    assert all(t > 0 for t in times)
+    again = torch.empty_like(images)
+    gbr.gbr_render(ctx, raw_t, offs, cams, again)
+    st = gbr.gbr_query_status(ctx)
+    assert not st.overflow
+    torch.cuda.synchronize()
+    assert torch.equal(again, images)
+    ctx.close()
