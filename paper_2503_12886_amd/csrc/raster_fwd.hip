@@ -411,7 +411,32 @@ template <int T> struct TileShape {
   static constexpr int PX = PXW * PXW;
   static constexpr int TPR = T / PXW;               // threads per pixel row
   static constexpr int NW = NT / 64;
+  static constexpr int RW = (64 / TPR) * PXW;       // pixel rows covered by one wave
 };
+
+// Whether a splat's alpha >= 1/255 region may reach the rectangle
+// [x0, x1] x [y0, y1] of pixel centres: the maximum of the concave power
+// ca dx^2 + cb dx dy + cc dy^2 over the rectangle (the mean inside: 0; else
+// the best point of the four edges) against log2(1 / (255 o)), less a margin
+// of 0.01 that keeps the test conservative under float32 rounding (at that
+// margin alpha is 0.7 % below the threshold).  A splat that cannot reach a
+// pixel is never taken there, so skipping it changes nothing.
+__device__ __forceinline__ bool strip_reach(float4 r0, float4 r1, float x0, float x1, float y0, float y1) {
+  const float ca = r0.z, cb = r0.w, cc = r1.x;
+  x0 -= r0.x; x1 -= r0.x; y0 -= r0.y; y1 -= r0.y;
+  if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+  const float kx = -cb / (2.0f * cc), ky = -cb / (2.0f * ca);
+  float best = -INFINITY;
+  {
+    const float ya = fminf(fmaxf(kx * x0, y0), y1), yb = fminf(fmaxf(kx * x1, y0), y1);
+    best = fmaxf(best, ca * x0 * x0 + cb * x0 * ya + cc * ya * ya);
+    best = fmaxf(best, ca * x1 * x1 + cb * x1 * yb + cc * yb * yb);
+    const float xa = fminf(fmaxf(ky * y0, x0), x1), xb = fminf(fmaxf(ky * y1, x0), x1);
+    best = fmaxf(best, ca * xa * xa + cb * xa * y0 + cc * y0 * y0);
+    best = fmaxf(best, ca * xb * xb + cb * xb * y1 + cc * y1 * y1);
+  }
+  return best >= -__log2f(255.0f * r1.y) - 0.01f;
+}
 
 // alpha of a splat at a pixel, bit-identical wherever it is evaluated:
 // power = ca dx^2 + cb dx dy + cc dy^2 (= -q/2 in log2 units), alpha = o 2^power.
@@ -480,49 +505,79 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
     const bool wave_active = __ballot(mine) != 0ull;
     if (lane == 0) wact[w] = wave_active ? 1 : 0;
     if (wave_active) {
-      uint32_t bits = 0;                   // wave-uniform: entries of the current 32 some pixel took
-      for (int i0 = 0; i0 < n; i0 += U) {
-        float4 r0[U], r1[U];
-        float cb2[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) { r0[u] = s0[i0 + u]; r1[u] = s1[i0 + u]; cb2[u] = s2[i0 + u]; }
-        bool took[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) took[u] = false;
-#pragma unroll
-        for (int p = 0; p < S::PX; ++p) {
-          float al[U];
+      // Entries whose alpha >= 1/255 region may reach this wave's pixel rows:
+      // one lane tests one entry against the rectangle of the wave's pixel
+      // centres; the wave then visits only those, in list order, U at a time,
+      // and stops as soon as all its pixels have stopped.
+      const float sx0 = (float)(tx * T) + 0.5f, sx1 = sx0 + (float)(T - 1);
+      const float sy0 = (float)(ty * T + w * S::RW) + 0.5f, sy1 = sy0 + (float)(S::RW - 1);
+      bool live = true;
+      for (int gb = 0; gb < n; gb += 64) {
+        unsigned long long cand = 0ull;
+        if (live) {
+          const int idx = gb + lane;
+          cand = __ballot(idx < n && strip_reach(s0[idx], s1[idx], sx0, sx1, sy0, sy1));
+        }
+        unsigned long long tookm = 0ull;
+        while (cand) {
+          int e[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            float dx, dy, pwr, g2;
-            al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr, g2);
+            e[u] = n + u;                  // padding entry: opacity 0, never taken
+            if (cand) {
+              e[u] = gb + (__ffsll((long long)cand) - 1);
+              cand &= cand - 1ull;
+            }
+          }
+          float4 r0[U], r1[U];
+          float cb2[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) { r0[u] = s0[e[u]]; r1[u] = s1[e[u]]; cb2[u] = s2[e[u]]; }
+          bool took[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) took[u] = false;
+#pragma unroll
+          for (int p = 0; p < S::PX; ++p) {
+            float al[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              float dx, dy, pwr, g2;
+              al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr, g2);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              // branch-free front-to-back step; the arithmetic of a taken entry is
+              // exactly that of the plain loop, an untaken one changes nothing
+              const bool ok = !done[p] && al[u] >= kAlphaMin;
+              const float alc = fminf(al[u], kAlphaMax);
+              const float tn = T_[p] * (1.0f - alc);
+              const bool stop = ok && tn < kTMin;
+              const bool take = ok && !stop;
+              done[p] = done[p] || stop;
+              const float wgt = take ? alc * T_[p] : 0.0f;
+              C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
+              C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
+              C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
+              T_[p] = take ? tn : T_[p];
+              last[p] = take ? (cb - start + (uint32_t)e[u] + 1u) : last[p];
+              ncon[p] += take ? 1u : 0u;
+              took[u] = took[u] || take;
+            }
           }
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            // branch-free front-to-back step; the arithmetic of a taken entry is
-            // exactly that of the plain loop, an untaken one changes nothing
-            const bool ok = !done[p] && (i0 + u < n) && al[u] >= kAlphaMin;
-            const float alc = fminf(al[u], kAlphaMax);
-            const float tn = T_[p] * (1.0f - alc);
-            const bool stop = ok && tn < kTMin;
-            const bool take = ok && !stop;
-            done[p] = done[p] || stop;
-            const float wgt = take ? alc * T_[p] : 0.0f;
-            C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
-            C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
-            C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
-            T_[p] = take ? tn : T_[p];
-            last[p] = take ? (cb - start + (uint32_t)(i0 + u) + 1u) : last[p];
-            ncon[p] += take ? 1u : 0u;
-            took[u] = took[u] || take;
+          for (int u = 0; u < U; ++u)
+            if (__ballot(took[u]) != 0ull) tookm |= 1ull << (e[u] - gb);
+          bool mine_now = false;
+#pragma unroll
+          for (int p = 0; p < S::PX; ++p) mine_now |= !done[p];
+          if (__ballot(mine_now) == 0ull) {
+            live = false;
+            break;
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (__ballot(took[u]) != 0ull) bits |= 1u << ((i0 + u) & 31);
-        if (((i0 + U) & 31) == 0 || i0 + U >= n) {
-          if (lane == 0) wbits[w][i0 >> 5] = bits;
-          bits = 0;
+        if (lane == 0) {
+          wbits[w][gb >> 5] = (uint32_t)tookm;
+          wbits[w][(gb >> 5) + 1] = (uint32_t)(tookm >> 32);
         }
       }
     }
