@@ -122,15 +122,29 @@ __device__ __forceinline__ float dpp_mov(float x) {
       __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK, BANK_MASK, BOUND_CTRL));
 }
 
-// Sum over the 64 lanes of a wave in a fixed order; the total lands in lane 63.
-__device__ __forceinline__ float wave_sum_to63(float v) {
+// Sum over the 16 lanes of each row; each row's total lands in its lane 15
+// (lanes 15, 31, 47, 63).  Out-of-row sources read zero.
+__device__ __forceinline__ float row_sum_to15(float v) {
   v += dpp_mov<0x111, 0xf, 0xf, true>(v);   // row_shr:1
   v += dpp_mov<0x112, 0xf, 0xf, true>(v);   // row_shr:2
-  v += dpp_mov<0x114, 0xf, 0xe, false>(v);  // row_shr:4, banks 1-3
-  v += dpp_mov<0x118, 0xf, 0xc, false>(v);  // row_shr:8, banks 2-3
-  v += dpp_mov<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1, 3
-  v += dpp_mov<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2, 3
+  v += dpp_mov<0x114, 0xf, 0xf, true>(v);   // row_shr:4
+  v += dpp_mov<0x118, 0xf, 0xf, true>(v);   // row_shr:8
   return v;
+}
+
+// Lane swaps of gfx950: after swap32(x, y), x holds (x lanes 0-31, y lanes
+// 0-31) and y holds (x lanes 32-63, y lanes 32-63); after swap16(x, y), by
+// rows of 16 lanes, x holds (x0, y0, x2, y2) and y holds (x1, y1, x3, y3).
+// Adding the two results folds two values into one register at half the
+// lane count each.  Written as inline assembly (both operands are read and
+// written in place) with two wait states on either side.
+__device__ __forceinline__ float fold32(float x, float y) {
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+  return x + y;
+}
+__device__ __forceinline__ float fold16(float x, float y) {
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+  return x + y;
 }
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

@@ -32,12 +32,10 @@ __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, f
 // Per-entry partial, summed over the tile's pixels:
 //   (d mx, d my, d ca, d cb, d cc, d opacity, d r, d g, d b)
 // where ca, cb, cc are the log2-scaled conic coefficients of the record.
-// A wave's sum over its lanes is taken in a fixed order: lane by lane through
-// the scalar unit when at most kSparseLanes lanes contribute (the common
-// case: a splat reaches few pixels of a tile), else a DPP tree.  The block
-// then adds its waves in order and writes the entry's partial, by emission
-// slot, only if some pixel contributed; a byte flag marks it.
-constexpr int kSparseLanes = 4;
+// A wave's sum over its lanes is taken in a fixed order (lane folds, then
+// in-row shifts); the block then adds its waves in order and writes the
+// entry's partial, by emission slot, only if some pixel contributed; a byte
+// flag marks it.
 
 // Folds one entry into a lane's back-to-front state (transmittance in front
 // of the entry, colour behind it) and returns its partial in acc.  Lanes
@@ -75,19 +73,6 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
     acc[4] += dpw * dy * dy;
     acc[0] -= dpw * (2.0f * r0.z * dx + r0.w * dy);
     acc[1] -= dpw * (r0.w * dx + 2.0f * r1.x * dy);
-  }
-}
-
-// Lane-order sum of the (at most kSparseLanes) lanes in `who`, wave-uniform.
-__device__ __forceinline__ void sparse_sum(const float* acc, unsigned long long who, float* sum) {
-#pragma unroll
-  for (int c = 0; c < 9; ++c) sum[c] = 0.0f;
-  while (who) {
-    const int l = __ffsll((long long)who) - 1;
-    who &= who - 1ull;
-#pragma unroll
-    for (int c = 0; c < 9; ++c)
-      sum[c] += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc[c]), l));
   }
 }
 
@@ -177,31 +162,31 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
           entry_grad<S::PX>(s0[i], s1[i], s2[i], li, pxf, pyf, nit, T_, R0, R1, R2, G0, G1, G2, acc[u], any[u]);
           who[u] = __ballot(any[u]);
         }
-        bool dense = false;
+        // Sums of the 2 x 9 partials over the wave's 64 lanes, in a fixed
+        // order: fold lanes 32 apart (value c of both entries into one
+        // register), then 16 apart (two values per register pair), then
+        // four in-row shifts.  Lane 16r + 15 of S[j] ends with value
+        // c = 2j + (r & 1) of entry u = r >> 1.
+        float R[9];
 #pragma unroll
-        for (int u = 0; u < U; ++u) dense = dense || __popcll(who[u]) > kSparseLanes;
-        float dsum[U][9];
-        if (dense) {
+        for (int c = 0; c < 9; ++c) R[c] = fold32(acc[0][c], acc[1][c]);
+        float Sj[5];
 #pragma unroll
-          for (int u = 0; u < U; ++u)
+        for (int j = 0; j < 4; ++j) Sj[j] = fold16(R[2 * j], R[2 * j + 1]);
+        Sj[4] = fold16(R[8], 0.0f);
 #pragma unroll
-            for (int c = 0; c < 9; ++c) dsum[u][c] = wave_sum_to63(acc[u][c]);
-        }
+        for (int j = 0; j < 5; ++j) Sj[j] = row_sum_to15(Sj[j]);
+        if ((lane & 15) == 15) {
+          const int r = lane >> 4, u = r >> 1;
+          const int eu = u ? e[1] : e[0];
+          const unsigned long long wu = u ? who[1] : who[0];
+          if (u < cnt && wu != 0ull) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (u >= cnt || who[u] == 0ull) continue;
-          if (__popcll(who[u]) <= kSparseLanes) {
-            float sum[9];
-            sparse_sum(acc[u], who[u], sum);
-            if (lane == 0) {
-#pragma unroll
-              for (int c = 0; c < 9; ++c) red[e[u]][w][c] = sum[c];
-              wany8[e[u] * 4 + w] = 1;
+            for (int j = 0; j < 5; ++j) {
+              const int c = 2 * j + (r & 1);
+              if (c < 9) red[eu][w][c] = Sj[j];
             }
-          } else if (lane == 63) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) red[e[u]][w][c] = dsum[u][c];
-            wany8[e[u] * 4 + w] = 1;
+            if ((r & 1) == 0) wany8[eu * 4 + w] = 1;
           }
         }
       }
