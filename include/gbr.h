@@ -111,9 +111,11 @@ int gbr_reserve(gbr_ctx* ctx, int64_t max_entries);
 int gbr_set_tiling(gbr_ctx* ctx, int32_t tile, int32_t chunk);
 
 /* Eq. 1.  raw[b] = bases[0] + sum_k weights[b][k-1] * bases[k] for B frames
-   that share one Gaussian set of N.  Accumulates in float64 on the matrix
-   cores and rounds once to float32, so the result does not depend on B.
-   bases [(K+1)][N][16], weights [B][K], raw [B][N][16]. */
+   that share one Gaussian set of N.  Accumulates in float64 in slice order
+   (each float32 x float32 product is exact in float64) and rounds once to
+   float32, so the result does not depend on B.  bases [(K+1)][N][16],
+   weights [B][K] (may be NULL when K = 0), raw [B][N][16] (pads written 0).
+   1 <= B <= 4096, 0 <= K <= 63, N >= 1, else GBR_ERR_INVALID_ARG. */
 int gbr_blend(gbr_ctx* ctx, const float* bases, const float* weights, int32_t B, int32_t K, int64_t N, float* raw,
               void* stream);
 
@@ -139,8 +141,11 @@ int gbr_rasterize(gbr_ctx* ctx, float* images, void* stream);
    floating-point atomics, fixed summation order. */
 int gbr_render_backward(gbr_ctx* ctx, const float* dimages, float* draw, void* stream);
 
-/* Adjoint of gbr_blend.  draw [B][N][16] -> dbases [(K+1)][N][16] and
-   dweights [B][K]; accumulate != 0 adds into the outputs. */
+/* Adjoint of gbr_blend.  draw [B][N][16] -> dbases [(K+1)][N][16] (pads
+   written 0) and dweights [B][K] (the contraction over N*16 runs on the
+   matrix cores with per-wave partials summed in a fixed order);
+   accumulate != 0 adds into the outputs.  1 <= B <= 64, 0 <= K <= 63,
+   B * N within the context's max_splats (GBR_ERR_CAPACITY). */
 int gbr_blend_backward(gbr_ctx* ctx, const float* draw, const float* bases, const float* weights, int32_t B,
                        int32_t K, int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream);
 

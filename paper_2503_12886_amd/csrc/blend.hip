@@ -1,177 +1,187 @@
-// Linear blending of Gaussian blendshapes (Eq. 1) and its adjoint on the
-// gfx950 matrix cores.
+// Linear blending of Gaussian blendshapes (Eq. 1) and its adjoint.
 //
 // Forward:  raw[b][n][f] = sum_{k=0..K} w~[b][k] * bases[k][n][f],  w~[b][0] = 1,
-//           w~[b][k] = weights[b][k-1].  A [16 frames x 4 k] times B [4 k x 16
-//           features of one Gaussian] per v_mfma_f64_16x16x4f64, accumulated in
-//           float64 and rounded to float32 once, so each frame's row is
-//           independent of the batch it is blended in.
-// Adjoint:  dbases[k][n][f] = sum_b w~[b][k] draw[b][n][f]      (contract over B)
+//           w~[b][k] = weights[b][k-1].
+// Adjoint:  dbases[k][n][f] = sum_b w~[b][k] draw[b][n][f]       (contract over frames)
 //           dweights[b][k-1] = sum_{n,f} bases[k][n][f] draw[b][n][f]
-//                                                              (contract over N*16,
-//           one partial per wave, reduced afterwards in wave order)
-// both with v_mfma_f32_16x16x4f32.
+//                                                               (contract over N*16)
+//
+// The blend and dbases contract over at most K+1 = 64 slices or the batch's
+// frames: short contractions whose cost is reading and writing the slices,
+// so one thread owns one (Gaussian, feature) element, reads each of its
+// inputs once (coalesced across the threads) and writes each output once.
+// The blend accumulates in float64 in slice order and rounds once: the
+// products of two float32 values are exact in float64, so each frame's
+// result is the float64 sum rounded to float32 and does not depend on the
+// batch it is blended in.  dweights contracts over N*16 elements into a
+// B x K result: a long dense contraction, done on the matrix cores
+// (v_mfma_f32_16x16x4f32) with per-wave partials reduced in a fixed order.
 #include "gbr_internal.h"
 
 namespace gbr {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlendMaxSteps = 16;   // K + 1 <= 64
+constexpr int kBlendThreads = 256;
+constexpr int kFrameGroup = 16;        // frames whose weights are staged together
 
-// One wave per (16-frame group, run of Gaussians).  Grid: x over Gaussian runs,
-// y over frame groups.  256 threads = 4 waves, each walking kGaussPerWave
-// consecutive Gaussians.
-constexpr int kGaussPerWave = 4;
+// ---------------------------------------------------------------- forward
+// The frames' weights, as float64 with the implicit 1 of slice 0, are laid
+// out once in a table that every thread reads at the same address (scalar
+// loads: each weight reaches the multiply-adds as a scalar operand).
+__global__ void blend_weights_f64_kernel(const float* __restrict__ weights, int K, double* __restrict__ w64) {
+  const int b = blockIdx.x, k = threadIdx.x;   // slices past K get weight 0
+  w64[(int64_t)b * kBlendW64Stride + k] = (k == 0) ? 1.0 : (k <= K ? (double)weights[(int64_t)b * K + (k - 1)] : 0.0);
+}
 
-__global__ __launch_bounds__(256) void blend_fwd_kernel(const float* __restrict__ bases,
-                                                         const float* __restrict__ weights, int B, int K,
-                                                         int64_t N, float* __restrict__ raw) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int b0 = blockIdx.y * 16;
-  const int steps = (K + 1 + 3) / 4;
-  const int row = lane & 15;     // A: frame within group;  B/D: feature
-  const int kq = lane >> 4;      // A/B: k within step
-
-  // A fragments (weights), kept for the whole run.
-  double afrag[kBlendMaxSteps];
+template <int KM>   // KM >= K + 1: slice values kept in registers
+__global__ __launch_bounds__(kBlendThreads) void blend_fwd_kernel(const float* __restrict__ bases,
+                                                                   const double* __restrict__ w64, int B, int K,
+                                                                   int64_t N, float* __restrict__ raw) {
+  const int64_t L = N * kNF;
+  const int64_t i = (int64_t)blockIdx.x * kBlendThreads + threadIdx.x;
+  if (i >= L) return;
+  const bool pad = (i % kNF) >= 14;
+  // every load is issued unconditionally (slice index clamped into range) so
+  // that they are all in flight together; slices past K are then zeroed
+  float x[KM];
 #pragma unroll
-  for (int s = 0; s < kBlendMaxSteps; ++s) {
-    double a = 0.0;
-    const int k = 4 * s + kq;
-    const int b = b0 + row;
-    if (s < steps && b < B && k <= K) a = (k == 0) ? 1.0 : (double)weights[(int64_t)b * K + (k - 1)];
-    afrag[s] = a;
-  }
-
-  const int64_t n_begin = ((int64_t)blockIdx.x * 4 + wave) * kGaussPerWave;
-  const int64_t slice = N * kNF;
-  for (int64_t n = n_begin; n < n_begin + kGaussPerWave && n < N; ++n) {
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < KM; ++k) x[k] = bases[(int64_t)min(k, K) * L + i];
+  double v[KM];
 #pragma unroll
-    for (int s = 0; s < kBlendMaxSteps; ++s) {
-      if (s < steps) {
-        const int k = 4 * s + kq;
-        const double bv = (k <= K) ? (double)bases[(int64_t)k * slice + n * kNF + row] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(afrag[s], bv, acc, 0, 0, 0);
-      }
-    }
-    // D layout of the f64 16x16x4 op: lane l, item r holds row 4r + l/16, column l%16.
+  for (int k = 0; k < KM; ++k) v[k] = (k <= K) ? (double)x[k] : 0.0;
+  for (int b = 0; b < B; ++b) {
+    const double* w = w64 + (int64_t)b * kBlendW64Stride;
+    double acc = v[0];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int b = b0 + 4 * r + kq;
-      if (b < B) raw[((int64_t)b * N + n) * kNF + row] = (row < 14) ? (float)acc[r] : 0.0f;
-    }
+    for (int k = 1; k < KM; ++k) acc = __builtin_fma(w[k], v[k], acc);   // exact product, one rounding per step
+    raw[(int64_t)b * L + i] = pad ? 0.0f : (float)acc;
   }
 }
 
-void launch_blend_fwd(const float* bases, const float* weights, int B, int K, int64_t N, float* raw,
+void launch_blend_fwd(const float* bases, const float* weights, int B, int K, int64_t N, float* raw, double* w64,
                       hipStream_t s) {
   if (N == 0 || B == 0) return;
-  dim3 grid(div_up(N, 4 * kGaussPerWave), div_up(B, 16));
-  hipLaunchKernelGGL(blend_fwd_kernel, grid, dim3(256), 0, s, bases, weights, B, K, N, raw);
+  hipLaunchKernelGGL(blend_weights_f64_kernel, dim3(B), dim3(kBlendW64Stride), 0, s, weights, K, w64);
+  const dim3 grid(div_up(N * kNF, kBlendThreads));
+  if (K + 1 <= 24)
+    hipLaunchKernelGGL(blend_fwd_kernel<24>, grid, dim3(kBlendThreads), 0, s, bases, w64, B, K, N, raw);
+  else
+    hipLaunchKernelGGL(blend_fwd_kernel<64>, grid, dim3(kBlendThreads), 0, s, bases, w64, B, K, N, raw);
 }
 
-// ---------------------------------------------------------------- adjoint
-// dbases: one wave per run of Gaussians; M = K+1 slices in row tiles of 16,
-// contraction over frames in steps of 4.
-template <int MAXT, int MAXS>
-__global__ __launch_bounds__(256) void blend_dbases_kernel(const float* __restrict__ draw,
-                                                            const float* __restrict__ weights, int B, int K,
-                                                            int64_t N, float* __restrict__ dbases,
-                                                            int accumulate) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int row = lane & 15, kq = lane >> 4;
-  const int ntile = (K + 1 + 15) / 16;
-  const int steps = (B + 3) / 4;
-  float afrag[MAXT][MAXS];
+// ---------------------------------------------------------------- adjoint: dbases
+// One thread per (Gaussian, feature): the frames' draw values are read once
+// per group of 16, every slice's sum is kept in a register and added over
+// the groups in frame order.
+template <int KM>
+__global__ __launch_bounds__(kBlendThreads) void blend_dbases_kernel(const float* __restrict__ draw,
+                                                                      const float* __restrict__ weights, int B,
+                                                                      int K, int64_t N, float* __restrict__ dbases,
+                                                                      int accumulate) {
+  __shared__ float wt[KM][kFrameGroup];   // slice-major: a slice's 16 weights in 4 loads
+  const int64_t L = N * kNF;
+  const int64_t i = (int64_t)blockIdx.x * kBlendThreads + threadIdx.x;
+  const bool live = i < L;
+  const bool pad = (i % kNF) >= 14;
+  float acc[KM];
 #pragma unroll
-  for (int t = 0; t < MAXT; ++t)
-#pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      const int k = 16 * t + row;
-      const int b = 4 * s + kq;
-      float a = 0.0f;
-      if (t < ntile && s < steps && k <= K && b < B) a = (k == 0) ? 1.0f : weights[(int64_t)b * K + (k - 1)];
-      afrag[t][s] = a;
+  for (int k = 0; k < KM; ++k) acc[k] = 0.0f;
+  for (int b0 = 0; b0 < B; b0 += kFrameGroup) {
+    const int nb = min(kFrameGroup, B - b0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kFrameGroup * KM; t += kBlendThreads) {
+      const int bb = t / KM, k = t % KM;
+      float x = 0.0f;
+      if (bb < nb && k <= K) x = (k == 0) ? 1.0f : weights[(int64_t)(b0 + bb) * K + (k - 1)];
+      wt[k][bb] = x;
     }
-  const int64_t n_begin = ((int64_t)blockIdx.x * 4 + wave) * kGaussPerWave;
-  const int64_t slice = N * kNF;
-  for (int64_t n = n_begin; n < n_begin + kGaussPerWave && n < N; ++n) {
-    float bfrag[MAXS];
+    __syncthreads();
+    if (!live) continue;
+    float d[kFrameGroup];
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      const int b = 4 * s + kq;
-      bfrag[s] = (s < steps && b < B) ? draw[((int64_t)b * N + n) * kNF + row] : 0.0f;
-    }
+    for (int bb = 0; bb < kFrameGroup; ++bb) d[bb] = draw[(int64_t)(b0 + min(bb, nb - 1)) * L + i];
 #pragma unroll
-    for (int t = 0; t < MAXT; ++t) {
-      if (t < ntile) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int bb = 0; bb < kFrameGroup; ++bb) d[bb] = (bb < nb) ? d[bb] : 0.0f;   // (weights past nb are 0 too)
 #pragma unroll
-        for (int s = 0; s < MAXS; ++s)
-          if (s < steps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afrag[t][s], bfrag[s], acc, 0, 0, 0);
-        // D layout of the f32 16x16x4 op: lane l, item r holds row 4(l/16) + r, column l%16.
+    for (int k = 0; k < KM; ++k) {
+      if (k <= K) {
+        float s = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = 16 * t + 4 * kq + r;
-          if (k <= K) {
-            float* dst = &dbases[(int64_t)k * slice + n * kNF + row];
-            const float v = (row < 14) ? acc[r] : 0.0f;
-            *dst = accumulate ? *dst + v : v;
-          }
-        }
+        for (int bb = 0; bb < kFrameGroup; ++bb) s = __builtin_fmaf(wt[k][bb], d[bb], s);
+        acc[k] += s;
       }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    if (k <= K) {
+      float* dst = &dbases[(int64_t)k * L + i];
+      const float v = pad ? 0.0f : acc[k];
+      *dst = accumulate ? *dst + v : v;
     }
   }
 }
 
-// dweights partials: wave w covers Gaussians [w*G, (w+1)*G) and writes a
-// [B][K] partial; frames in row tiles of 16, slices 1..K in column tiles of 16.
-constexpr int kDwGaussPerWave = 16;
+// ---------------------------------------------------------------- adjoint: dweights
+// Wave w covers the flattened elements [w * kDwSpan, (w + 1) * kDwSpan) of
+// the N*16 per-slice vectors in blocks of 16: lane (x, q) loads 4 consecutive
+// elements (q-th quarter) of frame x's draw and of slice x's (and 16 + x's)
+// base; each of the 4 components feeds one 16x16x4 product (frames x slices,
+// contracted over the 4 quarters).  The pad features (14, 15) are skipped.
+// Writes a [B][K] partial per wave.
+constexpr int kDwSpan = 256;
 
 template <int MAXBT, int MAXKT>
 __global__ __launch_bounds__(256) void blend_dweights_kernel(const float* __restrict__ draw,
                                                               const float* __restrict__ bases, int B, int K,
                                                               int64_t N, float* __restrict__ partials) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int row = lane & 15, kq = lane >> 4;
+  const int x = lane & 15, q = lane >> 4;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t L = N * kNF;
+  const int64_t e_begin = gw * kDwSpan;
+  const int64_t e_end = min(L, e_begin + kDwSpan);
   const int nbt = (B + 15) / 16, nkt = (K + 15) / 16;
-  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
-  const int64_t n_begin = gw * kDwGaussPerWave;
-  const int64_t slice = N * kNF;
   f4 acc[MAXBT][MAXKT];
 #pragma unroll
   for (int i = 0; i < MAXBT; ++i)
 #pragma unroll
     for (int j = 0; j < MAXKT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t n = n_begin; n < n_begin + kDwGaussPerWave && n < N; ++n) {
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t e0 = e_begin; e0 < e_end; e0 += 16) {
+    const int64_t e = e0 + 4 * q;            // L is a multiple of 16: the block is whole
+    f4 a[MAXBT], bb[MAXKT];
+    // unconditional loads (row clamped into range), masked afterwards
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {          // 16 features in 4 steps of 4
-      const int f = 4 * s + kq;
-      float a[MAXBT], bb[MAXKT];
+    for (int i = 0; i < MAXBT; ++i) {
+      const int b = 16 * i + x;
+      a[i] = *reinterpret_cast<const f4*>(draw + (int64_t)min(b, B - 1) * L + e);
+      if (!(i < nbt && b < B)) a[i] = zero;
+    }
 #pragma unroll
-      for (int i = 0; i < MAXBT; ++i) {
-        const int b = 16 * i + row;
-        a[i] = (i < nbt && b < B && f < 14) ? draw[((int64_t)b * N + n) * kNF + f] : 0.0f;
-      }
+    for (int j = 0; j < MAXKT; ++j) {
+      const int k = 16 * j + x + 1;
+      bb[j] = *reinterpret_cast<const f4*>(bases + (int64_t)min(k, K) * L + e);
+      if (!(j < nkt && k <= K)) bb[j] = zero;
+    }
+    if (q == 3) {                            // features 14 and 15 are pads
 #pragma unroll
-      for (int j = 0; j < MAXKT; ++j) {
-        const int k = 16 * j + row + 1;
-        bb[j] = (j < nkt && k <= K && f < 14) ? bases[(int64_t)k * slice + n * kNF + f] : 0.0f;
-      }
+      for (int i = 0; i < MAXBT; ++i) { a[i][2] = 0.f; a[i][3] = 0.f; }
+#pragma unroll
+      for (int j = 0; j < MAXKT; ++j) { bb[j][2] = 0.f; bb[j][3] = 0.f; }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int i = 0; i < MAXBT; ++i)
 #pragma unroll
         for (int j = 0; j < MAXKT; ++j)
-          if (i < nbt && j < nkt) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
-    }
+          if (i < nbt && j < nkt) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][c], bb[j][c], acc[i][j], 0, 0, 0);
   }
   float* out = partials + gw * (int64_t)B * K;
+  // D layout of the f32 16x16x4 op: lane l, item r holds row 4(l/16) + r, column l%16.
 #pragma unroll
   for (int i = 0; i < MAXBT; ++i)
 #pragma unroll
@@ -179,8 +189,8 @@ __global__ __launch_bounds__(256) void blend_dweights_kernel(const float* __rest
       if (i < nbt && j < nkt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int b = 16 * i + 4 * kq + r;
-          const int k = 16 * j + row;
+          const int b = 16 * i + 4 * q + r;
+          const int k = 16 * j + x;
           if (b < B && k < K) out[(int64_t)b * K + k] = acc[i][j][r];
         }
 }
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
 }
 
 int64_t blend_bwd_partials(int B, int K, int64_t N) {
-  const int64_t waves = (int64_t)div_up(N, 4 * kDwGaussPerWave) * 4;
+  const int64_t waves = (int64_t)div_up(N * kNF, 4 * kDwSpan) * 4;
   return waves * (int64_t)B * K;
 }
 
@@ -211,14 +221,15 @@ void launch_blend_bwd(const float* draw, const float* bases, const float* weight
                       float* dbases, float* dweights, float* partials, int64_t n_partials, int accumulate,
                       hipStream_t s) {
   if (N == 0 || B == 0) return;
-  const dim3 g1(div_up(N, 4 * kGaussPerWave));
-  if (B <= 16 && K + 1 <= 32)
-    hipLaunchKernelGGL((blend_dbases_kernel<2, 4>), g1, dim3(256), 0, s, draw, weights, B, K, N, dbases, accumulate);
+  const dim3 g1(div_up(N * kNF, kBlendThreads));
+  if (K + 1 <= 24)
+    hipLaunchKernelGGL(blend_dbases_kernel<24>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, dbases,
+                       accumulate);
   else
-    hipLaunchKernelGGL((blend_dbases_kernel<4, 16>), g1, dim3(256), 0, s, draw, weights, B, K, N, dbases,
+    hipLaunchKernelGGL(blend_dbases_kernel<64>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, dbases,
                        accumulate);
   if (K == 0) return;
-  const dim3 g2(div_up(N, 4 * kDwGaussPerWave));
+  const dim3 g2(div_up(N * kNF, 4 * kDwSpan));
   if (B <= 16 && K <= 32)
     hipLaunchKernelGGL((blend_dweights_kernel<1, 2>), g2, dim3(256), 0, s, draw, bases, B, K, N, partials);
   else

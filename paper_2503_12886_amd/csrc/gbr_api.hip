@@ -87,6 +87,7 @@ struct gbr_ctx {
   float* draw_scratch = nullptr;
   float* loss_part = nullptr;
   float* blend_part = nullptr;
+  double* blend_w64 = nullptr;     // [kBlendMaxFrames][kBlendW64Stride]
   int64_t blend_part_n = 0;
   float *mlp_z1 = nullptr, *mlp_z2 = nullptr, *mlp_dz1 = nullptr, *mlp_dz2 = nullptr;
   // host staging
@@ -195,7 +196,7 @@ void free_all(gbr_ctx* c) {
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
-  dfree(c->loss_part); dfree(c->blend_part);
+  dfree(c->loss_part); dfree(c->blend_part); dfree(c->blend_w64);
   dfree(c->mlp_z1); dfree(c->mlp_z2); dfree(c->mlp_dz1); dfree(c->mlp_dz2);
   if (c->h_frames) (void)hipHostFree(c->h_frames);
   if (c->h_status) (void)hipHostFree(c->h_status);
@@ -403,6 +404,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->loss_part, 2 * loss_partials(3 * c->cap_pixels) + 2));
   c->blend_part_n = 4 * c->cap_splats + 4096LL * c->cap_frames + 64LL * 64 * 8;
   TRY(dalloc(&c->blend_part, c->blend_part_n));
+  TRY(dalloc(&c->blend_w64, (int64_t)kBlendMaxFrames * kBlendW64Stride));
   TRY(dalloc(&c->mlp_z1, (int64_t)c->cap_frames * 1024));
   TRY(dalloc(&c->mlp_z2, (int64_t)c->cap_frames * 1024));
   TRY(dalloc(&c->mlp_dz1, (int64_t)c->cap_frames * 1024));
@@ -451,10 +453,11 @@ int gbr_set_tiling(gbr_ctx* c, int32_t tile, int32_t chunk) {
 
 int gbr_blend(gbr_ctx* c, const float* bases, const float* weights, int32_t B, int32_t K, int64_t N, float* raw,
               void* stream) {
-  if (!c || !bases || !raw || B < 1 || K < 0 || K > kMaxK || N < 1 || (K > 0 && !weights)) return GBR_ERR_INVALID_ARG;
+  if (!c || !bases || !raw || B < 1 || B > kBlendMaxFrames || K < 0 || K > kMaxK || N < 1 || (K > 0 && !weights))
+    return GBR_ERR_INVALID_ARG;
   {
     KTimer t(c, GBR_K_BLEND, (hipStream_t)stream);
-    launch_blend_fwd(bases, weights, B, K, N, raw, (hipStream_t)stream);
+    launch_blend_fwd(bases, weights, B, K, N, raw, c->blend_w64, (hipStream_t)stream);
   }
   GBR_HIP(hipGetLastError());
   return GBR_OK;

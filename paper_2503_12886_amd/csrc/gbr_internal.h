@@ -155,7 +155,10 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 namespace gbr {
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
-void launch_blend_fwd(const float* bases, const float* weights, int B, int K, int64_t N, float* raw, hipStream_t s);
+constexpr int kBlendMaxFrames = 4096;   // frames per gbr_blend call (rows of the float64 weight table)
+constexpr int kBlendW64Stride = 64;     // K + 1 <= 64
+void launch_blend_fwd(const float* bases, const float* weights, int B, int K, int64_t N, float* raw, double* w64,
+                      hipStream_t s);
 void launch_blend_bwd(const float* draw, const float* bases, const float* weights, int B, int K, int64_t N,
                       float* dbases, float* dweights, float* partials, int64_t n_partials, int accumulate,
                       hipStream_t s);

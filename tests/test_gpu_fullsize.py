@@ -67,6 +67,31 @@ def masked(dimg, flags):
     return [np.where(f[None] == 0, d, 0.0).astype(np.float32) for d, f in zip(dimg, flags)]
 
 
+def check_long_sum(got, ref, bases, draw):
+    """Weight gradients are sums of N * 14 products with cancellation: each
+    entry must be within 1e-3 of its value or within 1e-5 of the sum of the
+    products' magnitudes (float32 summation of that many terms in a tree
+    errs by a few float32 epsilons times that sum)."""
+    mag = np.einsum("knf,bnf->bk", np.abs(bases[1:, :, :14]), np.abs(draw[:, :, :14]))
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    bound = np.maximum(1e-3 * np.abs(ref), 1e-5 * mag)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
+def check_frame_sum(got, ref, mag):
+    """Base gradients sum each Gaussian's gradient over the frames with the
+    weights: an entry passes the per-entry rule (1e-3 of its value, floor
+    1e-3 of its column's largest) or is within 1e-5 of the sum of the
+    terms' magnitudes (a sum with cancellation can only be as exact as its
+    terms, whose own float32 error is a few epsilons)."""
+    g = np.asarray(got, np.float64)
+    r = np.asarray(ref, np.float64)
+    colmax = np.abs(r).max(axis=0, keepdims=True)
+    bound = np.maximum(1e-3 * np.maximum(np.abs(r), 1e-3 * colmax), 1e-5 * mag)
+    err = np.abs(g - r)
+    assert np.all(err <= bound), float((err / bound).max())
+
+
 def check_tile_lists(ctx, raw, cams, N, tile, frames):
     """The GPU's per-tile lists of the given frames equal the reference's,
     entry by entry (global splat index = frame * N + Gaussian)."""
@@ -150,10 +175,13 @@ def test_training_step_full_size():
     draw = np.stack(pmap(frame_adjoint, [(raw[b], cams[b], dm[b]) for b in range(B)]))
     dbases_ref, dpsi_ref = bs.blend_adjoint(draw, bases0, psi64)
     rows = lambda a: np.transpose(a[..., :14], (1, 0, 2)).reshape(N, -1)
-    rel, worst = grad_check(rows(host(dB)), rows(dbases_ref))
-    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
-    rel, worst = grad_check(host(dpsi_m), dpsi_ref)
-    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+    rel, _ = grad_check(rows(host(dB)), rows(dbases_ref))
+    assert rel <= 1e-3, rel
+    mag = bs.blend_adjoint(np.abs(draw), bases0, np.abs(psi64))[0]
+    check_frame_sum(rows(host(dB)), rows(dbases_ref), rows(mag))
+    rel, _ = grad_check(host(dpsi_m), dpsi_ref)
+    assert rel <= 1e-3, rel
+    check_long_sum(host(dpsi_m), dpsi_ref, bases0, draw)
 
     # tile lists and depth order of the whole batch, bit for bit
     check_tile_lists(tr.ctx, raw, cams, N, cfg.tile, range(B))
@@ -189,15 +217,17 @@ def test_adjoint_random_subset_full_size():
     torch.cuda.synchronize()
     draw = np.stack(pmap(frame_adjoint, [(raw[b], cams[b], dm[b]) for b in range(B)]))
     dbases_ref, dw_ref = bs.blend_adjoint(draw, bases.astype(np.float64), w.astype(np.float64))
-    del draw
     # a 1 % random subset of the base entries (14 live features of every slice), entry by entry
     got = host(dB)[..., :14].ravel()
     ref = dbases_ref[..., :14].ravel()
     pick = rng.choice(got.size, size=got.size // 100, replace=False)
-    rel, worst = grad_check(got[pick][:, None], ref[pick][:, None])
-    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
-    rel, worst = grad_check(host(dW), dw_ref)
-    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+    rel, _ = grad_check(got[pick][:, None], ref[pick][:, None])
+    assert rel <= 1e-3, rel
+    mag = bs.blend_adjoint(np.abs(draw), bases.astype(np.float64), np.abs(w.astype(np.float64)))[0][..., :14].ravel()
+    check_frame_sum(got[pick][:, None], ref[pick][:, None], mag[pick][:, None])
+    rel, _ = grad_check(host(dW), dw_ref)
+    assert rel <= 1e-3, rel
+    check_long_sum(host(dW), dw_ref, bases.astype(np.float64), draw)
     ctx.close()
 
 
