@@ -248,12 +248,47 @@ void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* 
 }
 
 // ---------------------------------------------------------------- gather + projection adjoint
-// One thread per splat: sums its entries' partials in row-major tile order
-// (unflagged entries -- no contributing pixel, or past the tile's last used
-// position -- are zero), then chains back through the conic, the EWA
-// projection and the activations in float64.
-__global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float* __restrict__ raw,
-                                                         float* __restrict__ draw) {
+// Two passes.  gather_sum: one thread per splat sums its entries' partials in
+// row-major tile order (unflagged entries -- no contributing pixel, or past
+// the tile's last used position -- are zero): the flags of 8 entries are
+// read together, then the flagged partials, all loads in flight before any
+// is used; the 9 sums go to the splat's draw row as scratch.  proj_adjoint:
+// one thread per splat chains those sums back through the conic, the EWA
+// projection and the activations in float64 and overwrites the row.  Kept
+// apart so the summing pass runs at full occupancy.
+__global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __restrict__ draw) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= a.n_splats) return;
+  const uint32_t c = a.cnt[s];
+  float acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+  if (!a.status->overflow && c > 0) {
+    const uint32_t off = a.soff[s];
+    for (uint32_t e0 = off; e0 < off + c; e0 += 8) {
+      bool f[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f[u] = a.part_flag[min(e0 + u, off + c - 1)] != 0 && e0 + u < off + c;
+      float q[8][9];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float* src = a.part + (int64_t)(f[u] ? e0 + u : off) * 9;   // in range either way
+#pragma unroll
+        for (int k = 0; k < 9; ++k) q[u][k] = src[k];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += f[u] ? q[u][k] : 0.0f;
+    }
+  }
+  float* out = draw + s * kNF;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) out[k] = acc[k];
+}
+
+__global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const float* __restrict__ raw,
+                                                           float* __restrict__ draw) {
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= a.n_splats) return;
   float4* out = reinterpret_cast<float4*>(draw + s * kNF);
@@ -265,25 +300,9 @@ __global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float
   }
   const int b = frame_of_splat(a.frames, a.B, s);
   const FrameDev& F = a.frames[b];
-  const uint32_t off = a.soff[s];
   float acc[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-  // the splat's entries are contiguous in emission order (tiles of its rect,
-  // row-major); unflagged entries are zero
-  for (uint32_t e0 = off; e0 < off + c; e0 += 8) {
-    uint8_t f[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) f[u] = (e0 + u < off + c) ? a.part_flag[e0 + u] : (uint8_t)0;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (f[u]) {
-        const float* q = a.part + (int64_t)(e0 + u) * 9;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += q[k];
-      }
-    }
-  }
+  for (int k = 0; k < 9; ++k) acc[k] = draw[s * kNF + k];
 
   // ---- recompute the forward quantities (float64) ----
   const float* gp = raw + s * kNF;
@@ -387,7 +406,8 @@ __global__ __launch_bounds__(256) void gather_bwd_kernel(PassArgs a, const float
 
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s) {
   if (a.n_splats == 0) return;
-  hipLaunchKernelGGL(gather_bwd_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, raw, draw);
+  hipLaunchKernelGGL(gather_sum_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, draw);
+  hipLaunchKernelGGL(proj_adjoint_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, raw, draw);
 }
 
 // ---------------------------------------------------------------- loss
@@ -403,11 +423,20 @@ __global__ __launch_bounds__(kLossThreads) void loss_kernel(const float* __restr
   __shared__ double sm[kLossThreads];
   const int64_t base = (int64_t)blockIdx.x * kLossPerBlock;
   const float inv = 1.0f / (float)n;
+  // loads issued unconditionally (index clamped into range, n >= 1), then masked
+  float xv[16], yv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int64_t k = min(base + (int64_t)i * kLossThreads + threadIdx.x, n - 1);
+    xv[i] = x[k];
+    yv[i] = y[k];
+  }
   double s = 0.0;
+#pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int64_t k = base + (int64_t)i * kLossThreads + threadIdx.x;
     if (k < n) {
-      const float d = x[k] - y[k];
+      const float d = xv[i] - yv[i];
       if (kind == 1) {
         s += fabs((double)d);
         dx[k] = (d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f));

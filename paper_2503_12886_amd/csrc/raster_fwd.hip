@@ -36,11 +36,16 @@ __global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(const uint32_
                                                                     uint32_t* __restrict__ block_sums) {
   __shared__ uint32_t lw[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock;
-  uint32_t s = 0;
+  // loads issued unconditionally (index clamped into range), then masked
+  uint32_t v[kScanItems];
+#pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int64_t k = base + (int64_t)i * kScanThreads + threadIdx.x;
-    if (k < n) s += in[k];
+    v[i] = (n > 0) ? in[min(k, n - 1)] : 0u;
   }
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) s += (base + (int64_t)i * kScanThreads + threadIdx.x < n) ? v[i] : 0u;
   uint32_t tot;
   block_excl_scan<kScanThreads>(s, lw, &tot);
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
@@ -76,10 +81,13 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
   __shared__ uint32_t tile[kScanBlock];
   __shared__ uint32_t lw[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  uint32_t v[kScanItems];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) v[i] = (n > 0) ? in[min(base + i * kScanThreads + threadIdx.x, n - 1)] : 0u;
+#pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int idx = i * kScanThreads + threadIdx.x;
-    const int64_t k = base + idx;
-    tile[idx] = (k < n) ? in[k] : 0u;
+    tile[idx] = (base + idx < n) ? v[i] : 0u;
   }
   __syncthreads();
   uint32_t local[kScanItems];
