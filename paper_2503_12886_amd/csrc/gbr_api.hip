@@ -138,6 +138,7 @@ PassArgs make_args(gbr_ctx* c) {
   a.keys = c->keys; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
   a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
+  a.sort_list_cap = std::max(0, std::min(4096, 32768 - std::max(a.bitmap_words, 1)));
   a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_start = c->bkt_start; a.bkt_cursor = c->bkt_cursor;
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
   a.big_list = c->big_list; a.big_count = c->big_count;
@@ -170,9 +171,9 @@ int alloc_entries(gbr_ctx* c, int64_t cap) {
   int rc = GBR_OK;
   if ((rc = dalloc(&c->keys, cap))) return rc;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
-  if ((rc = dalloc(&c->part_flag, cap + 16))) return rc;
+  if ((rc = dalloc(&c->part_flag, cap + 64))) return rc;   // gather reads 64-entry flag windows
   if ((rc = dalloc(&c->cmask, cap))) return rc;
-  if ((rc = dalloc(&c->part, cap * 9))) return rc;
+  if ((rc = dalloc(&c->part, cap * kPartF))) return rc;
   c->cap_entries = cap;
   return GBR_OK;
 }

@@ -15,7 +15,8 @@ constexpr double kLowPass = 0.3;           // px^2 added to the 2D covariance
 constexpr double kBoxPad = 0.01;           // px added to the alpha-support box
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
-constexpr int kRecF = 12;                  // floats per splat record
+constexpr int kRecF = 12;
+constexpr int kPartF = 12;          // floats per partial record: 9 values, padded to 48 B (3 x 16-B loads)                  // floats per splat record
 constexpr int kMaxFrameTilesLds = 4096;    // per-frame tile histogram kept in LDS
 
 // Per-frame table entry, built on the host for every render and uploaded
@@ -74,6 +75,7 @@ struct PassArgs {
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
   int32_t bitmap_words;     // LDS words of the per-tile rank bitmap (max frame size / 32)
+  int32_t sort_list_cap;    // LDS words after the bitmap for a tile's sorted ranks (longer lists go via memory)
   uint32_t* minmax;         // [B][2] min / max binary32 depth bits of the frame's valid splats
   uint32_t* bkt_count;      // [B * nbk]
   uint32_t* bkt_start;      // [B * nbk + 1] exclusive scan; frame b's valid splats start at bkt_start[b * nbk]
@@ -88,7 +90,7 @@ struct PassArgs {
   uint32_t* n_iter;         // [pixels] list position after the last contributor
   uint32_t* n_contrib;      // [pixels] number of contributors
   float* t_final;           // [pixels]
-  float* part;              // [E][9] per-entry gradient partials, by emission slot
+  float* part;              // [E][kPartF] per-entry gradient partials (9 used), by emission slot
   uint8_t* part_flag;       // [E] 1 where the entry's partial is non-zero and written
   uint8_t* cmask;           // [E] bit w: some pixel of wave w of the tile took this entry (forward)
 };

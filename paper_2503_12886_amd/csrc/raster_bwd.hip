@@ -208,9 +208,10 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
       const uint32_t sp = sid[i];
       const int4 r = a.rect[sp];
       const uint32_t e = a.soff[sp] + (uint32_t)((ty - r.y) * (r.z - r.x + 1) + (tx - r.x));
-      float* dst = a.part + (int64_t)e * 9;
-#pragma unroll
-      for (int c = 0; c < 9; ++c) dst[c] = v[c];
+      float4* dst = reinterpret_cast<float4*>(a.part + (int64_t)e * kPartF);
+      dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+      dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+      dst[2] = make_float4(v[8], 0.0f, 0.0f, 0.0f);
       a.part_flag[e] = 1;
     }
   }
@@ -256,6 +257,11 @@ void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* 
 // one thread per splat chains those sums back through the conic, the EWA
 // projection and the activations in float64 and overwrites the row.  Kept
 // apart so the summing pass runs at full occupancy.
+// Flag bytes (0 or 1) of 4 entries -> 4 bits.
+__device__ __forceinline__ uint32_t flag_nibble(uint32_t w) {
+  return (w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u);
+}
+
 __global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __restrict__ draw) {
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= a.n_splats) return;
@@ -264,22 +270,45 @@ __global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __re
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
   if (!a.status->overflow && c > 0) {
-    const uint32_t off = a.soff[s];
-    for (uint32_t e0 = off; e0 < off + c; e0 += 8) {
-      bool f[8];
+    const uint32_t off = a.soff[s], end = off + c;
+    const uint32_t* fw = reinterpret_cast<const uint32_t*>(a.part_flag);   // padded by 64 bytes past the capacity
+    // windows of 64 entries starting at a multiple of 4: the 16 flag words
+    // are read together and turned into a bit mask of the flagged entries,
+    // whose partials are then read 4 at a time (all 4 in flight together)
+    for (uint32_t e0 = off & ~3u; e0 < end; e0 += 64) {
+      uint32_t w[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) f[u] = a.part_flag[min(e0 + u, off + c - 1)] != 0 && e0 + u < off + c;
-      float q[8][9];
+      for (int k = 0; k < 16; ++k) w[k] = fw[(e0 >> 2) + k];
+      unsigned long long m = 0ull;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const float* src = a.part + (int64_t)(f[u] ? e0 + u : off) * 9;   // in range either way
+      for (int k = 0; k < 16; ++k) m |= (unsigned long long)flag_nibble(w[k]) << (4 * k);
+      // keep [off, end) only
+      const uint32_t lo = off > e0 ? off - e0 : 0u;
+      const uint32_t hi = end - e0 < 64u ? end - e0 : 64u;
+      m &= (hi >= 64u ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+      while (m) {
+        uint32_t e[4];
+        bool v[4];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) q[u][k] = src[k];
+        for (int u = 0; u < 4; ++u) {
+          v[u] = m != 0ull;
+          e[u] = v[u] ? e0 + (uint32_t)(__ffsll((long long)m) - 1) : off;   // off: in range, unused
+          m &= m - 1ull;
+        }
+        float4 q[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4* src = reinterpret_cast<const float4*>(a.part + (int64_t)e[u] * kPartF);
+          q[u][0] = src[0]; q[u][1] = src[1]; q[u][2] = src[2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!v[u]) continue;
+          acc[0] += q[u][0].x; acc[1] += q[u][0].y; acc[2] += q[u][0].z; acc[3] += q[u][0].w;
+          acc[4] += q[u][1].x; acc[5] += q[u][1].y; acc[6] += q[u][1].z; acc[7] += q[u][1].w;
+          acc[8] += q[u][2].x;
+        }
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += f[u] ? q[u][k] : 0.0f;
     }
   }
   float* out = draw + s * kNF;

@@ -367,26 +367,28 @@ __global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
   const int w0 = threadIdx.x * wpt, w1 = min(W, w0 + wpt);
   uint32_t c = 0;
   for (int w = w0; w < w1; ++w) c += __popc(bitmap[w]);
-  uint32_t out = start + block_excl_scan<256>(c, lw, nullptr);
-  // ranks in ascending order (each thread writes the set bits of its words)
+  const uint32_t first = block_excl_scan<256>(c, lw, nullptr);
+  // ranks in ascending order (each thread emits the set bits of its words):
+  // into LDS after the bitmap when the list fits, else through the output
+  uint32_t* list = (n <= (uint32_t)a.sort_list_cap) ? bitmap + W : a.sorted + start;
+  uint32_t out = first;
   for (int w = w0; w < w1; ++w) {
     uint32_t bits = bitmap[w];
     while (bits) {
       const uint32_t bit = __ffs(bits) - 1u;
       bits &= bits - 1u;
-      a.sorted[out++] = (uint32_t)w * 32u + bit;
+      list[out++] = (uint32_t)w * 32u + bit;
     }
   }
   __threadfence_block();
   __syncthreads();
   // rank -> splat, one entry per thread
-  const uint32_t* __restrict__ ranks = a.sorted + start;
   for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * 256) {
     uint32_t sp[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint32_t i = i0 + u * 256;
-      sp[u] = (i < n) ? a.depth_sorted[vbase + ranks[i]] : 0u;
+      sp[u] = (i < n) ? a.depth_sorted[vbase + list[i]] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
 
 void launch_tile_sort(const PassArgs& a, hipStream_t s) {
   if (a.n_tiles == 0) return;
-  const size_t lds = (size_t)std::max(a.bitmap_words, 1) * sizeof(uint32_t);
+  const size_t lds = (size_t)(std::max(a.bitmap_words, 1) + a.sort_list_cap) * sizeof(uint32_t);
   static bool attr_set = false;   // more than 64 KB of dynamic LDS must be requested explicitly
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_sort_kernel),
