@@ -124,6 +124,26 @@ __device__ __forceinline__ float dpp_mov(float x) {
       __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK, BANK_MASK, BOUND_CTRL));
 }
 
+// Pixels of a tile and the threads that composite them.  T = 8: 64 threads,
+// one pixel each; T = 16: 256 threads, one pixel each; T = 32: 256 threads,
+// a 2x2 pixel block each.  Each wave covers a square quadrant of the tile
+// (the whole tile when T = 8), its lanes row-major inside it: compact wave
+// footprints let whole waves skip a splat or stop early.  The forward and
+// backward passes share this map (the forward's per-wave contribution bits
+// are read by the backward's waves).
+template <int T> struct TileMap {
+  static constexpr int NT = (T == 8) ? 64 : 256;
+  static constexpr int PXW = (T == 32) ? 2 : 1;     // pixels per thread along x and y
+  static constexpr int PX = PXW * PXW;
+  static constexpr int NW = NT / 64;
+  static constexpr int QW = (NW == 1) ? T : T / 2;  // side of a wave's quadrant, pixels
+  static constexpr int LPR = QW / PXW;              // lanes per quadrant row
+  __device__ static int qx(int tid) { return (tid >> 6) & 1; }
+  __device__ static int qy(int tid) { return (tid >> 6) >> 1; }
+  __device__ static int lx0(int tid) { return qx(tid) * QW + ((tid & 63) % LPR) * PXW; }
+  __device__ static int ly0(int tid) { return qy(tid) * QW + ((tid & 63) / LPR) * PXW; }
+};
+
 // Sum over the 16 lanes of each row; each row's total lands in its lane 15
 // (lanes 15, 31, 47, 63).  Out-of-row sources read zero.
 __device__ __forceinline__ float row_sum_to15(float v) {

@@ -6,13 +6,7 @@
 
 namespace gbr {
 
-template <int T> struct TileShapeB {
-  static constexpr int NT = (T == 8) ? 64 : 256;
-  static constexpr int PXW = (T == 32) ? 2 : 1;
-  static constexpr int PX = PXW * PXW;
-  static constexpr int TPR = T / PXW;
-  static constexpr int NW = NT / 64;
-};
+template <int T> using TileShapeB = TileMap<T>;
 
 // Must stay bit-identical to the forward kernel's alpha.
 __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, float py, float& dx, float& dy,
@@ -98,7 +92,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   const int tx = lt % F.ntx, ty = lt / F.ntx;
   const uint32_t start = a.tile_start[g];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lx0 = (threadIdx.x % S::TPR) * S::PXW, ly0 = (threadIdx.x / S::TPR) * S::PXW;
+  const int lx0 = S::lx0(threadIdx.x), ly0 = S::ly0(threadIdx.x);
   float T_[S::PX], R0[S::PX], R1[S::PX], R2[S::PX], G0[S::PX], G1[S::PX], G2[S::PX];
   uint32_t nit[S::PX];
   float pxf[S::PX], pyf[S::PX];

@@ -411,18 +411,10 @@ void launch_tile_sort(const PassArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- compositing
-// One workgroup per tile.  T = 8: 64 threads, one pixel each; T = 16: 256
-// threads, one pixel each; T = 32: 256 threads, a 2x2 pixel block each.
+// One workgroup per tile (pixels to threads: TileMap).
 // CHUNK sorted entries at a time are staged in LDS and read by every thread
 // (broadcast); the tile stops when all its pixels have stopped.
-template <int T> struct TileShape {
-  static constexpr int NT = (T == 8) ? 64 : 256;
-  static constexpr int PXW = (T == 32) ? 2 : 1;     // pixels per thread along x and y
-  static constexpr int PX = PXW * PXW;
-  static constexpr int TPR = T / PXW;               // threads per pixel row
-  static constexpr int NW = NT / 64;
-  static constexpr int RW = (64 / TPR) * PXW;       // pixel rows covered by one wave
-};
+template <int T> using TileShape = TileMap<T>;
 
 // Whether a splat's alpha >= 1/255 region may reach the rectangle
 // [x0, x1] x [y0, y1] of pixel centres: the maximum of the concave power
@@ -482,7 +474,7 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   const int tx = lt % F.ntx, ty = lt / F.ntx;
   const uint32_t start = a.tile_start[g], end = a.tile_start[g + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lx0 = (threadIdx.x % S::TPR) * S::PXW, ly0 = (threadIdx.x / S::TPR) * S::PXW;
+  const int lx0 = S::lx0(threadIdx.x), ly0 = S::ly0(threadIdx.x);
   float T_[S::PX], C0[S::PX], C1[S::PX], C2[S::PX], pxf[S::PX], pyf[S::PX];
   uint32_t last[S::PX], ncon[S::PX];
   bool done[S::PX], inside[S::PX];
@@ -519,8 +511,8 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
       // one lane tests one entry against the rectangle of the wave's pixel
       // centres; the wave then visits only those, in list order, U at a time,
       // and stops as soon as all its pixels have stopped.
-      const float sx0 = (float)(tx * T) + 0.5f, sx1 = sx0 + (float)(T - 1);
-      const float sy0 = (float)(ty * T + w * S::RW) + 0.5f, sy1 = sy0 + (float)(S::RW - 1);
+      const float sx0 = (float)(tx * T + S::qx(threadIdx.x) * S::QW) + 0.5f, sx1 = sx0 + (float)(S::QW - 1);
+      const float sy0 = (float)(ty * T + S::qy(threadIdx.x) * S::QW) + 0.5f, sy1 = sy0 + (float)(S::QW - 1);
       bool live = true;
       for (int gb = 0; gb < n; gb += 64) {
         unsigned long long cand = 0ull;
