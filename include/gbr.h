@@ -217,7 +217,11 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
    (global splat index),
    5 per-pixel list position after the last contributor [pixels] u32,
    6 per-pixel final transmittance [pixels] f32, 7 per-tile entries used
-   [tiles] u32, 8 per-pixel number of contributing Gaussians [pixels] u32.
+   [tiles] u32, 8 per-pixel number of contributing Gaussians [pixels] u32,
+   9 per-entry contribution mask [entries] u8: bit w set when some pixel of
+   the tile's quadrant w (tiles of 16 and 32 px: quadrants of half the side,
+   w = 2 * (row half) + (column half); tiles of 8 px: one quadrant, bit 0)
+   took the entry in the forward pass.
    *bytes in: capacity of dst; out: bytes written. */
 int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
 

@@ -159,15 +159,34 @@ __device__ __forceinline__ float row_sum_to15(float v) {
 // rows of 16 lanes, x holds (x0, y0, x2, y2) and y holds (x1, y1, x3, y3).
 // Adding the two results folds two values into one register at half the
 // lane count each.  Written as inline assembly (both operands are read and
-// written in place) with two wait states on either side.
-__device__ __forceinline__ float fold32(float x, float y) {
-  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
-  return x + y;
+// written in place), several swaps per statement, with two wait states
+// before the first (after the VALU writes of the operands) and after the
+// last.
+#define GBR_SWAP_PAIR(op, i, j) op " %" #i ", %" #j "\n\t"
+__device__ __forceinline__ void fold32x9(float* x, float* y) {   // x[c] <- x[c] + y[c] folded, c < 9
+  asm volatile("s_nop 1\n\t"
+               GBR_SWAP_PAIR("v_permlane32_swap_b32", 0, 9) GBR_SWAP_PAIR("v_permlane32_swap_b32", 1, 10)
+               GBR_SWAP_PAIR("v_permlane32_swap_b32", 2, 11) GBR_SWAP_PAIR("v_permlane32_swap_b32", 3, 12)
+               GBR_SWAP_PAIR("v_permlane32_swap_b32", 4, 13) GBR_SWAP_PAIR("v_permlane32_swap_b32", 5, 14)
+               GBR_SWAP_PAIR("v_permlane32_swap_b32", 6, 15) GBR_SWAP_PAIR("v_permlane32_swap_b32", 7, 16)
+               GBR_SWAP_PAIR("v_permlane32_swap_b32", 8, 17) "s_nop 1"
+               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
+                 "+v"(x[8]), "+v"(y[0]), "+v"(y[1]), "+v"(y[2]), "+v"(y[3]), "+v"(y[4]), "+v"(y[5]), "+v"(y[6]),
+                 "+v"(y[7]), "+v"(y[8]));
+#pragma unroll
+  for (int c = 0; c < 9; ++c) x[c] += y[c];
 }
-__device__ __forceinline__ float fold16(float x, float y) {
-  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
-  return x + y;
+__device__ __forceinline__ void fold16x5(float* x, float* y) {   // x[j] <- x[j] + y[j] folded, j < 5
+  asm volatile("s_nop 1\n\t"
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 0, 5) GBR_SWAP_PAIR("v_permlane16_swap_b32", 1, 6)
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 2, 7) GBR_SWAP_PAIR("v_permlane16_swap_b32", 3, 8)
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 4, 9) "s_nop 1"
+               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(y[0]), "+v"(y[1]), "+v"(y[2]),
+                 "+v"(y[3]), "+v"(y[4]));
+#pragma unroll
+  for (int j = 0; j < 5; ++j) x[j] += y[j];
 }
+#undef GBR_SWAP_PAIR
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

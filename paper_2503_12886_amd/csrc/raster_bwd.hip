@@ -161,13 +161,10 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
         // register), then 16 apart (two values per register pair), then
         // four in-row shifts.  Lane 16r + 15 of S[j] ends with value
         // c = 2j + (r & 1) of entry u = r >> 1.
-        float R[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) R[c] = fold32(acc[0][c], acc[1][c]);
-        float Sj[5];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Sj[j] = fold16(R[2 * j], R[2 * j + 1]);
-        Sj[4] = fold16(R[8], 0.0f);
+        fold32x9(acc[0], acc[1]);                 // acc[0][c]: value c of entry 0 | entry 1
+        float Sj[5] = {acc[0][0], acc[0][2], acc[0][4], acc[0][6], acc[0][8]};
+        float Tj[5] = {acc[0][1], acc[0][3], acc[0][5], acc[0][7], 0.0f};
+        fold16x5(Sj, Tj);                        // Sj[j]: values 2j, 2j+1 of both entries, by row
 #pragma unroll
         for (int j = 0; j < 5; ++j) Sj[j] = row_sum_to15(Sj[j]);
         if ((lane & 15) == 15) {

@@ -212,3 +212,51 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(gbr.GbrError) as e:
         gbr.gbr_render_backward(fresh, out, raw)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_contribution_masks_match_reference_contributors(tile):
+    """The forward pass's per-entry contribution bits (one per wave quadrant)
+    are exactly 'some pixel of the quadrant has this Gaussian among its
+    contributors' in the reference, on quadrants with no ambiguous pixel;
+    no reference contributor lies past a tile's last used list position."""
+    raw, cams, N = batch_case(B=3, N=2500, seed=7)
+    ctx = make_ctx(tile=tile)
+    render(ctx, raw, cams)
+    ntiles = [((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile) for c in cams]
+    tile_base = np.concatenate([[0], np.cumsum(ntiles)])
+    ts = gbr.gbr_inspect(ctx, "tile_start", int(tile_base[-1]) + 1).astype(np.int64)
+    srt = gbr.gbr_inspect(ctx, "sorted", int(ts[-1])).astype(np.int64)
+    cm = gbr.gbr_inspect(ctx, "cmask", int(ts[-1]))
+    last = gbr.gbr_inspect(ctx, "tile_last", int(tile_base[-1])).astype(np.int64)
+    q = tile // 2 if tile > 8 else tile          # quadrant side
+    nq = 4 if tile > 8 else 1
+    checked = 0
+    for b, cam in enumerate(cams):
+        r = raw[b * N:(b + 1) * N]
+        lists, cnt = raster.contributors(r, cam, cap=1024)
+        _, _, _, fl = raster.render(r, cam)
+        ntx = (cam.width + tile - 1) // tile
+        for lt in range(ntiles[b]):
+            g = tile_base[b] + lt
+            tx, ty = lt % ntx, lt // ntx
+            sets, ambiguous = [], []
+            for w in range(nq):
+                x0, y0 = tx * tile + (w & 1) * q, ty * tile + (w >> 1) * q
+                ys = slice(y0, min(y0 + q, cam.height))
+                xs = slice(x0, min(x0 + q, cam.width))
+                sub = lists[ys, xs]
+                sets.append(set(sub[sub >= 0].tolist()))
+                ambiguous.append(bool(fl[ys, xs].any()))
+            for i in range(ts[g], ts[g + 1]):
+                n = srt[i] - b * N
+                want = [n in sets[w] for w in range(nq)]
+                if i - ts[g] >= last[g]:
+                    assert not any(want[w] and not ambiguous[w] for w in range(nq)), (b, lt, i)
+                    continue
+                for w in range(nq):
+                    if not ambiguous[w]:
+                        assert bool((cm[i] >> w) & 1) == want[w], (b, lt, i, w)
+                        checked += 1
+    assert checked > 1000
+    ctx.close()
