@@ -69,7 +69,7 @@ struct gbr_ctx {
   uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_cursor = nullptr, *tile_last = nullptr;
   uint32_t* keys = nullptr;
   uint32_t* sorted = nullptr;
-  uint32_t *order_fwd = nullptr, *order_bwd = nullptr;
+  uint32_t *order_fwd = nullptr, *order_bwd = nullptr, *cls_cnt = nullptr;
   uint8_t* part_flag = nullptr;
   uint8_t* cmask = nullptr;
   // per-frame depth order
@@ -134,7 +134,7 @@ PassArgs make_args(gbr_ctx* c) {
   a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff;
   a.tile_count = c->tile_count; a.tile_start = c->tile_start; a.tile_cursor = c->tile_cursor;
   a.tile_last = c->tile_last;
-  a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd;
+  a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd; a.cls_cnt = c->cls_cnt;
   a.keys = c->keys; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
   a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
@@ -192,7 +192,7 @@ int alloc_buckets(gbr_ctx* c, int64_t n) {
 void free_all(gbr_ctx* c) {
   dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff);
   dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_cursor); dfree(c->tile_last);
-  dfree(c->order_fwd); dfree(c->order_bwd);
+  dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
   dfree(c->keys); dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
@@ -304,14 +304,15 @@ int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
   }
   {
     KTimer t(c, GBR_K_TILE_SORT, s);
-    launch_tile_order(a, false, s);
+    launch_fill_u32(c->cls_cnt, 0u, 66, s);   // both schedules of this pass start empty
+    launch_classify_tiles(a, false, s);
     launch_tile_sort(a, s);
   }
   {
     KTimer t(c, GBR_K_COMPOSITE_FWD, s);
     launch_composite_fwd(a, images, c->chunk, s);
   }
-  launch_tile_order(a, true, s);
+  launch_classify_tiles(a, true, s);
   GBR_HIP(hipGetLastError());
   c->have_raster = true;
   return GBR_OK;
@@ -386,8 +387,9 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->tile_start, c->cap_tiles + 1));
   TRY(dalloc(&c->tile_cursor, c->cap_tiles));
   TRY(dalloc(&c->tile_last, c->cap_tiles));
-  TRY(dalloc(&c->order_fwd, c->cap_tiles));
-  TRY(dalloc(&c->order_bwd, c->cap_tiles));
+  TRY(dalloc(&c->order_fwd, 33 * c->cap_tiles));
+  TRY(dalloc(&c->order_bwd, 33 * c->cap_tiles));
+  TRY(dalloc(&c->cls_cnt, 66));
   TRY(dalloc(&c->minmax, 2LL * c->cap_frames));
   TRY(dalloc(&c->big_count, 1));
   TRY(dalloc(&c->bkeys, c->cap_splats));

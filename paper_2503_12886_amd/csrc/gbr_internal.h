@@ -70,8 +70,9 @@ struct PassArgs {
   uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel
   uint32_t* keys;           // [E] frame-local depth rank of each entry's splat (unsorted)
   uint32_t* sorted;         // [E] splat index in tile order
-  uint32_t* order_fwd;      // [tiles] tiles by descending list length (scheduling only)
-  uint32_t* order_bwd;      // [tiles] tiles by descending entries used by the forward pass
+  uint32_t* order_fwd;      // [33][tiles] tiles by class of list length (scheduling only)
+  uint32_t* order_bwd;      // [33][tiles] tiles by class of entries used by the forward pass
+  uint32_t* cls_cnt;        // [2][33] tiles per class (forward, backward)
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
   int32_t bitmap_words;     // LDS words of the per-tile rank bitmap (max frame size / 32)
@@ -144,6 +145,24 @@ template <int T> struct TileMap {
   __device__ static int ly0(int tid) { return qy(tid) * QW + ((tid & 63) / LPR) * PXW; }
 };
 
+// Longest-first tile scheduling.  Workgroups start in blockIdx order, so the
+// compositing passes visit tiles by descending work: a tile goes to the list
+// of its work class (floor(log2(work)); class 32 = no work, last), and a
+// workgroup finds its tile by walking the 33 class counts.  Scheduling only:
+// a tile's result does not depend on when it runs.
+__device__ __forceinline__ int work_class(uint32_t work) { return work ? 31 - __clz(work) : 32; }
+
+__device__ __forceinline__ int tile_of_rank(const uint32_t* cnt, const uint32_t* lists, int n_tiles, int r) {
+  uint32_t acc = 0;
+  for (int i = 0; i < 33; ++i) {
+    const int c = (i < 32) ? 31 - i : 32;
+    const uint32_t k = cnt[c];
+    if ((uint32_t)r < acc + k) return (int)lists[(int64_t)c * n_tiles + (r - acc)];
+    acc += k;
+  }
+  return -1;
+}
+
 // Sum over the 16 lanes of each row; each row's total lands in its lane 15
 // (lanes 15, 31, 47, 63).  Out-of-row sources read zero.
 __device__ __forceinline__ float row_sum_to15(float v) {
@@ -210,8 +229,8 @@ int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
 void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s);
 void launch_tile_sort(const PassArgs& a, hipStream_t s);
+void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);
-void launch_tile_order(const PassArgs& a, bool backward, hipStream_t s);
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s);

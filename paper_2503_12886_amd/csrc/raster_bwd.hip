@@ -83,7 +83,8 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   __shared__ uint8_t cm[CHUNK];
   __shared__ uint32_t sid[CHUNK];
   if (a.status->overflow) return;
-  const int g = (int)a.order_bwd[blockIdx.x];
+  const int g = tile_of_rank(a.cls_cnt + 33, a.order_bwd, a.n_tiles, blockIdx.x);
+  if (g < 0) return;
   const uint32_t L = a.tile_last[g];
   if (L == 0) return;
   const int b = frame_of_tile(a.frames, a.B, g);

@@ -306,34 +306,34 @@ void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s) 
   hipLaunchKernelGGL(scatter_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a);
 }
 
-// ---------------------------------------------------------------- longest-first tile order
-// Workgroups are dispatched in blockIdx order, so visiting tiles through a
-// list sorted by descending work (classes of floor(log2(work))) starts the
-// long lists first instead of leaving them for the end.  Scheduling only:
-// every tile's result is independent of when it runs.
-__global__ __launch_bounds__(1024) void tile_order_kernel(PassArgs a, int backward) {
-  __shared__ uint32_t cnt[33], cur[33];
+// ---------------------------------------------------------------- tile classes
+// Forward: work = list length; backward: entries the forward pass used.  A
+// workgroup of 1024 tiles counts its tiles per class in LDS, reserves one
+// range per class in the class lists (33 global atomics), and writes its
+// tiles there.
+__global__ __launch_bounds__(1024) void classify_tiles_kernel(PassArgs a, int backward) {
+  __shared__ uint32_t cnt[33], base[33];
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0u;
   __syncthreads();
-  uint32_t* order = backward ? a.order_bwd : a.order_fwd;
-  auto cls = [&](int g) -> int {
-    const uint32_t wk = backward ? a.tile_last[g] : a.tile_start[g + 1] - a.tile_start[g];
-    return wk ? 31 - __clz(wk) : 32;   // class 32 = empty, last
-  };
-  for (int g = threadIdx.x; g < a.n_tiles; g += 1024) atomicAdd(&cnt[cls(g)], 1u);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int c = 31; c >= 0; --c) { cur[c] = run; run += cnt[c]; }
-    cur[32] = run;
+  const int g = blockIdx.x * 1024 + threadIdx.x;
+  int c = -1;
+  uint32_t slot = 0;
+  if (g < a.n_tiles) {
+    const uint32_t work = backward ? a.tile_last[g] : a.tile_start[g + 1] - a.tile_start[g];
+    c = work_class(work);
+    slot = atomicAdd(&cnt[c], 1u);
   }
   __syncthreads();
-  for (int g = threadIdx.x; g < a.n_tiles; g += 1024) order[atomicAdd(&cur[cls(g)], 1u)] = (uint32_t)g;
+  uint32_t* gcnt = a.cls_cnt + (backward ? 33 : 0);
+  if (threadIdx.x < 33) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&gcnt[threadIdx.x], cnt[threadIdx.x]) : 0u;
+  __syncthreads();
+  uint32_t* lists = backward ? a.order_bwd : a.order_fwd;
+  if (c >= 0) lists[(int64_t)c * a.n_tiles + base[c] + slot] = (uint32_t)g;
 }
 
-void launch_tile_order(const PassArgs& a, bool backward, hipStream_t s) {
+void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s) {
   if (a.n_tiles == 0) return;
-  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, a, backward ? 1 : 0);
+  hipLaunchKernelGGL(classify_tiles_kernel, dim3(div_up(a.n_tiles, 1024)), dim3(1024), 0, s, a, backward ? 1 : 0);
 }
 
 // ---------------------------------------------------------------- per-tile order
@@ -347,7 +347,8 @@ __global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
   extern __shared__ uint32_t bitmap[];
   __shared__ uint32_t lw[4];
   if (a.status->overflow) return;
-  const int g = (int)a.order_fwd[blockIdx.x];
+  const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
+  if (g < 0) return;
   const uint32_t start = a.tile_start[g];
   const uint32_t n = a.tile_start[g + 1] - start;
   if (n == 0) return;
@@ -467,7 +468,8 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   __shared__ uint8_t wact[S::NW];
   __shared__ uint32_t s_last;
   if (a.status->overflow) return;
-  const int g = (int)a.order_fwd[blockIdx.x];
+  const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
+  if (g < 0) return;
   const int b = frame_of_tile(a.frames, a.B, g);
   const FrameDev& F = a.frames[b];
   const int lt = g - F.tile_base;
