@@ -214,14 +214,17 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
    pixel range of the alpha >= 1/255 support), 2 tile rects [S][4] i32 (inclusive
    tx0, ty0, tx1, ty1), 3 tile starts [tiles+1] u32 (tile g's entries are
    [start[g], start[g+1]) of the sorted list), 4 sorted entries [entries] u32
-   (global splat index),
+   (global splat index; the complete lists: when the forward pass ordered
+   each tile only as far as it composited, this call completes them first),
    5 per-pixel list position after the last contributor [pixels] u32,
    6 per-pixel final transmittance [pixels] f32, 7 per-tile entries used
    [tiles] u32, 8 per-pixel number of contributing Gaussians [pixels] u32,
    9 per-entry contribution mask [entries] u8: bit w set when some pixel of
    the tile's quadrant w (tiles of 16 and 32 px: quadrants of half the side,
    w = 2 * (row half) + (column half); tiles of 8 px: one quadrant, bit 0)
-   took the entry in the forward pass.
+   took the entry in the forward pass, 10 the sorted entries [entries] u32
+   as the pass left them (each tile's list is valid at least up to its
+   last used position, 7).
    *bytes in: capacity of dst; out: bytes written. */
 int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
 

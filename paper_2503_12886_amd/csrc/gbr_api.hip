@@ -306,7 +306,7 @@ int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
     KTimer t(c, GBR_K_TILE_SORT, s);
     launch_fill_u32(c->cls_cnt, 0u, 66, s);   // both schedules of this pass start empty
     launch_classify_tiles(a, false, s);
-    launch_tile_sort(a, s);
+    if (!fused_sort(a)) launch_tile_sort(a, s);   // else the forward orders each tile lazily
   }
   {
     KTimer t(c, GBR_K_COMPOSITE_FWD, s);
@@ -729,11 +729,18 @@ int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
   StatusDev st;
   GBR_HIP(hipMemcpy(&st, c->d_status, sizeof(st), hipMemcpyDeviceToHost));
   const int64_t entries = std::min<int64_t>((int64_t)st.entries, c->cap_entries);
+  if (what >= 4 && !c->have_raster) return GBR_ERR_STATE;
   switch (what) {
     case 1: src = c->rec; n = c->n_splats * kRecF * 4; break;
     case 2: src = c->rect; n = c->n_splats * 16; break;
     case 3: src = c->tile_start; n = ((int64_t)c->n_tiles + 1) * 4; break;
-    case 4: src = c->sorted; n = entries * 4; break;
+    case 4:   // the complete per-tile lists (the forward may have ordered only what it consumed)
+      if (fused_sort(make_args(c))) {
+        launch_tile_sort(make_args(c), nullptr);
+        GBR_HIP(hipDeviceSynchronize());
+      }
+      src = c->sorted; n = entries * 4; break;
+    case 10: src = c->sorted; n = entries * 4; break;   // as the pass left it
     case 5: src = c->n_iter; n = c->n_pixels * 4; break;
     case 6: src = c->t_final; n = c->n_pixels * 4; break;
     case 7: src = c->tile_last; n = (int64_t)c->n_tiles * 4; break;
@@ -741,7 +748,6 @@ int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
     case 9: src = c->cmask; n = entries; break;
     default: return GBR_ERR_INVALID_ARG;
   }
-  if ((what >= 4) && !c->have_raster) return GBR_ERR_STATE;
   if (*bytes < n) return GBR_ERR_CAPACITY;
   if (n > 0) GBR_HIP(hipMemcpy(dst, src, (size_t)n, hipMemcpyDeviceToHost));
   *bytes = n;

@@ -230,6 +230,8 @@ void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_sp
 void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s);
 void launch_tile_sort(const PassArgs& a, hipStream_t s);
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
+constexpr int kFusedSortMaxWords = 8192;   // bitmap words (32 KB of LDS) up to which the forward sorts lazily
+bool fused_sort(const PassArgs& a);
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);

@@ -457,7 +457,16 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
   return r1.y * g2;
 }
 
-template <int T, int CHUNK>
+// FUSED: the tile's list is put in depth order here, a chunk at a time, as
+// the compositing consumes it (the per-tile sort above, done lazily): the
+// tile's frame-local ranks set bits of an LDS bitmap once, each thread owns a
+// run of bitmap words and knows (block prefix count) where its ranks fall in
+// the sorted order, and each chunk's ranks are emitted from the runs that
+// overlap it.  Entries behind the point where every pixel has stopped are
+// never ordered, mapped to splats or read.  The consumed part of the sorted
+// list is written out for the backward pass.  Used while the bitmap is small
+// (frames of up to kFusedSortMaxWords * 32 visible splats).
+template <int T, int CHUNK, bool FUSED>
 __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
   constexpr int U = 4;                  // entries evaluated together (independent alphas)
@@ -467,6 +476,8 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   __shared__ uint32_t wbits[S::NW][CHUNK / 32];
   __shared__ uint8_t wact[S::NW];
   __shared__ uint32_t s_last;
+  __shared__ uint32_t flw[S::NW];
+  extern __shared__ uint32_t fdyn[];    // FUSED: rank bitmap [W], then the chunk's ranks [CHUNK]
   if (a.status->overflow) return;
   const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
   if (g < 0) return;
@@ -490,12 +501,59 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
     done[p] = !inside[p];
   }
   if (threadIdx.x == 0) s_last = 0;
+  uint32_t vbase = 0, fw0 = 0, fw1 = 0, fbase = 0, fcnt = 0;
+  uint32_t* bitmap = fdyn;
+  uint32_t* list = fdyn;
+  if (FUSED && end > start) {
+    vbase = a.bkt_start[b * a.nbk];
+    const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
+    const uint32_t W = (nv + 31) / 32;
+    list = fdyn + W;
+    for (uint32_t q = threadIdx.x; q < W; q += S::NT) bitmap[q] = 0u;
+    __syncthreads();
+    for (uint32_t i = start + threadIdx.x; i < end; i += S::NT) {
+      const uint32_t r = a.keys[i];
+      atomicOr(&bitmap[r >> 5], 1u << (r & 31u));
+    }
+    __syncthreads();
+    const uint32_t wpt = (W + S::NT - 1) / S::NT;
+    fw0 = min(W, threadIdx.x * wpt);
+    fw1 = min(W, fw0 + wpt);
+    for (uint32_t q = fw0; q < fw1; ++q) fcnt += __popc(bitmap[q]);
+    fbase = block_excl_scan<S::NT>(fcnt, flw, nullptr);
+  }
   for (uint32_t cb = start; cb < end; cb += CHUNK) {
     const int n = (int)min((uint32_t)CHUNK, end - cb);
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += S::NT) {
-      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[cb + i] * kRecF);
-      s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+    if (FUSED) {
+      // ranks of sorted positions [c0, c1) into list[]
+      const uint32_t c0 = cb - start, c1 = c0 + (uint32_t)n;
+      if (fbase < c1 && fbase + fcnt > c0) {
+        uint32_t pos = fbase;
+        for (uint32_t q = fw0; q < fw1 && pos < c1; ++q) {
+          uint32_t bits = bitmap[q];
+          const uint32_t pc = __popc(bits);
+          if (pos + pc <= c0) { pos += pc; continue; }
+          while (bits) {
+            const uint32_t bit = __ffs(bits) - 1u;
+            bits &= bits - 1u;
+            if (pos >= c0 && pos < c1) list[pos - c0] = q * 32u + bit;
+            ++pos;
+          }
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < n; i += S::NT) {
+        const uint32_t sp = a.depth_sorted[vbase + list[i]];
+        a.sorted[cb + i] = sp;
+        const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
+        s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+      }
+    } else {
+      for (int i = threadIdx.x; i < n; i += S::NT) {
+        const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[cb + i] * kRecF);
+        s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+      }
     }
     if (threadIdx.x < U) {                 // padding entries: opacity 0, never taken
       s0[n + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -621,11 +679,20 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   if (threadIdx.x == 0) a.tile_last[g] = s_last;
 }
 
+bool fused_sort(const PassArgs& a) { return a.bitmap_words <= kFusedSortMaxWords; }
+
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s) {
   if (a.n_tiles == 0) return;
   const dim3 grid(a.n_tiles);
-#define GBR_FWD(TT, CC) \
-  hipLaunchKernelGGL((composite_fwd_kernel<TT, CC>), grid, dim3(TileShape<TT>::NT), 0, s, a, images)
+  const bool fused = fused_sort(a);
+  const size_t lds = fused ? (size_t)(std::max(a.bitmap_words, 1) + chunk) * sizeof(uint32_t) : 0;
+#define GBR_FWD(TT, CC)                                                                                         \
+  do {                                                                                                          \
+    if (fused)                                                                                                  \
+      hipLaunchKernelGGL((composite_fwd_kernel<TT, CC, true>), grid, dim3(TileShape<TT>::NT), lds, s, a, images); \
+    else                                                                                                        \
+      hipLaunchKernelGGL((composite_fwd_kernel<TT, CC, false>), grid, dim3(TileShape<TT>::NT), 0, s, a, images);  \
+  } while (0)
 #define GBR_FWD_T(TT)                      \
   if (chunk == 64) GBR_FWD(TT, 64);        \
   else if (chunk == 128) GBR_FWD(TT, 128); \

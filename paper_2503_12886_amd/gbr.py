@@ -355,7 +355,8 @@ def gbr_autotune(ctx: Context, raw, gauss_offsets, cams, images, dimages, draw, 
 
 INSPECT = {"records": (1, np.float32, 12), "rects": (2, np.int32, 4), "tile_start": (3, np.uint32, 1),
            "sorted": (4, np.uint32, 1), "n_iter": (5, np.uint32, 1), "t_final": (6, np.float32, 1),
-           "tile_last": (7, np.uint32, 1), "n_contrib": (8, np.uint32, 1), "cmask": (9, np.uint8, 1)}
+           "tile_last": (7, np.uint32, 1), "n_contrib": (8, np.uint32, 1), "cmask": (9, np.uint8, 1),
+           "sorted_pass": (10, np.uint32, 1)}
 
 
 def gbr_timing(ctx: Context, which: int, enable: bool) -> None:

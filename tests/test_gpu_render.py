@@ -260,3 +260,43 @@ def test_contribution_masks_match_reference_contributors(tile):
                         checked += 1
     assert checked > 1000
     ctx.close()
+
+
+def test_pass_order_is_a_prefix_of_the_complete_lists():
+    """The forward pass orders each tile's list only as far as it composites;
+    what it left must be the leading part of the complete sorted list."""
+    raw, cams, N = batch_case(B=3, N=3000, seed=11)
+    ctx = make_ctx()
+    render(ctx, raw, cams)
+    n_tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    ts = gbr.gbr_inspect(ctx, "tile_start", n_tiles + 1).astype(np.int64)
+    last = gbr.gbr_inspect(ctx, "tile_last", n_tiles).astype(np.int64)
+    part = gbr.gbr_inspect(ctx, "sorted_pass", int(ts[-1])).astype(np.int64)
+    full = gbr.gbr_inspect(ctx, "sorted", int(ts[-1])).astype(np.int64)
+    used = 0
+    for g in range(n_tiles):
+        k = ts[g] + last[g]
+        assert np.array_equal(part[ts[g]:k], full[ts[g]:k]), g
+        used += last[g]
+    assert used > 0
+    ctx.close()
+
+
+def test_large_frame_orders_tiles_in_a_separate_pass():
+    """Frames with more visible splats than the lazy in-kernel ordering holds
+    (its bitmap) take the separate per-tile sort; same images, same lists."""
+    N = 300_000
+    bases = synth.make_scene(N, 2, seed=12)
+    w = synth.make_weights(1, 2, seed=13)
+    cam = synth.fixed_camera(64, 64, 75.0, 0.5, bg=(0.3, 0.2, 0.1))
+    raw = bs.blend(bases, w).astype(np.float32)[0]
+    ctx = make_ctx(max_splats=N, max_entries=1 << 24)
+    imgs, _, _ = render(ctx, raw, [cam])
+    ref, _, _, fl = raster.render(raw, cam)
+    err, masked = compare_image(imgs[0], ref, fl)
+    assert err <= IMAGE_TOL and masked < 0.05, (err, masked)
+    proj = raster.project(raw, cam)
+    ranges, sf, sg, _ = raster.bin_and_sort([proj], [cam], 16)
+    srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
+    assert np.array_equal(srt, sg)
+    ctx.close()
