@@ -205,6 +205,19 @@ __device__ __forceinline__ void fold16x5(float* x, float* y) {   // x[j] <- x[j]
 #pragma unroll
   for (int j = 0; j < 5; ++j) x[j] += y[j];
 }
+__device__ __forceinline__ void fold16x9(float* x, float* y) {   // x[c] <- x[c] + y[c] folded, c < 9
+  asm volatile("s_nop 1\n\t"
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 0, 9) GBR_SWAP_PAIR("v_permlane16_swap_b32", 1, 10)
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 2, 11) GBR_SWAP_PAIR("v_permlane16_swap_b32", 3, 12)
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 4, 13) GBR_SWAP_PAIR("v_permlane16_swap_b32", 5, 14)
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 6, 15) GBR_SWAP_PAIR("v_permlane16_swap_b32", 7, 16)
+               GBR_SWAP_PAIR("v_permlane16_swap_b32", 8, 17) "s_nop 1"
+               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
+                 "+v"(x[8]), "+v"(y[0]), "+v"(y[1]), "+v"(y[2]), "+v"(y[3]), "+v"(y[4]), "+v"(y[5]), "+v"(y[6]),
+                 "+v"(y[7]), "+v"(y[8]));
+#pragma unroll
+  for (int c = 0; c < 9; ++c) x[c] += y[c];
+}
 #undef GBR_SWAP_PAIR
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

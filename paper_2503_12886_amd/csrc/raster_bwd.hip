@@ -74,7 +74,7 @@ template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
   using S = TileShapeB<T>;
-  constexpr int U = 2;                      // entries folded per step (independent alphas)
+  constexpr int U = 4;                      // entries folded per step (independent alphas)
   __shared__ float4 s0[CHUNK];
   __shared__ float4 s1[CHUNK];
   __shared__ float s2[CHUNK];
@@ -151,34 +151,30 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
         unsigned long long who[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          // an absent second entry is folded as an untaken one (zeros, state kept)
+          // an absent entry is folded as an untaken one (zeros, state kept)
           const int i = e[u] < 0 ? e[0] : e[u];
           const uint32_t li = e[u] < 0 ? 0xffffffffu : (uint32_t)(cbeg + i);
           entry_grad<S::PX>(s0[i], s1[i], s2[i], li, pxf, pyf, nit, T_, R0, R1, R2, G0, G1, G2, acc[u], any[u]);
           who[u] = __ballot(any[u]);
         }
-        // Sums of the 2 x 9 partials over the wave's 64 lanes, in a fixed
-        // order: fold lanes 32 apart (value c of both entries into one
-        // register), then 16 apart (two values per register pair), then
-        // four in-row shifts.  Lane 16r + 15 of S[j] ends with value
-        // c = 2j + (r & 1) of entry u = r >> 1.
-        fold32x9(acc[0], acc[1]);                 // acc[0][c]: value c of entry 0 | entry 1
-        float Sj[5] = {acc[0][0], acc[0][2], acc[0][4], acc[0][6], acc[0][8]};
-        float Tj[5] = {acc[0][1], acc[0][3], acc[0][5], acc[0][7], 0.0f};
-        fold16x5(Sj, Tj);                        // Sj[j]: values 2j, 2j+1 of both entries, by row
+        // Sums of the 4 x 9 partials over the wave's 64 lanes, in a fixed
+        // order: fold lanes 32 apart (entries 0|1 and 2|3 into one register
+        // per value), then 16 apart (all four entries of a value in one
+        // register, a row each), then four in-row shifts.  Lane 16r + 15 of
+        // acc[0][c] ends with value c of entry (r >> 1) | ((r & 1) << 1).
+        fold32x9(acc[0], acc[1]);
+        fold32x9(acc[2], acc[3]);
+        fold16x9(acc[0], acc[2]);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) Sj[j] = row_sum_to15(Sj[j]);
+        for (int c = 0; c < 9; ++c) acc[0][c] = row_sum_to15(acc[0][c]);
         if ((lane & 15) == 15) {
-          const int r = lane >> 4, u = r >> 1;
-          const int eu = u ? e[1] : e[0];
-          const unsigned long long wu = u ? who[1] : who[0];
+          const int r = lane >> 4, u = (r >> 1) | ((r & 1) << 1);
+          const int eu = u == 0 ? e[0] : u == 1 ? e[1] : u == 2 ? e[2] : e[3];
+          const unsigned long long wu = u == 0 ? who[0] : u == 1 ? who[1] : u == 2 ? who[2] : who[3];
           if (u < cnt && wu != 0ull) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) {
-              const int c = 2 * j + (r & 1);
-              if (c < 9) red[eu][w][c] = Sj[j];
-            }
-            if ((r & 1) == 0) wany8[eu * 4 + w] = 1;
+            for (int c = 0; c < 9; ++c) red[eu][w][c] = acc[0][c];
+            wany8[eu * 4 + w] = 1;
           }
         }
       }
