@@ -24,8 +24,12 @@ __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, f
 }
 
 // Per-entry partial, summed over the tile's pixels:
-//   (d mx, d my, d ca, d cb, d cc, d opacity, d r, d g, d b)
-// where ca, cb, cc are the log2-scaled conic coefficients of the record.
+//   (sum dpw dx, sum dpw dy, d ca, d cb, d cc, d opacity, d r, d g, d b)
+// where ca, cb, cc are the log2-scaled conic coefficients of the record,
+// dpw = dL/d(power) at a pixel and (dx, dy) its offset from the mean; the
+// mean's gradient -(2 ca, cb; cb, 2 cc) (sum dpw dx, sum dpw dy) is formed
+// once per splat, after the sums.  Along the traversal each lane keeps only
+// the transmittance and <colour behind, dL/dout>.
 // A wave's sum over its lanes is taken in a fixed order (lane folds, then
 // in-row shifts); the block then adds its waves in order and writes the
 // entry's partial, by emission slot, only if some pixel contributed; a byte
@@ -37,8 +41,8 @@ __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, f
 template <int PX>
 __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, const float cbl, const uint32_t li,
                                            const float* pxf, const float* pyf, const uint32_t* nit, float* T_,
-                                           float* R0, float* R1, float* R2, const float* G0, const float* G1,
-                                           const float* G2, float* acc, bool& any) {
+                                           float* SG, const float* G0, const float* G1, const float* G2,
+                                           float* acc, bool& any) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
   any = false;
@@ -53,20 +57,20 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
     const float Ti = T_[p] * inv;                     // transmittance in front of this entry
     const float wgt = take ? al * Ti : 0.0f;
     acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
-    const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];
-    const float rg = R0[p] * G0[p] + R1[p] * G1[p] + R2[p] * G2[p];
-    const float dal = Ti * cg - rg * inv;             // d out / d alpha
-    R0[p] += wgt * r1.z; R1[p] += wgt * r1.w; R2[p] += wgt * cbl;
+    const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];   // <colour, dL/dout>
+    const float dal = Ti * cg - SG[p] * inv;          // d out / d alpha
+    SG[p] += wgt * cg;                                // <colour behind, dL/dout>
     T_[p] = take ? Ti : T_[p];
     // min(0.99, .) passes the gradient only below the clamp
     const float da = (take && a0 < kAlphaMax) ? dal : 0.0f;
     acc[5] += g2 * da;
     const float dpw = (pwr > 0.0f) ? 0.0f : da * a0 * (float)kLn2;
-    acc[2] += dpw * dx * dx;
-    acc[3] += dpw * dx * dy;
-    acc[4] += dpw * dy * dy;
-    acc[0] -= dpw * (2.0f * r0.z * dx + r0.w * dy);
-    acc[1] -= dpw * (r0.w * dx + 2.0f * r1.x * dy);
+    const float p1 = dpw * dx, p2 = dpw * dy;
+    acc[0] += p1;
+    acc[1] += p2;
+    acc[2] += p1 * dx;
+    acc[3] += p1 * dy;
+    acc[4] += p2 * dy;
   }
 }
 
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   const uint32_t start = a.tile_start[g];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lx0 = S::lx0(threadIdx.x), ly0 = S::ly0(threadIdx.x);
-  float T_[S::PX], R0[S::PX], R1[S::PX], R2[S::PX], G0[S::PX], G1[S::PX], G2[S::PX];
+  float T_[S::PX], SG[S::PX], G0[S::PX], G1[S::PX], G2[S::PX];
   uint32_t nit[S::PX];
   float pxf[S::PX], pyf[S::PX];
   const float* img_g = dimages + F.pix_base * 3;
@@ -104,14 +108,14 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     const int px = tx * T + lx0 + (p % S::PXW), py = ty * T + ly0 + (p / S::PXW);
     pxf[p] = (float)px + 0.5f;
     pyf[p] = (float)py + 0.5f;
-    nit[p] = 0; T_[p] = 1.0f; R0[p] = R1[p] = R2[p] = 0.0f; G0[p] = G1[p] = G2[p] = 0.0f;
+    nit[p] = 0; T_[p] = 1.0f; SG[p] = 0.0f; G0[p] = G1[p] = G2[p] = 0.0f;
     if (px < F.W && py < F.H) {
       const int64_t pix = (int64_t)py * F.W + px;
       nit[p] = a.n_iter[F.pix_base + pix];
       T_[p] = a.t_final[F.pix_base + pix];
       G0[p] = img_g[pix]; G1[p] = img_g[hw + pix]; G2[p] = img_g[2 * hw + pix];
-      // suffix colour behind the current entry, starts as T_end * background
-      R0[p] = T_[p] * F.bg[0]; R1[p] = T_[p] * F.bg[1]; R2[p] = T_[p] * F.bg[2];
+      // <colour behind the current entry, dL/dout>, starts at <T_end * background, dL/dout>
+      SG[p] = T_[p] * (F.bg[0] * G0[p] + F.bg[1] * G1[p] + F.bg[2] * G2[p]);
     }
   }
   uint8_t* wany8 = reinterpret_cast<uint8_t*>(wany);
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
           // an absent entry is folded as an untaken one (zeros, state kept)
           const int i = e[u] < 0 ? e[0] : e[u];
           const uint32_t li = e[u] < 0 ? 0xffffffffu : (uint32_t)(cbeg + i);
-          entry_grad<S::PX>(s0[i], s1[i], s2[i], li, pxf, pyf, nit, T_, R0, R1, R2, G0, G1, G2, acc[u], any[u]);
+          entry_grad<S::PX>(s0[i], s1[i], s2[i], li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc[u], any[u]);
           who[u] = __ballot(any[u]);
         }
         // Sums of the 4 x 9 partials over the wave's 64 lanes, in a fixed
@@ -389,7 +393,10 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
     djy += dW[3 + k] * R[3 + k]; duy += dW[3 + k] * R[6 + k];
   }
   // jx = fx/tz, ux = -fx tx/tz^2, jy = fy/tz, uy = -fy ty/tz^2; mean = (fx tx/tz + cx, fy ty/tz + cy)
-  const double dmx = acc[0], dmy = acc[1];
+  // mean: d power / d mean = -(2 ca dx + cb dy, cb dx + 2 cc dy), summed as (sum dpw dx, sum dpw dy)
+  const double ca = -0.5 * kLog2e * QA, cbq = -kLog2e * QB, cc = -0.5 * kLog2e * QC;
+  const double dmx = -(2.0 * ca * (double)acc[0] + cbq * (double)acc[1]);
+  const double dmy = -(cbq * (double)acc[0] + 2.0 * cc * (double)acc[1]);
   double dtx = dux * (-fx * iz * iz) + dmx * fx * iz;
   double dty = duy * (-fy * iz * iz) + dmy * fy * iz;
   double dtz = djx * (-fx * iz * iz) + dux * (2.0 * fx * tx * iz * iz * iz) + djy * (-fy * iz * iz) +
