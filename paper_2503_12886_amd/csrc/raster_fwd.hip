@@ -287,9 +287,16 @@ __global__ __launch_bounds__(256) void scatter_kernel(PassArgs a) {
     for (int ty = r.y; ty <= r.w; ++ty)
       for (int tx = r.x; tx <= r.z; ++tx) atomicAdd(&hist[ty * F.ntx + tx], 1u);
     __syncthreads();
-    for (int t = threadIdx.x; t < F.n_tiles; t += 256) {
-      const uint32_t c = hist[t];
-      if (c) hist[t] = atomicAdd(&a.tile_cursor[F.tile_base + t], c);
+    // one global reservation per touched tile, four tiles per thread in flight together
+    for (int t0 = threadIdx.x; t0 < F.n_tiles; t0 += 4 * 256) {
+      uint32_t c[4], base[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c[u] = (t0 + u * 256 < F.n_tiles) ? hist[t0 + u * 256] : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) base[u] = c[u] ? atomicAdd(&a.tile_cursor[F.tile_base + t0 + u * 256], c[u]) : 0u;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (c[u]) hist[t0 + u * 256] = base[u];
     }
     __syncthreads();
   }
