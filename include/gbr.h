@@ -235,8 +235,8 @@ int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
    (call after the stream has been synchronised, e.g. by gbr_query_status). */
 #define GBR_K_BLEND 0
 #define GBR_K_PREPROCESS 1
-#define GBR_K_BINNING 2      /* splat-offset scan + scatter of tile entries */
-#define GBR_K_TILE_SORT 3
+#define GBR_K_BINNING 2      /* splat-offset scan + per-tile rank bitmap rows */
+#define GBR_K_TILE_SORT 3    /* tile scheduling classes (the lists are ordered inside the forward pass) */
 #define GBR_K_COMPOSITE_FWD 4
 #define GBR_K_COMPOSITE_BWD 5
 #define GBR_K_GATHER_BWD 6

@@ -19,7 +19,7 @@ constexpr int kSlots = 5;          // pinned frame-table slots; the last one is 
 constexpr int kCaptureSlot = kSlots - 1;
 constexpr int kMaxK = 63;
 constexpr int kMaxFramesHard = 4096;
-constexpr int64_t kMaxBitmapWords = 32768;   // 128 KB of LDS: frames of up to 1,048,576 Gaussians
+constexpr int64_t kMaxBitmapWords = 32768;   // 128 KB bitmap row per tile: frames of up to 1,048,576 Gaussians
 
 #define GBR_HIP(x)                           \
   do {                                       \
@@ -45,7 +45,7 @@ void dfree(T*& p) {
 // counts/cursors, per-frame depth ranges, the large-bucket list, the status.
 __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n_tiles) { a.tile_count[i] = 0u; a.tile_cursor[i] = 0u; }
+  if (i < a.n_tiles) a.tile_count[i] = 0u;
   if (i < n_bkt) { a.bkt_count[i] = 0u; a.bkt_cursor[i] = 0u; }
   if (i < a.B) { a.minmax[2 * i] = 0xffffffffu; a.minmax[2 * i + 1] = 0u; }
   if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
@@ -66,8 +66,9 @@ struct gbr_ctx {
   float* rec = nullptr;
   int4* rect = nullptr;
   uint32_t *cnt = nullptr, *soff = nullptr;
-  uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_cursor = nullptr, *tile_last = nullptr;
-  uint32_t* keys = nullptr;
+  uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_last = nullptr;
+  uint32_t* tbits = nullptr;        // [cap_tbits] per-tile rank bitmap rows
+  int64_t cap_tbits = 0;
   uint32_t* sorted = nullptr;
   uint32_t *order_fwd = nullptr, *order_bwd = nullptr, *cls_cnt = nullptr;
   uint8_t* part_flag = nullptr;
@@ -132,13 +133,12 @@ PassArgs make_args(gbr_ctx* c) {
   a.cap_entries = c->cap_entries;
   a.status = c->d_status;
   a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff;
-  a.tile_count = c->tile_count; a.tile_start = c->tile_start; a.tile_cursor = c->tile_cursor;
+  a.tile_count = c->tile_count; a.tile_start = c->tile_start;
   a.tile_last = c->tile_last;
   a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd; a.cls_cnt = c->cls_cnt;
-  a.keys = c->keys; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
+  a.tbits = c->tbits; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
   a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
-  a.sort_list_cap = std::max(0, std::min(4096, 32768 - std::max(a.bitmap_words, 1)));
   a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_start = c->bkt_start; a.bkt_cursor = c->bkt_cursor;
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
   a.big_list = c->big_list; a.big_count = c->big_count;
@@ -167,9 +167,8 @@ int check_tiling(int tile, int chunk) {
 }
 
 int alloc_entries(gbr_ctx* c, int64_t cap) {
-  dfree(c->keys); dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
+  dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   int rc = GBR_OK;
-  if ((rc = dalloc(&c->keys, cap))) return rc;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
   if ((rc = dalloc(&c->part_flag, cap + 64))) return rc;   // gather reads 64-entry flag windows
   if ((rc = dalloc(&c->cmask, cap))) return rc;
@@ -191,9 +190,9 @@ int alloc_buckets(gbr_ctx* c, int64_t n) {
 
 void free_all(gbr_ctx* c) {
   dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff);
-  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_cursor); dfree(c->tile_last);
+  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->tbits);
   dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
-  dfree(c->keys); dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
+  dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
@@ -300,13 +299,14 @@ int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
   {
     KTimer t(c, GBR_K_BINNING, s);
     launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
-    launch_scatter(a, c->max_frame_splats, s);
+    int mft = 0;
+    for (const FrameDev& f : c->frames_host) mft = std::max(mft, f.n_tiles);
+    launch_bitmap_rows(a, c->max_frame_splats, mft, s);
   }
   {
     KTimer t(c, GBR_K_TILE_SORT, s);
     launch_fill_u32(c->cls_cnt, 0u, 66, s);   // both schedules of this pass start empty
     launch_classify_tiles(a, false, s);
-    if (!fused_sort(a)) launch_tile_sort(a, s);   // else the forward orders each tile lazily
   }
   {
     KTimer t(c, GBR_K_COMPOSITE_FWD, s);
@@ -332,6 +332,16 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
     GBR_HIP(hipDeviceSynchronize());
     rc = alloc_buckets(c, (int64_t)B * nbk);
     if (rc) return rc;
+  }
+  const int64_t need_bits = std::max<int64_t>(1, (int64_t)nt * ((mfs + 31) / 32));
+  if (need_bits > c->cap_tbits) {
+    if (c->capturing) return GBR_ERR_STATE;
+    GBR_HIP(hipDeviceSynchronize());
+    dfree(c->tbits);
+    c->cap_tbits = 0;
+    rc = dalloc(&c->tbits, need_bits);
+    if (rc) return rc;
+    c->cap_tbits = need_bits;
   }
   c->frames_host.swap(fr);
   c->B = B; c->n_tiles = nt; c->n_pixels = np; c->n_splats = ns; c->max_frame_splats = mfs;
@@ -385,7 +395,6 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->soff, c->cap_splats + 1));
   TRY(dalloc(&c->tile_count, c->cap_tiles));
   TRY(dalloc(&c->tile_start, c->cap_tiles + 1));
-  TRY(dalloc(&c->tile_cursor, c->cap_tiles));
   TRY(dalloc(&c->tile_last, c->cap_tiles));
   TRY(dalloc(&c->order_fwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->order_bwd, 33 * c->cap_tiles));
@@ -735,10 +744,8 @@ int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
     case 2: src = c->rect; n = c->n_splats * 16; break;
     case 3: src = c->tile_start; n = ((int64_t)c->n_tiles + 1) * 4; break;
     case 4:   // the complete per-tile lists (the forward may have ordered only what it consumed)
-      if (fused_sort(make_args(c))) {
-        launch_tile_sort(make_args(c), nullptr);
-        GBR_HIP(hipDeviceSynchronize());
-      }
+      launch_tile_lists(make_args(c), nullptr);
+      GBR_HIP(hipDeviceSynchronize());
       src = c->sorted; n = entries * 4; break;
     case 10: src = c->sorted; n = entries * 4; break;   // as the pass left it
     case 5: src = c->n_iter; n = c->n_pixels * 4; break;

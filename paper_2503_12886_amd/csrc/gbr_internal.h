@@ -66,17 +66,15 @@ struct PassArgs {
   // tile stage
   uint32_t* tile_count;     // [tiles]
   uint32_t* tile_start;     // [tiles + 1]
-  uint32_t* tile_cursor;    // [tiles]
   uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel
-  uint32_t* keys;           // [E] frame-local depth rank of each entry's splat (unsorted)
+  uint32_t* tbits;          // [tiles][bitmap_words] per-tile bitmaps of frame-local depth ranks
   uint32_t* sorted;         // [E] splat index in tile order
   uint32_t* order_fwd;      // [33][tiles] tiles by class of list length (scheduling only)
   uint32_t* order_bwd;      // [33][tiles] tiles by class of entries used by the forward pass
   uint32_t* cls_cnt;        // [2][33] tiles per class (forward, backward)
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
-  int32_t bitmap_words;     // LDS words of the per-tile rank bitmap (max frame size / 32)
-  int32_t sort_list_cap;    // LDS words after the bitmap for a tile's sorted ranks (longer lists go via memory)
+  int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32)
   uint32_t* minmax;         // [B][2] min / max binary32 depth bits of the frame's valid splats
   uint32_t* bkt_count;      // [B * nbk]
   uint32_t* bkt_start;      // [B * nbk + 1] exclusive scan; frame b's valid splats start at bkt_start[b * nbk]
@@ -240,11 +238,10 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blo
                      int64_t cap_check, unsigned long long* total_out, hipStream_t s);
 int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
-void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s);
-void launch_tile_sort(const PassArgs& a, hipStream_t s);
+void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s);
+void launch_tile_lists(const PassArgs& a, hipStream_t s);
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
-constexpr int kFusedSortMaxWords = 8192;   // bitmap words (32 KB of LDS) up to which the forward sorts lazily
-bool fused_sort(const PassArgs& a);
+
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);

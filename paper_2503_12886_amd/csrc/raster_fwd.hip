@@ -259,58 +259,74 @@ void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_sp
   hipLaunchKernelGGL(preprocess_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a, raw);
 }
 
-// ---------------------------------------------------------------- scatter
-// Each block reserves, per tile, one contiguous range of slots for all its
-// Gaussians' entries (one global atomic per tile and block), then hands out
-// slots inside the range with LDS atomics.  An entry is its splat's
-// frame-local depth rank; the order inside a tile is arbitrary here and the
-// per-tile sort that follows makes it unique.
-__global__ __launch_bounds__(256) void scatter_kernel(PassArgs a) {
-  __shared__ uint32_t hist[kMaxFrameTilesLds];
-  if (a.status->overflow) return;
+// ---------------------------------------------------------------- binning
+// A tile's list is the set of frame-local depth ranks of the splats that
+// overlap it.  Each tile owns a row of bitmap_words words (bit r = rank r);
+// reading a row's set bits in ascending order gives the tile's list in depth
+// order, so no entry array is scattered or sorted.
+//
+// Rows are built by rank: workgroup j of a frame takes the splats of ranks
+// [256 j, 256 j + 256), which own bitmap words [8 j, 8 j + 8) of every row.
+// Each splat ORs its bit into an LDS copy of those 8 words for every tile of
+// its rect; the workgroup then stores the 8 words of every tile of the frame
+// (zeros included), so every word of every row is written by exactly one
+// workgroup and nothing needs clearing.  Frames with more tiles than the LDS
+// copy holds set the bits in memory with atomics after clearing the rows.
+constexpr int kRowBuildWords = 16384;        // LDS words: 8 per tile, frames of up to 2048 tiles
+
+__global__ __launch_bounds__(256) void bitmap_rows_kernel(PassArgs a) {
+  __shared__ uint32_t words[kRowBuildWords];
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if ((int64_t)blockIdx.x * 256 >= F.gauss_count) return;
-  const bool lds = F.n_tiles <= kMaxFrameTilesLds;
-  if (lds)
-    for (int t = threadIdx.x; t < F.n_tiles; t += 256) hist[t] = 0u;
+  const uint32_t vbase = a.bkt_start[b * a.nbk];
+  const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
+  const uint32_t r0 = blockIdx.x * 256u;
+  if (r0 >= nv || a.status->overflow) return;
+  const int nw = F.n_tiles * 8;
+  for (int q = threadIdx.x; q < nw; q += 256) words[q] = 0u;
   __syncthreads();
-  int4 r = make_int4(0, 0, -1, -1);
-  int64_t s = F.gauss_base + n;
-  uint32_t key = 0;
-  if (n < F.gauss_count && a.cnt[s] > 0) {
-    r = a.rect[s];
-    key = a.rank[s];
+  const uint32_t r = r0 + threadIdx.x;
+  if (r < nv) {
+    const uint32_t s = a.depth_sorted[vbase + r];
+    const int4 rc = a.rect[s];
+    const uint32_t bit = 1u << (r & 31u);
+    const int wl = (int)((r >> 5) & 7u);
+    for (int ty = rc.y; ty <= rc.w; ++ty)
+      for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(&words[(ty * F.ntx + tx) * 8 + wl], bit);
   }
-  if (lds) {
-    for (int ty = r.y; ty <= r.w; ++ty)
-      for (int tx = r.x; tx <= r.z; ++tx) atomicAdd(&hist[ty * F.ntx + tx], 1u);
-    __syncthreads();
-    // one global reservation per touched tile, four tiles per thread in flight together
-    for (int t0 = threadIdx.x; t0 < F.n_tiles; t0 += 4 * 256) {
-      uint32_t c[4], base[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) c[u] = (t0 + u * 256 < F.n_tiles) ? hist[t0 + u * 256] : 0u;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) base[u] = c[u] ? atomicAdd(&a.tile_cursor[F.tile_base + t0 + u * 256], c[u]) : 0u;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (c[u]) hist[t0 + u * 256] = base[u];
-    }
-    __syncthreads();
+  __syncthreads();
+  uint32_t* rows = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (r0 >> 5);
+  const uint32_t wmax = (uint32_t)a.bitmap_words - (r0 >> 5);   // words of the row left from 8 j
+  for (int q = threadIdx.x; q < nw; q += 256) {
+    const int t = q >> 3, k = q & 7;
+    if ((uint32_t)k < wmax) rows[(int64_t)t * a.bitmap_words + k] = words[q];
   }
-  for (int ty = r.y; ty <= r.w; ++ty)
-    for (int tx = r.x; tx <= r.z; ++tx) {
-      const int t = ty * F.ntx + tx;
-      const uint32_t slot = lds ? atomicAdd(&hist[t], 1u) : atomicAdd(&a.tile_cursor[F.tile_base + t], 1u);
-      a.keys[(uint64_t)a.tile_start[F.tile_base + t] + slot] = key;
-    }
 }
 
-void launch_scatter(const PassArgs& a, int64_t max_frame_splats, hipStream_t s) {
+__global__ __launch_bounds__(256) void bitmap_rows_atomic_kernel(PassArgs a) {
+  const int b = blockIdx.y;
+  const FrameDev& F = a.frames[b];
+  const uint32_t vbase = a.bkt_start[b * a.nbk];
+  const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
+  const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+  if (r >= nv || a.status->overflow) return;
+  const uint32_t s = a.depth_sorted[vbase + r];
+  const int4 rc = a.rect[s];
+  const uint32_t bit = 1u << (r & 31u);
+  uint32_t* base = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (r >> 5);
+  for (int ty = rc.y; ty <= rc.w; ++ty)
+    for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(base + (int64_t)(ty * F.ntx + tx) * a.bitmap_words, bit);
+}
+
+void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s) {
   if (a.B == 0 || max_frame_splats == 0) return;
-  hipLaunchKernelGGL(scatter_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a);
+  const dim3 grid(div_up(max_frame_splats, 256), a.B);
+  if ((int64_t)max_frame_tiles * 8 <= kRowBuildWords) {
+    hipLaunchKernelGGL(bitmap_rows_kernel, grid, dim3(256), 0, s, a);
+  } else {
+    launch_fill_u32(a.tbits, 0u, (int64_t)a.n_tiles * a.bitmap_words, s);
+    hipLaunchKernelGGL(bitmap_rows_atomic_kernel, grid, dim3(256), 0, s, a);
+  }
 }
 
 // ---------------------------------------------------------------- tile classes
@@ -343,79 +359,41 @@ void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s) {
   hipLaunchKernelGGL(classify_tiles_kernel, dim3(div_up(a.n_tiles, 1024)), dim3(1024), 0, s, a, backward ? 1 : 0);
 }
 
-// ---------------------------------------------------------------- per-tile order
-// Every splat of a frame has a unique frame-local rank in (depth, index)
-// order (computed once per frame by the depth-order stage), and a tile's
-// list is a subset of its frame's splats.  Sorting the list is therefore set
-// membership: mark the tile's ranks in an LDS bitmap, prefix-count the set
-// bits, and read them back in ascending order.  O(frame size / 32 + entries)
-// per tile, exact and deterministic.
-__global__ __launch_bounds__(256) void tile_sort_kernel(PassArgs a) {
-  extern __shared__ uint32_t bitmap[];
+// ---------------------------------------------------------------- complete lists
+// The whole sorted list of every tile, from its bitmap row: each thread owns
+// a run of words, a block prefix count places its set bits, which it writes
+// as splat indices (rank -> splat through the frame's depth order).  The
+// forward pass orders each tile only as far as it composites; this pass
+// completes the lists on request.
+__global__ __launch_bounds__(256) void tile_lists_kernel(PassArgs a) {
   __shared__ uint32_t lw[4];
   if (a.status->overflow) return;
-  const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
-  if (g < 0) return;
+  const int g = blockIdx.x;
   const uint32_t start = a.tile_start[g];
-  const uint32_t n = a.tile_start[g + 1] - start;
-  if (n == 0) return;
+  if (a.tile_start[g + 1] == start) return;
   const int b = frame_of_tile(a.frames, a.B, g);
-  const FrameDev& F = a.frames[b];
   const uint32_t vbase = a.bkt_start[b * a.nbk];
   const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
-  const int W = (int)((nv + 31) / 32);
-  for (int w = threadIdx.x; w < W; w += 256) bitmap[w] = 0u;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += 256) {
-    const uint32_t r = a.keys[start + i];
-    atomicOr(&bitmap[r >> 5], 1u << (r & 31u));
-  }
-  __syncthreads();
-  const int wpt = (W + 255) / 256;
-  const int w0 = threadIdx.x * wpt, w1 = min(W, w0 + wpt);
+  const uint32_t W = (nv + 31) / 32;
+  const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  const uint32_t wpt = (W + 255) / 256;
+  const uint32_t w0 = min(W, threadIdx.x * wpt), w1 = min(W, w0 + wpt);
   uint32_t c = 0;
-  for (int w = w0; w < w1; ++w) c += __popc(bitmap[w]);
-  const uint32_t first = block_excl_scan<256>(c, lw, nullptr);
-  // ranks in ascending order (each thread emits the set bits of its words):
-  // into LDS after the bitmap when the list fits, else through the output
-  uint32_t* list = (n <= (uint32_t)a.sort_list_cap) ? bitmap + W : a.sorted + start;
-  uint32_t out = first;
-  for (int w = w0; w < w1; ++w) {
-    uint32_t bits = bitmap[w];
+  for (uint32_t w = w0; w < w1; ++w) c += __popc(row[w]);
+  uint32_t out = start + block_excl_scan<256>(c, lw, nullptr);
+  for (uint32_t w = w0; w < w1; ++w) {
+    uint32_t bits = row[w];
     while (bits) {
       const uint32_t bit = __ffs(bits) - 1u;
       bits &= bits - 1u;
-      list[out++] = (uint32_t)w * 32u + bit;
-    }
-  }
-  __threadfence_block();
-  __syncthreads();
-  // rank -> splat, one entry per thread
-  for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 4 * 256) {
-    uint32_t sp[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t i = i0 + u * 256;
-      sp[u] = (i < n) ? a.depth_sorted[vbase + list[i]] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t i = i0 + u * 256;
-      if (i < n) a.sorted[start + i] = sp[u];
+      a.sorted[out++] = a.depth_sorted[vbase + w * 32u + bit];
     }
   }
 }
 
-void launch_tile_sort(const PassArgs& a, hipStream_t s) {
+void launch_tile_lists(const PassArgs& a, hipStream_t s) {
   if (a.n_tiles == 0) return;
-  const size_t lds = (size_t)(std::max(a.bitmap_words, 1) + a.sort_list_cap) * sizeof(uint32_t);
-  static bool attr_set = false;   // more than 64 KB of dynamic LDS must be requested explicitly
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_sort_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 32768 * (int)sizeof(uint32_t));
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(tile_sort_kernel, dim3(a.n_tiles), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(tile_lists_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------- compositing
@@ -464,16 +442,14 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
   return r1.y * g2;
 }
 
-// FUSED: the tile's list is put in depth order here, a chunk at a time, as
-// the compositing consumes it (the per-tile sort above, done lazily): the
-// tile's frame-local ranks set bits of an LDS bitmap once, each thread owns a
-// run of bitmap words and knows (block prefix count) where its ranks fall in
-// the sorted order, and each chunk's ranks are emitted from the runs that
-// overlap it.  Entries behind the point where every pixel has stopped are
-// never ordered, mapped to splats or read.  The consumed part of the sorted
-// list is written out for the backward pass.  Used while the bitmap is small
-// (frames of up to kFusedSortMaxWords * 32 visible splats).
-template <int T, int CHUNK, bool FUSED>
+// The tile's list is read in depth order from its bitmap row, a chunk at a
+// time, as the compositing consumes it: each thread owns a run of the row's
+// words and knows (block prefix count) where its ranks fall in the sorted
+// order, and each chunk's ranks are emitted from the runs that overlap it.
+// Entries behind the point where every pixel has stopped are never ordered,
+// mapped to splats or read.  The consumed part of the sorted list is written
+// out for the backward pass.
+template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
   constexpr int U = 4;                  // entries evaluated together (independent alphas)
@@ -484,7 +460,7 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   __shared__ uint8_t wact[S::NW];
   __shared__ uint32_t s_last;
   __shared__ uint32_t flw[S::NW];
-  extern __shared__ uint32_t fdyn[];    // FUSED: rank bitmap [W], then the chunk's ranks [CHUNK]
+  __shared__ uint32_t list[CHUNK];      // ranks of the chunk being staged
   if (a.status->overflow) return;
   const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
   if (g < 0) return;
@@ -509,36 +485,27 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   }
   if (threadIdx.x == 0) s_last = 0;
   uint32_t vbase = 0, fw0 = 0, fw1 = 0, fbase = 0, fcnt = 0;
-  uint32_t* bitmap = fdyn;
-  uint32_t* list = fdyn;
-  if (FUSED && end > start) {
+  const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  if (end > start) {
     vbase = a.bkt_start[b * a.nbk];
     const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
     const uint32_t W = (nv + 31) / 32;
-    list = fdyn + W;
-    for (uint32_t q = threadIdx.x; q < W; q += S::NT) bitmap[q] = 0u;
-    __syncthreads();
-    for (uint32_t i = start + threadIdx.x; i < end; i += S::NT) {
-      const uint32_t r = a.keys[i];
-      atomicOr(&bitmap[r >> 5], 1u << (r & 31u));
-    }
-    __syncthreads();
     const uint32_t wpt = (W + S::NT - 1) / S::NT;
     fw0 = min(W, threadIdx.x * wpt);
     fw1 = min(W, fw0 + wpt);
-    for (uint32_t q = fw0; q < fw1; ++q) fcnt += __popc(bitmap[q]);
+    for (uint32_t q = fw0; q < fw1; ++q) fcnt += __popc(row[q]);
     fbase = block_excl_scan<S::NT>(fcnt, flw, nullptr);
   }
   for (uint32_t cb = start; cb < end; cb += CHUNK) {
     const int n = (int)min((uint32_t)CHUNK, end - cb);
     __syncthreads();
-    if (FUSED) {
+    {
       // ranks of sorted positions [c0, c1) into list[]
       const uint32_t c0 = cb - start, c1 = c0 + (uint32_t)n;
       if (fbase < c1 && fbase + fcnt > c0) {
         uint32_t pos = fbase;
         for (uint32_t q = fw0; q < fw1 && pos < c1; ++q) {
-          uint32_t bits = bitmap[q];
+          uint32_t bits = row[q];
           const uint32_t pc = __popc(bits);
           if (pos + pc <= c0) { pos += pc; continue; }
           while (bits) {
@@ -554,11 +521,6 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
         const uint32_t sp = a.depth_sorted[vbase + list[i]];
         a.sorted[cb + i] = sp;
         const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
-        s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
-      }
-    } else {
-      for (int i = threadIdx.x; i < n; i += S::NT) {
-        const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[cb + i] * kRecF);
         s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
       }
     }
@@ -686,20 +648,11 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   if (threadIdx.x == 0) a.tile_last[g] = s_last;
 }
 
-bool fused_sort(const PassArgs& a) { return a.bitmap_words <= kFusedSortMaxWords; }
-
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s) {
   if (a.n_tiles == 0) return;
   const dim3 grid(a.n_tiles);
-  const bool fused = fused_sort(a);
-  const size_t lds = fused ? (size_t)(std::max(a.bitmap_words, 1) + chunk) * sizeof(uint32_t) : 0;
-#define GBR_FWD(TT, CC)                                                                                         \
-  do {                                                                                                          \
-    if (fused)                                                                                                  \
-      hipLaunchKernelGGL((composite_fwd_kernel<TT, CC, true>), grid, dim3(TileShape<TT>::NT), lds, s, a, images); \
-    else                                                                                                        \
-      hipLaunchKernelGGL((composite_fwd_kernel<TT, CC, false>), grid, dim3(TileShape<TT>::NT), 0, s, a, images);  \
-  } while (0)
+#define GBR_FWD(TT, CC) \
+  hipLaunchKernelGGL((composite_fwd_kernel<TT, CC>), grid, dim3(TileShape<TT>::NT), 0, s, a, images)
 #define GBR_FWD_T(TT)                      \
   if (chunk == 64) GBR_FWD(TT, 64);        \
   else if (chunk == 128) GBR_FWD(TT, 128); \

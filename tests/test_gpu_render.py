@@ -300,3 +300,27 @@ def test_large_frame_orders_tiles_in_a_separate_pass():
     srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
     assert np.array_equal(srt, sg)
     ctx.close()
+
+
+def test_frames_with_many_tiles_build_rows_in_memory():
+    """A frame with more tiles than the workgroup's LDS copy of its bitmap
+    words holds (tile 8, 400 x 360 = 2250 tiles) sets its rows' bits in
+    memory; lists and image as the reference."""
+    N = 3000
+    bases = synth.make_scene(N, 2, seed=14)
+    w = synth.make_weights(1, 2, seed=15)
+    cam = synth.fixed_camera(400, 360, 400.0, 0.5, bg=(0.5, 0.4, 0.3))
+    raw = bs.blend(bases, w).astype(np.float32)[0]
+    ctx = make_ctx(tile=8)
+    imgs, _, _ = render(ctx, raw, [cam])
+    ref, _, _, fl = raster.render(raw, cam)
+    err, masked = compare_image(imgs[0], ref, fl)
+    assert err <= IMAGE_TOL and masked < 0.02, (err, masked)
+    proj = raster.project(raw, cam)
+    ranges, sf, sg, _ = raster.bin_and_sort([proj], [cam], 8)
+    assert len(ranges) > 2048
+    ts = gbr.gbr_inspect(ctx, "tile_start", len(ranges) + 1).astype(np.int64)
+    assert np.array_equal(ts[:-1], ranges[:, 0]) and np.array_equal(ts[1:], ranges[:, 1])
+    srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
+    assert np.array_equal(srt, sg)
+    ctx.close()
