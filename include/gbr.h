@@ -128,9 +128,10 @@ int gbr_blend(gbr_ctx* ctx, const float* bases, const float* weights, int32_t B,
 int gbr_render(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B,
                float* images, void* stream);
 /* The two halves of gbr_render, for callers that want the paper's per-frame
-   scheme (Fig. 4a/4b): gbr_preprocess, then gbr_entry_count (a host
-   synchronisation that returns the number of tile entries, and grows the
-   capacity if needed), then gbr_rasterize. */
+   scheme (Fig. 4a/4b): gbr_preprocess (activation, projection, per-frame
+   depth order, per-tile rank bitmaps and entry counts), then gbr_entry_count
+   (a host synchronisation that returns the number of tile entries, and
+   grows the capacity if needed), then gbr_rasterize (compositing). */
 int gbr_preprocess(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B,
                    void* stream);
 int gbr_entry_count(gbr_ctx* ctx, void* stream, int64_t* entries);

@@ -45,7 +45,6 @@ void dfree(T*& p) {
 // counts/cursors, per-frame depth ranges, the large-bucket list, the status.
 __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.n_tiles) a.tile_count[i] = 0u;
   if (i < n_bkt) { a.bkt_count[i] = 0u; a.bkt_cursor[i] = 0u; }
   if (i < a.B) { a.minmax[2 * i] = 0xffffffffu; a.minmax[2 * i + 1] = 0u; }
   if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
@@ -279,6 +278,18 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
     launch_preprocess(a, raw, c->max_frame_splats, s);
   }
   {
+    KTimer t(c, GBR_K_DEPTH_ORDER, s);
+    launch_depth_order(a, c->max_frame_splats, c->scan_scratch, s);
+  }
+  {
+    KTimer t(c, GBR_K_BINNING, s);
+    int mft = 0;
+    for (const FrameDev& f : c->frames_host) mft = std::max(mft, f.n_tiles);
+    launch_bitmap_rows(a, c->max_frame_splats, mft, s);
+    launch_tile_count(a, s);
+    launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
+  }
+  {
     KTimer t(c, GBR_K_TILE_SCAN, s);
     launch_scan_u32(c->tile_count, c->tile_start, c->n_tiles, c->scan_scratch, c->d_status, c->cap_entries,
                     &c->d_status->entries, s);
@@ -292,17 +303,6 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
 
 int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
   PassArgs a = make_args(c);
-  {
-    KTimer t(c, GBR_K_DEPTH_ORDER, s);
-    launch_depth_order(a, c->max_frame_splats, c->scan_scratch, s);
-  }
-  {
-    KTimer t(c, GBR_K_BINNING, s);
-    launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
-    int mft = 0;
-    for (const FrameDev& f : c->frames_host) mft = std::max(mft, f.n_tiles);
-    launch_bitmap_rows(a, c->max_frame_splats, mft, s);
-  }
   {
     KTimer t(c, GBR_K_TILE_SORT, s);
     launch_fill_u32(c->cls_cnt, 0u, 66, s);   // both schedules of this pass start empty

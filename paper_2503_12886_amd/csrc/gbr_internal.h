@@ -240,6 +240,7 @@ int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
 void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s);
 void launch_tile_lists(const PassArgs& a, hipStream_t s);
+void launch_tile_count(const PassArgs& a, hipStream_t s);
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
 
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);

@@ -197,23 +197,19 @@ __device__ __forceinline__ void project_gaussian(const float* __restrict__ g, co
 }
 
 __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float* __restrict__ raw) {
-  __shared__ uint32_t hist[kMaxFrameTilesLds];
   __shared__ uint32_t dmin, dmax;
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if ((int64_t)blockIdx.x * 256 >= F.gauss_count) return;   // uniform per block
-  const bool lds = F.n_tiles <= kMaxFrameTilesLds;
-  if (lds)
-    for (int t = threadIdx.x; t < F.n_tiles; t += 256) hist[t] = 0u;
   if (threadIdx.x == 0) { dmin = 0xffffffffu; dmax = 0u; }
   __syncthreads();
-  int4 r = make_int4(0, 0, -1, -1);
   if (n < F.gauss_count) {
     const int64_t s = F.gauss_base + n;
     Projected p;
     project_gaussian(raw + s * kNF, F, p);
     float* rec = a.rec + s * kRecF;
+    int4 r = make_int4(0, 0, -1, -1);
     uint32_t count = 0;
     if (p.valid) {
       const int T = a.tile;
@@ -236,18 +232,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
     a.rect[s] = r;
     a.cnt[s] = count;
   }
-  for (int ty = r.y; ty <= r.w; ++ty)
-    for (int tx = r.x; tx <= r.z; ++tx) {
-      const int t = ty * F.ntx + tx;
-      if (lds) atomicAdd(&hist[t], 1u);
-      else atomicAdd(&a.tile_count[F.tile_base + t], 1u);
-    }
   __syncthreads();
-  if (lds)
-    for (int t = threadIdx.x; t < F.n_tiles; t += 256) {
-      const uint32_t c = hist[t];
-      if (c) atomicAdd(&a.tile_count[F.tile_base + t], c);
-    }
   if (threadIdx.x == 0 && dmin <= dmax) {
     atomicMin(&a.minmax[2 * b], dmin);
     atomicMax(&a.minmax[2 * b + 1], dmax);
@@ -327,6 +312,27 @@ void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_fra
     launch_fill_u32(a.tbits, 0u, (int64_t)a.n_tiles * a.bitmap_words, s);
     hipLaunchKernelGGL(bitmap_rows_atomic_kernel, grid, dim3(256), 0, s, a);
   }
+}
+
+// A tile's entry count is the number of set bits of its row: one wave per
+// tile, lanes over the row's words.
+__global__ __launch_bounds__(256) void tile_count_kernel(PassArgs a) {
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= a.n_tiles) return;
+  const int lane = threadIdx.x & 63;
+  const int b = frame_of_tile(a.frames, a.B, g);
+  const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - a.bkt_start[b * a.nbk];
+  const uint32_t W = (nv + 31) / 32;
+  const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  uint32_t c = 0;
+  for (uint32_t q = lane; q < W; q += 64) c += __popc(row[q]);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane == 0) a.tile_count[g] = c;
+}
+
+void launch_tile_count(const PassArgs& a, hipStream_t s) {
+  if (a.n_tiles == 0) return;
+  hipLaunchKernelGGL(tile_count_kernel, dim3(div_up(a.n_tiles, 4)), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------- tile classes
