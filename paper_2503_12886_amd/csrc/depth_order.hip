@@ -18,54 +18,74 @@ __device__ __forceinline__ uint32_t depth_bucket(uint32_t bits, uint32_t mn, uin
                     ((unsigned long long)(mx - mn) + 1ull));
 }
 
+// Bucketing without global atomics.  Workgroup (frame b, block j) takes the
+// frame's splats [4096 j, 4096 j + 4096) and histograms their buckets in
+// LDS; the histograms of all (frame, block) pairs form a matrix, bucket-major
+// with the blocks of a bucket adjacent, whose exclusive scan gives every
+// block its own range inside every bucket.  The scatter pass recomputes the
+// buckets and places each splat at its block's offset plus its LDS rank.
+constexpr int kBucketBlock = 4096;   // splats per workgroup, 16 per thread
+
+__device__ __forceinline__ bool bucket_of(const PassArgs& a, const FrameDev& F, int64_t n, uint32_t mn, uint32_t mx,
+                                          uint32_t& bits, uint32_t& bk, int64_t& s) {
+  if (n >= F.gauss_count) return false;
+  s = F.gauss_base + n;
+  if (a.cnt[s] == 0) return false;
+  bits = __float_as_uint(a.rec[s * kRecF + 9]);
+  bk = depth_bucket(bits, mn, mx, a.nbk);
+  return true;
+}
+
 __global__ __launch_bounds__(256) void bucket_count_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxBuckets];
-  const int b = blockIdx.y;
+  const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
-  if ((int64_t)blockIdx.x * 256 >= F.gauss_count) return;
   for (int t = threadIdx.x; t < a.nbk; t += 256) hist[t] = 0u;
   __syncthreads();
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t mn = a.minmax[2 * b], mx = a.minmax[2 * b + 1];
-  if (n < F.gauss_count) {
-    const int64_t s = F.gauss_base + n;
-    if (a.cnt[s] > 0) atomicAdd(&hist[depth_bucket(__float_as_uint(a.rec[s * kRecF + 9]), mn, mx, a.nbk)], 1u);
+  for (int i = 0; i < kBucketBlock / 256; ++i) {
+    uint32_t bits, bk;
+    int64_t s;
+    if (bucket_of(a, F, (int64_t)blk * kBucketBlock + i * 256 + threadIdx.x, mn, mx, bits, bk, s))
+      atomicAdd(&hist[bk], 1u);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < a.nbk; t += 256) {
-    const uint32_t c = hist[t];
-    if (c) atomicAdd(&a.bkt_count[b * a.nbk + t], c);
-  }
+  for (int t = threadIdx.x; t < a.nbk; t += 256)   // every row is written, zeros included
+    a.bkt_count[((int64_t)b * a.nbk + t) * a.nblk + blk] = hist[t];
 }
 
 __global__ __launch_bounds__(256) void bucket_scatter_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxBuckets];
-  const int b = blockIdx.y;
+  const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
-  if ((int64_t)blockIdx.x * 256 >= F.gauss_count) return;
+  if ((int64_t)blk * kBucketBlock >= F.gauss_count) return;
   for (int t = threadIdx.x; t < a.nbk; t += 256) hist[t] = 0u;
   __syncthreads();
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const uint32_t mn = a.minmax[2 * b], mx = a.minmax[2 * b + 1];
-  const int64_t s = F.gauss_base + n;
-  bool live = false;
-  uint32_t bits = 0, bk = 0;
-  if (n < F.gauss_count && a.cnt[s] > 0) {
-    live = true;
-    bits = __float_as_uint(a.rec[s * kRecF + 9]);
-    bk = depth_bucket(bits, mn, mx, a.nbk);
-    atomicAdd(&hist[bk], 1u);
+  uint32_t rk[kBucketBlock / 256];
+#pragma unroll
+  for (int i = 0; i < kBucketBlock / 256; ++i) {
+    uint32_t bits, bk;
+    int64_t s;
+    rk[i] = bucket_of(a, F, (int64_t)blk * kBucketBlock + i * 256 + threadIdx.x, mn, mx, bits, bk, s)
+                ? atomicAdd(&hist[bk], 1u) : 0u;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < a.nbk; t += 256) {
-    const uint32_t c = hist[t];
-    if (c) hist[t] = atomicAdd(&a.bkt_cursor[b * a.nbk + t], c);
-  }
+  for (int t = threadIdx.x; t < a.nbk; t += 256) hist[t] = a.bkt_moff[((int64_t)b * a.nbk + t) * a.nblk + blk];
   __syncthreads();
-  if (live) {
-    const uint32_t slot = atomicAdd(&hist[bk], 1u);
-    a.bkeys[a.bkt_start[b * a.nbk + bk] + slot] = ((unsigned long long)bits << 32) | (uint32_t)s;
+#pragma unroll
+  for (int i = 0; i < kBucketBlock / 256; ++i) {
+    uint32_t bits, bk;
+    int64_t s;
+    if (bucket_of(a, F, (int64_t)blk * kBucketBlock + i * 256 + threadIdx.x, mn, mx, bits, bk, s))
+      a.bkeys[hist[bk] + rk[i]] = ((unsigned long long)bits << 32) | (uint32_t)s;
   }
+}
+
+// bkt_start[i] = start of bucket i (frame-major) = the scanned matrix at block 0.
+__global__ void bucket_starts_kernel(PassArgs a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i <= n) a.bkt_start[i] = a.bkt_moff[i * a.nblk];
 }
 
 __device__ __forceinline__ void emit_ranked(const PassArgs& a, unsigned long long key, uint32_t pos, uint32_t vbase) {
@@ -154,9 +174,11 @@ __global__ __launch_bounds__(kSortThreads) void bucket_sort_big_kernel(PassArgs 
 
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s) {
   if (a.B == 0 || max_frame_splats == 0) return;
-  const dim3 grid(div_up(max_frame_splats, 256), a.B);
+  const dim3 grid(a.nblk, a.B);
+  const int64_t nb = (int64_t)a.B * a.nbk;
   hipLaunchKernelGGL(bucket_count_kernel, grid, dim3(256), 0, s, a);
-  launch_scan_u32(a.bkt_count, a.bkt_start, (int64_t)a.B * a.nbk, scan_scratch, a.status, -1, nullptr, s);
+  launch_scan_u32(a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, a.status, -1, nullptr, s);
+  hipLaunchKernelGGL(bucket_starts_kernel, dim3(div_up(nb + 1, 256)), dim3(256), 0, s, a, nb);
   hipLaunchKernelGGL(bucket_scatter_kernel, grid, dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_sort_small_kernel, dim3(div_up((int64_t)a.B * a.nbk, 4)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_sort_big_kernel, dim3(std::min(a.B * a.nbk, 512)), dim3(kSortThreads), 0, s, a);

@@ -45,7 +45,6 @@ void dfree(T*& p) {
 // counts/cursors, per-frame depth ranges, the large-bucket list, the status.
 __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_bkt) { a.bkt_count[i] = 0u; a.bkt_cursor[i] = 0u; }
   if (i < a.B) { a.minmax[2 * i] = 0xffffffffu; a.minmax[2 * i + 1] = 0u; }
   if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
 }
@@ -73,17 +72,18 @@ struct gbr_ctx {
   uint8_t* part_flag = nullptr;
   uint8_t* cmask = nullptr;
   // per-frame depth order
-  uint32_t *minmax = nullptr, *bkt_count = nullptr, *bkt_start = nullptr, *bkt_cursor = nullptr;
+  uint32_t *minmax = nullptr, *bkt_count = nullptr, *bkt_moff = nullptr, *bkt_start = nullptr;
   uint32_t *big_list = nullptr, *big_count = nullptr;
   unsigned long long *bkeys = nullptr, *bkeys_alt = nullptr;
   uint32_t *depth_sorted = nullptr, *rank = nullptr;
-  int64_t cap_bkt = 0;
-  int nbk = 64;
+  int64_t cap_bkt = 0, cap_bkt_cells = 0;
+  int nbk = 64, nblk = 1;
   float* part = nullptr;
   uint32_t* n_iter = nullptr;
   uint32_t* n_contrib = nullptr;
   float* t_final = nullptr;
   uint32_t* scan_scratch = nullptr;
+  int64_t cap_scan_words = 0;
   float* draw_scratch = nullptr;
   float* loss_part = nullptr;
   float* blend_part = nullptr;
@@ -137,8 +137,9 @@ PassArgs make_args(gbr_ctx* c) {
   a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd; a.cls_cnt = c->cls_cnt;
   a.tbits = c->tbits; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
+  a.nblk = c->nblk;
   a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
-  a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_start = c->bkt_start; a.bkt_cursor = c->bkt_cursor;
+  a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_moff = c->bkt_moff; a.bkt_start = c->bkt_start;
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
   a.big_list = c->big_list; a.big_count = c->big_count;
   a.n_iter = c->n_iter; a.n_contrib = c->n_contrib; a.t_final = c->t_final; a.part = c->part;
@@ -176,14 +177,15 @@ int alloc_entries(gbr_ctx* c, int64_t cap) {
   return GBR_OK;
 }
 
-int alloc_buckets(gbr_ctx* c, int64_t n) {
-  dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
+int alloc_buckets(gbr_ctx* c, int64_t n, int64_t cells) {
+  dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
+  c->cap_bkt = 0; c->cap_bkt_cells = 0;
   int rc = GBR_OK;
-  if ((rc = dalloc(&c->bkt_count, n))) return rc;
+  if ((rc = dalloc(&c->bkt_count, cells))) return rc;
+  if ((rc = dalloc(&c->bkt_moff, cells + 1))) return rc;
   if ((rc = dalloc(&c->bkt_start, n + 1))) return rc;
-  if ((rc = dalloc(&c->bkt_cursor, n))) return rc;
   if ((rc = dalloc(&c->big_list, n))) return rc;
-  c->cap_bkt = n;
+  c->cap_bkt = n; c->cap_bkt_cells = cells;
   return GBR_OK;
 }
 
@@ -192,7 +194,7 @@ void free_all(gbr_ctx* c) {
   dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->tbits);
   dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
-  dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_start); dfree(c->bkt_cursor); dfree(c->big_list);
+  dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
   dfree(c->loss_part); dfree(c->blend_part); dfree(c->blend_w64);
@@ -327,11 +329,22 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   if ((mfs + 31) / 32 > kMaxBitmapWords) return GBR_ERR_CAPACITY;
   int nbk = 64;
   while (nbk < 8192 && (int64_t)nbk * 16 < mfs) nbk *= 2;
-  if ((int64_t)B * nbk > c->cap_bkt) {
+  const int nblk = (int)std::max<int64_t>(1, (mfs + 4095) / 4096);
+  if ((int64_t)B * nbk > c->cap_bkt || (int64_t)B * nbk * nblk > c->cap_bkt_cells) {
     if (c->capturing) return GBR_ERR_STATE;
     GBR_HIP(hipDeviceSynchronize());
-    rc = alloc_buckets(c, (int64_t)B * nbk);
+    rc = alloc_buckets(c, (int64_t)B * nbk, (int64_t)B * nbk * nblk);
     if (rc) return rc;
+  }
+  const int64_t scan_words = scan_scratch_words((int64_t)B * nbk * nblk);
+  if (scan_words > c->cap_scan_words) {   // the bucket-count matrix is the longest scan of a pass
+    if (c->capturing) return GBR_ERR_STATE;
+    GBR_HIP(hipDeviceSynchronize());
+    dfree(c->scan_scratch);
+    c->cap_scan_words = 0;
+    rc = dalloc(&c->scan_scratch, scan_words);
+    if (rc) return rc;
+    c->cap_scan_words = scan_words;
   }
   const int64_t need_bits = std::max<int64_t>(1, (int64_t)nt * ((mfs + 31) / 32));
   if (need_bits > c->cap_tbits) {
@@ -346,6 +359,7 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   c->frames_host.swap(fr);
   c->B = B; c->n_tiles = nt; c->n_pixels = np; c->n_splats = ns; c->max_frame_splats = mfs;
   c->nbk = nbk;
+  c->nblk = nblk;
   return GBR_OK;
 }
 
@@ -405,13 +419,13 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->bkeys_alt, c->cap_splats));
   TRY(dalloc(&c->depth_sorted, c->cap_splats));
   TRY(dalloc(&c->rank, c->cap_splats));
-  TRY(alloc_buckets(c, 64LL * c->cap_frames));
+  TRY(alloc_buckets(c, 64LL * c->cap_frames, 64LL * c->cap_frames));
   TRY(dalloc(&c->n_iter, c->cap_pixels));
   TRY(dalloc(&c->n_contrib, c->cap_pixels));
   TRY(dalloc(&c->t_final, c->cap_pixels));
-  TRY(dalloc(&c->scan_scratch,
-             scan_scratch_words(std::max<int64_t>(std::max<int64_t>(c->cap_splats, c->cap_tiles),
-                                                  (int64_t)8192 * c->cap_frames))));
+  c->cap_scan_words = scan_scratch_words(std::max<int64_t>(std::max<int64_t>(c->cap_splats, c->cap_tiles),
+                                                            (int64_t)8192 * c->cap_frames));
+  TRY(dalloc(&c->scan_scratch, c->cap_scan_words));
   TRY(dalloc(&c->draw_scratch, c->cap_splats * kNF));
   TRY(dalloc(&c->loss_part, 2 * loss_partials(3 * c->cap_pixels) + 2));
   c->blend_part_n = 4 * c->cap_splats + 4096LL * c->cap_frames + 64LL * 64 * 8;

@@ -74,11 +74,12 @@ struct PassArgs {
   uint32_t* cls_cnt;        // [2][33] tiles per class (forward, backward)
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
+  int32_t nblk;             // workgroups of 4096 splats per frame in the bucket passes
   int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32)
   uint32_t* minmax;         // [B][2] min / max binary32 depth bits of the frame's valid splats
-  uint32_t* bkt_count;      // [B * nbk]
+  uint32_t* bkt_count;      // [B * nbk][nblk] per-block bucket counts
+  uint32_t* bkt_moff;       // [B * nbk * nblk + 1] their exclusive scan
   uint32_t* bkt_start;      // [B * nbk + 1] exclusive scan; frame b's valid splats start at bkt_start[b * nbk]
-  uint32_t* bkt_cursor;     // [B * nbk]
   unsigned long long* bkeys;      // [S] (depth bits << 32) | splat, grouped by bucket
   unsigned long long* bkeys_alt;  // [S] ping-pong for large buckets
   uint32_t* depth_sorted;   // [S] valid splats of each frame in (depth, index) order
