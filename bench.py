@@ -281,7 +281,8 @@ def cpu_baseline(budget_s: float) -> dict:
     t_adam = time.perf_counter() - t1
     per_img = t_frames / frames + t_adam / cfg.B
     return {"value": round(1.0 / per_img, 5), "unit": "img/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} of the 16 frames (N=50000, K=20, 512x512): float64 blend + render + L1 gradient + "
+            "sample": f"{frames} frames, cycling over the 16-frame batch (N=50000, K=20, 512x512): float64 blend + "
+                      f"render + L1 gradient + "
                       f"render adjoint + blend adjoint, {t_frames:.1f} s; plus one MLP backward and Adam update of "
                       f"all {flat.size} base parameters ({t_adam:.1f} s) amortised over 16 frames",
             "cpu": cpu_model()}

@@ -4,9 +4,10 @@
 // instead of once per tile:
 //   1. splats are distributed over nbk buckets per frame by their depth bits,
 //      scaled between the frame's min and max (monotone in depth);
-//   2. a wave ranks each bucket of at most 64 splats by direct comparison;
-//      larger buckets go to a block that compares in LDS (<= 2048) or runs
-//      the stable radix passes through global memory.
+//   2. buckets are ranked by direct comparison, 64 buckets per workgroup
+//      in LDS (or a wave per bucket when they do not fit); large buckets go
+//      to a block that compares in LDS (<= 2048) or runs the stable radix
+//      passes through global memory.
 #include "gbr_device.h"
 
 namespace gbr {
@@ -24,61 +25,65 @@ __device__ __forceinline__ uint32_t depth_bucket(uint32_t bits, uint32_t mn, uin
 // with the blocks of a bucket adjacent, whose exclusive scan gives every
 // block its own range inside every bucket.  The scatter pass recomputes the
 // buckets and places each splat at its block's offset plus its LDS rank.
-constexpr int kBucketBlock = 4096;   // splats per workgroup, 16 per thread
+// Depth keys come from the compact per-splat key array (invalid splats carry
+// 0xffffffff, which no positive depth has); loads are clamped into range and
+// issued unconditionally so that a thread's four loads overlap.
+constexpr int kBucketBlock = 4096;   // splats per workgroup
+constexpr int kBucketThreads = 1024;
+constexpr int kBucketItems = kBucketBlock / kBucketThreads;
 
-__device__ __forceinline__ bool bucket_of(const PassArgs& a, const FrameDev& F, int64_t n, uint32_t mn, uint32_t mx,
-                                          uint32_t& bits, uint32_t& bk, int64_t& s) {
-  if (n >= F.gauss_count) return false;
-  s = F.gauss_base + n;
-  if (a.cnt[s] == 0) return false;
-  bits = __float_as_uint(a.rec[s * kRecF + 9]);
-  bk = depth_bucket(bits, mn, mx, a.nbk);
-  return true;
+__device__ __forceinline__ void load_bucket_keys(const PassArgs& a, const FrameDev& F, int blk, uint32_t mn,
+                                                 uint32_t mx, uint32_t* key, uint32_t* bk) {
+  const int64_t cnt = F.gauss_count;
+#pragma unroll
+  for (int i = 0; i < kBucketItems; ++i) {
+    const int64_t n = (int64_t)blk * kBucketBlock + i * kBucketThreads + threadIdx.x;
+    const int64_t nn = n < cnt ? n : cnt - 1;
+    key[i] = cnt > 0 ? a.dkey[F.gauss_base + nn] : 0xffffffffu;
+    if (n >= cnt) key[i] = 0xffffffffu;
+  }
+#pragma unroll
+  for (int i = 0; i < kBucketItems; ++i) bk[i] = key[i] != 0xffffffffu ? depth_bucket(key[i], mn, mx, a.nbk) : 0u;
 }
 
-__global__ __launch_bounds__(256) void bucket_count_kernel(PassArgs a) {
+__global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxBuckets];
   const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
-  for (int t = threadIdx.x; t < a.nbk; t += 256) hist[t] = 0u;
-  __syncthreads();
+  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
   const uint32_t mn = a.minmax[2 * b], mx = a.minmax[2 * b + 1];
-  for (int i = 0; i < kBucketBlock / 256; ++i) {
-    uint32_t bits, bk;
-    int64_t s;
-    if (bucket_of(a, F, (int64_t)blk * kBucketBlock + i * 256 + threadIdx.x, mn, mx, bits, bk, s))
-      atomicAdd(&hist[bk], 1u);
-  }
+  uint32_t key[kBucketItems], bk[kBucketItems];
+  load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();
-  for (int t = threadIdx.x; t < a.nbk; t += 256)   // every row is written, zeros included
+#pragma unroll
+  for (int i = 0; i < kBucketItems; ++i)
+    if (key[i] != 0xffffffffu) atomicAdd(&hist[bk[i]], 1u);
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads)   // every row is written, zeros included
     a.bkt_count[((int64_t)b * a.nbk + t) * a.nblk + blk] = hist[t];
 }
 
-__global__ __launch_bounds__(256) void bucket_scatter_kernel(PassArgs a) {
+__global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxBuckets];
   const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
   if ((int64_t)blk * kBucketBlock >= F.gauss_count) return;
-  for (int t = threadIdx.x; t < a.nbk; t += 256) hist[t] = 0u;
-  __syncthreads();
+  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
   const uint32_t mn = a.minmax[2 * b], mx = a.minmax[2 * b + 1];
-  uint32_t rk[kBucketBlock / 256];
-#pragma unroll
-  for (int i = 0; i < kBucketBlock / 256; ++i) {
-    uint32_t bits, bk;
-    int64_t s;
-    rk[i] = bucket_of(a, F, (int64_t)blk * kBucketBlock + i * 256 + threadIdx.x, mn, mx, bits, bk, s)
-                ? atomicAdd(&hist[bk], 1u) : 0u;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < a.nbk; t += 256) hist[t] = a.bkt_moff[((int64_t)b * a.nbk + t) * a.nblk + blk];
+  uint32_t key[kBucketItems], bk[kBucketItems], rk[kBucketItems];
+  load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < kBucketBlock / 256; ++i) {
-    uint32_t bits, bk;
-    int64_t s;
-    if (bucket_of(a, F, (int64_t)blk * kBucketBlock + i * 256 + threadIdx.x, mn, mx, bits, bk, s))
-      a.bkeys[hist[bk] + rk[i]] = ((unsigned long long)bits << 32) | (uint32_t)s;
+  for (int i = 0; i < kBucketItems; ++i) rk[i] = key[i] != 0xffffffffu ? atomicAdd(&hist[bk[i]], 1u) : 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads)
+    hist[t] = a.bkt_moff[((int64_t)b * a.nbk + t) * a.nblk + blk];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kBucketItems; ++i) {
+    if (key[i] == 0xffffffffu) continue;
+    const int64_t s = F.gauss_base + (int64_t)blk * kBucketBlock + i * kBucketThreads + threadIdx.x;
+    a.bkeys[hist[bk[i]] + rk[i]] = ((unsigned long long)key[i] << 32) | (uint32_t)s;
   }
 }
 
@@ -94,30 +99,67 @@ __device__ __forceinline__ void emit_ranked(const PassArgs& a, unsigned long lon
   a.rank[s] = pos - vbase;
 }
 
-// One wave per bucket: keys are unique, so a key's rank is the number of
-// smaller keys in the bucket.
-__global__ __launch_bounds__(256) void bucket_sort_small_kernel(PassArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int gb = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (gb >= a.B * a.nbk) return;
-  const uint32_t start = a.bkt_start[gb];
-  const uint32_t n = a.bkt_start[gb + 1] - start;
-  if (n == 0) return;
-  if (n > 64) {
-    if (lane == 0) a.big_list[atomicAdd(a.big_count, 1u)] = (uint32_t)gb;
+// Ranks within buckets.  Keys are unique, so a key's rank is the number of
+// smaller keys in its bucket.  A workgroup takes 64 consecutive buckets:
+// when their keys fit in LDS, every thread ranks keys against the keys of
+// their bucket there; otherwise a wave per bucket compares through lane
+// reads.  Buckets of more than kRankMax keys (kWaveMax on the wave path) go
+// to the large-bucket pass.  The bucket count per frame is a power of two
+// of at least 64, so a workgroup's buckets belong to one frame.
+constexpr int kRankBuckets = 64;
+constexpr int kRankKeys = 2048;
+constexpr uint32_t kRankMax = 128;
+constexpr uint32_t kWaveMax = 64;
+
+__global__ __launch_bounds__(256) void bucket_rank_kernel(PassArgs a) {
+  __shared__ unsigned long long keys[kRankKeys];
+  __shared__ uint32_t bs[kRankBuckets + 1];
+  __shared__ uint32_t vb;
+  const int nb = a.B * a.nbk;
+  const int gb0 = blockIdx.x * kRankBuckets;
+  const int nbl = min(nb - gb0, kRankBuckets);
+  if (threadIdx.x <= nbl) bs[threadIdx.x] = a.bkt_start[gb0 + threadIdx.x];
+  if (threadIdx.x == 0) vb = a.bkt_start[(gb0 / a.nbk) * a.nbk];
+  __syncthreads();
+  const uint32_t k0 = bs[0], nk = bs[nbl] - k0;
+  const uint32_t cap = nk <= (uint32_t)kRankKeys ? kRankMax : kWaveMax;
+  if (threadIdx.x < nbl) {
+    const uint32_t n = bs[threadIdx.x + 1] - bs[threadIdx.x];
+    if (n > cap) a.big_list[atomicAdd(a.big_count, 1u)] = (uint32_t)(gb0 + threadIdx.x);
+  }
+  if (nk <= (uint32_t)kRankKeys) {
+    for (uint32_t i = threadIdx.x; i < nk; i += 256) keys[i] = a.bkeys[k0 + i];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nk; i += 256) {
+      // bucket of key i: the last j with bs[j] <= k0 + i
+      int lo = 0, hi = nbl - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bs[mid] <= k0 + i) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t j0 = bs[lo] - k0, j1 = bs[lo + 1] - k0;
+      if (j1 - j0 > cap) continue;
+      const unsigned long long k = keys[i];
+      uint32_t rank = 0;
+      for (uint32_t j = j0; j < j1; ++j) rank += keys[j] < k ? 1u : 0u;
+      emit_ranked(a, k, k0 + j0 + rank, vb);
+    }
     return;
   }
-  const int b = gb / a.nbk;
-  const uint32_t vbase = a.bkt_start[b * a.nbk];
-  const unsigned long long key = (lane < (int)n) ? a.bkeys[start + lane] : ~0ull;
-  const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
-  uint32_t rank = 0;
-  for (uint32_t j = 0; j < n; ++j) {
-    const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)hi, (int)j);
-    const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)j);
-    rank += (khi < hi || (khi == hi && klo < lo)) ? 1u : 0u;
+  const int lane = threadIdx.x & 63;
+  for (int j = threadIdx.x >> 6; j < nbl; j += 4) {
+    const uint32_t start = bs[j], n = bs[j + 1] - start;
+    if (n == 0 || n > cap) continue;
+    const unsigned long long key = (lane < (int)n) ? a.bkeys[start + lane] : ~0ull;
+    const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+    uint32_t rank = 0;
+    for (uint32_t q = 0; q < n; ++q) {
+      const uint32_t khi = (uint32_t)__builtin_amdgcn_readlane((int)hi, (int)q);
+      const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)q);
+      rank += (khi < hi || (khi == hi && klo < lo)) ? 1u : 0u;
+    }
+    if (lane < (int)n) emit_ranked(a, key, start + rank, vb);
   }
-  if (lane < (int)n) emit_ranked(a, key, start + rank, vbase);
 }
 
 constexpr int kBigDirect = 2048;
@@ -176,11 +218,11 @@ void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* s
   if (a.B == 0 || max_frame_splats == 0) return;
   const dim3 grid(a.nblk, a.B);
   const int64_t nb = (int64_t)a.B * a.nbk;
-  hipLaunchKernelGGL(bucket_count_kernel, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bucket_count_kernel, grid, dim3(kBucketThreads), 0, s, a);
   launch_scan_u32(a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, a.status, -1, nullptr, s);
   hipLaunchKernelGGL(bucket_starts_kernel, dim3(div_up(nb + 1, 256)), dim3(256), 0, s, a, nb);
-  hipLaunchKernelGGL(bucket_scatter_kernel, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bucket_sort_small_kernel, dim3(div_up((int64_t)a.B * a.nbk, 4)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bucket_scatter_kernel, grid, dim3(kBucketThreads), 0, s, a);
+  hipLaunchKernelGGL(bucket_rank_kernel, dim3(div_up((int64_t)a.B * a.nbk, kRankBuckets)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_sort_big_kernel, dim3(std::min(a.B * a.nbk, 512)), dim3(kSortThreads), 0, s, a);
 }
 

@@ -63,10 +63,13 @@ struct gbr_ctx {
   StatusDev* d_status = nullptr;
   float* rec = nullptr;
   int4* rect = nullptr;
-  uint32_t *cnt = nullptr, *soff = nullptr;
+  uint32_t *cnt = nullptr, *soff = nullptr, *dkey = nullptr;
   uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_last = nullptr;
   uint32_t* tbits = nullptr;        // [cap_tbits] per-tile rank bitmap rows
   int64_t cap_tbits = 0;
+  uint16_t* seg_cnt = nullptr;      // [cap_seg] set bits per row segment
+  int64_t cap_seg = 0;
+  int seg_words = 16, max_frame_tiles = 0;
   uint32_t* sorted = nullptr;
   uint32_t *order_fwd = nullptr, *order_bwd = nullptr, *cls_cnt = nullptr;
   uint8_t* part_flag = nullptr;
@@ -131,14 +134,17 @@ PassArgs make_args(gbr_ctx* c) {
   a.n_pixels = c->n_pixels;
   a.cap_entries = c->cap_entries;
   a.status = c->d_status;
-  a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff;
+  a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff; a.dkey = c->dkey;
   a.tile_count = c->tile_count; a.tile_start = c->tile_start;
   a.tile_last = c->tile_last;
   a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd; a.cls_cnt = c->cls_cnt;
   a.tbits = c->tbits; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
   a.nblk = c->nblk;
-  a.bitmap_words = (int32_t)((c->max_frame_splats + 31) / 32);
+  a.bitmap_words = (int32_t)(((c->max_frame_splats + 31) / 32 + 31) / 32 * 32);
+  a.seg_words = c->seg_words;
+  a.seg_stride = a.bitmap_words / a.seg_words;
+  a.seg_cnt = c->seg_cnt;
   a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_moff = c->bkt_moff; a.bkt_start = c->bkt_start;
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
   a.big_list = c->big_list; a.big_count = c->big_count;
@@ -190,8 +196,8 @@ int alloc_buckets(gbr_ctx* c, int64_t n, int64_t cells) {
 }
 
 void free_all(gbr_ctx* c) {
-  dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff);
-  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->tbits);
+  dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff); dfree(c->dkey);
+  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->tbits); dfree(c->seg_cnt);
   dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
@@ -285,9 +291,7 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
   }
   {
     KTimer t(c, GBR_K_BINNING, s);
-    int mft = 0;
-    for (const FrameDev& f : c->frames_host) mft = std::max(mft, f.n_tiles);
-    launch_bitmap_rows(a, c->max_frame_splats, mft, s);
+    launch_bitmap_rows(a, c->max_frame_splats, c->max_frame_tiles, s);
     launch_tile_count(a, s);
     launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
   }
@@ -346,7 +350,11 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
     if (rc) return rc;
     c->cap_scan_words = scan_words;
   }
-  const int64_t need_bits = std::max<int64_t>(1, (int64_t)nt * ((mfs + 31) / 32));
+  int mft = 0;
+  for (const FrameDev& f : fr) mft = std::max(mft, f.n_tiles);
+  const int64_t row_words = ((mfs + 31) / 32 + 31) / 32 * 32;
+  const int seg_words = bitmap_seg_words(mft, row_words);
+  const int64_t need_bits = std::max<int64_t>(1, (int64_t)nt * row_words);
   if (need_bits > c->cap_tbits) {
     if (c->capturing) return GBR_ERR_STATE;
     GBR_HIP(hipDeviceSynchronize());
@@ -356,10 +364,22 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
     if (rc) return rc;
     c->cap_tbits = need_bits;
   }
+  const int64_t need_seg = std::max<int64_t>(1, (int64_t)nt * (row_words / seg_words));
+  if (need_seg > c->cap_seg) {
+    if (c->capturing) return GBR_ERR_STATE;
+    GBR_HIP(hipDeviceSynchronize());
+    dfree(c->seg_cnt);
+    c->cap_seg = 0;
+    rc = dalloc(&c->seg_cnt, need_seg);
+    if (rc) return rc;
+    c->cap_seg = need_seg;
+  }
   c->frames_host.swap(fr);
   c->B = B; c->n_tiles = nt; c->n_pixels = np; c->n_splats = ns; c->max_frame_splats = mfs;
   c->nbk = nbk;
   c->nblk = nblk;
+  c->seg_words = seg_words;
+  c->max_frame_tiles = mft;
   return GBR_OK;
 }
 
@@ -407,6 +427,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->rect, c->cap_splats));
   TRY(dalloc(&c->cnt, c->cap_splats));
   TRY(dalloc(&c->soff, c->cap_splats + 1));
+  TRY(dalloc(&c->dkey, c->cap_splats));
   TRY(dalloc(&c->tile_count, c->cap_tiles));
   TRY(dalloc(&c->tile_start, c->cap_tiles + 1));
   TRY(dalloc(&c->tile_last, c->cap_tiles));

@@ -63,11 +63,13 @@ struct PassArgs {
   int4* rect;               // [S] inclusive tile rect (tx0, ty0, tx1, ty1)
   uint32_t* cnt;            // [S] tiles touched
   uint32_t* soff;           // [S] exclusive scan of cnt (emission offsets)
+  uint32_t* dkey;           // [S] binary32 depth bits of a valid splat, 0xffffffff otherwise
   // tile stage
   uint32_t* tile_count;     // [tiles]
   uint32_t* tile_start;     // [tiles + 1]
   uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel
   uint32_t* tbits;          // [tiles][bitmap_words] per-tile bitmaps of frame-local depth ranks
+  uint16_t* seg_cnt;        // [tiles][seg_stride] set bits of each row segment
   uint32_t* sorted;         // [E] splat index in tile order
   uint32_t* order_fwd;      // [33][tiles] tiles by class of list length (scheduling only)
   uint32_t* order_bwd;      // [33][tiles] tiles by class of entries used by the forward pass
@@ -75,7 +77,9 @@ struct PassArgs {
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
   int32_t nblk;             // workgroups of 4096 splats per frame in the bucket passes
-  int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32)
+  int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32, rounded up to 16)
+  int32_t seg_words;        // words per row segment (8 or 16); a segment's set bits are counted once
+  int32_t seg_stride;       // segments per row = bitmap_words / seg_words
   uint32_t* minmax;         // [B][2] min / max binary32 depth bits of the frame's valid splats
   uint32_t* bkt_count;      // [B * nbk][nblk] per-block bucket counts
   uint32_t* bkt_moff;       // [B * nbk * nblk + 1] their exclusive scan
@@ -239,6 +243,10 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blo
                      int64_t cap_check, unsigned long long* total_out, hipStream_t s);
 int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
+// Words per bitmap row segment for frames of up to max_frame_tiles tiles
+// (the workgroup that builds a segment of every row of a frame holds them in LDS).
+constexpr int kMaxRowSegs = 1024;   // segments per bitmap row at most (the compositing lists them in LDS)
+int bitmap_seg_words(int max_frame_tiles, int64_t row_words);
 void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s);
 void launch_tile_lists(const PassArgs& a, hipStream_t s);
 void launch_tile_count(const PassArgs& a, hipStream_t s);

@@ -196,24 +196,34 @@ __device__ __forceinline__ void project_gaussian(const float* __restrict__ g, co
   p.valid = true;
 }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
+}
+
 __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float* __restrict__ raw) {
-  __shared__ uint32_t dmin, dmax;
+  __shared__ uint32_t wmin[4], wmax[4];
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if ((int64_t)blockIdx.x * 256 >= F.gauss_count) return;   // uniform per block
-  if (threadIdx.x == 0) { dmin = 0xffffffffu; dmax = 0u; }
-  __syncthreads();
+  const int tsh = __ffs(a.tile) - 1;                         // tile is a power of two
+  uint32_t dmin = 0xffffffffu, dmax = 0u;
   if (n < F.gauss_count) {
     const int64_t s = F.gauss_base + n;
     Projected p;
     project_gaussian(raw + s * kNF, F, p);
     float* rec = a.rec + s * kRecF;
     int4 r = make_int4(0, 0, -1, -1);
-    uint32_t count = 0;
+    uint32_t count = 0, key = 0xffffffffu;
     if (p.valid) {
-      const int T = a.tile;
-      r = make_int4(p.x0 / T, p.y0 / T, p.x1 / T, p.y1 / T);
+      r = make_int4(p.x0 >> tsh, p.y0 >> tsh, p.x1 >> tsh, p.y1 >> tsh);
       count = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
       const float4 r0 = make_float4((float)p.mx, (float)p.my, (float)(-0.5 * kLog2e * p.A), (float)(-kLog2e * p.Bq));
       const float4 r1 = make_float4((float)(-0.5 * kLog2e * p.C), (float)p.o, raw[s * kNF + 11], raw[s * kNF + 12]);
@@ -223,19 +233,27 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
       reinterpret_cast<float4*>(rec)[0] = r0;
       reinterpret_cast<float4*>(rec)[1] = r1;
       reinterpret_cast<float4*>(rec)[2] = r2;
-      const uint32_t db = __float_as_uint(r2.y);
-      atomicMin(&dmin, db);
-      atomicMax(&dmax, db);
+      key = __float_as_uint(r2.y);
+      dmin = key; dmax = key;
     } else {
       reinterpret_cast<float4*>(rec)[2] = make_float4(0.0f, (float)p.tz, 0.0f, 0.0f);
     }
     a.rect[s] = r;
     a.cnt[s] = count;
+    a.dkey[s] = key;
   }
+  // frame depth range: wave reductions, then one pair of atomics per block
+  dmin = wave_min_u32(dmin);
+  dmax = wave_max_u32(dmax);
+  if ((threadIdx.x & 63) == 0) { wmin[threadIdx.x >> 6] = dmin; wmax[threadIdx.x >> 6] = dmax; }
   __syncthreads();
-  if (threadIdx.x == 0 && dmin <= dmax) {
-    atomicMin(&a.minmax[2 * b], dmin);
-    atomicMax(&a.minmax[2 * b + 1], dmax);
+  if (threadIdx.x == 0) {
+    dmin = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    dmax = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    if (dmin <= dmax) {
+      atomicMin(&a.minmax[2 * b], dmin);
+      atomicMax(&a.minmax[2 * b + 1], dmax);
+    }
   }
 }
 
@@ -248,43 +266,68 @@ void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_sp
 // A tile's list is the set of frame-local depth ranks of the splats that
 // overlap it.  Each tile owns a row of bitmap_words words (bit r = rank r);
 // reading a row's set bits in ascending order gives the tile's list in depth
-// order, so no entry array is scattered or sorted.
+// order, so no entry array is scattered or sorted.  Rows are cut into
+// segments of seg_words words, and the set bits of every segment are counted
+// once (seg_cnt): the tile's entry count is their sum, and the compositing
+// places each segment in the tile's order from those counts alone, reading
+// only the segments it consumes.
 //
 // Rows are built by rank: workgroup j of a frame takes the splats of ranks
-// [256 j, 256 j + 256), which own bitmap words [8 j, 8 j + 8) of every row.
-// Each splat ORs its bit into an LDS copy of those 8 words for every tile of
-// its rect; the workgroup then stores the 8 words of every tile of the frame
-// (zeros included), so every word of every row is written by exactly one
-// workgroup and nothing needs clearing.  Frames with more tiles than the LDS
-// copy holds set the bits in memory with atomics after clearing the rows.
-constexpr int kRowBuildWords = 16384;        // LDS words: 8 per tile, frames of up to 2048 tiles
+// [32 SW j, 32 SW (j + 1)), which own segment j (words [SW j, SW (j + 1)))
+// of every row.  Each splat ORs its bit into an LDS copy of those SW words
+// for every tile of its rect; the workgroup then stores the segment of every
+// tile of the frame (zeros included) and its bit count, so every word of
+// every row is written by exactly one workgroup and nothing needs clearing.
+// Frames with more tiles than the LDS copy holds set the bits in memory with
+// atomics after clearing the rows, and count the segments in a second pass.
+constexpr int kRowBuildWords = 16384;        // LDS words (64 KB)
 
-__global__ __launch_bounds__(256) void bitmap_rows_kernel(PassArgs a) {
-  __shared__ uint32_t words[kRowBuildWords];
+int bitmap_seg_words(int max_frame_tiles, int64_t row_words) {
+  int sw = (int64_t)max_frame_tiles * 16 <= kRowBuildWords ? 16 : 8;
+  while (row_words / sw > kMaxRowSegs) sw *= 2;
+  return sw;
+}
+
+template <int SW>
+__global__ __launch_bounds__(32 * SW) void bitmap_rows_kernel(PassArgs a) {
+  constexpr int NT = 32 * SW;                 // one thread per rank of the segment
+  __shared__ __align__(16) uint32_t words[kRowBuildWords];
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
   const uint32_t vbase = a.bkt_start[b * a.nbk];
   const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
-  const uint32_t r0 = blockIdx.x * 256u;
+  const uint32_t r0 = blockIdx.x * (uint32_t)NT;
   if (r0 >= nv || a.status->overflow) return;
-  const int nw = F.n_tiles * 8;
-  for (int q = threadIdx.x; q < nw; q += 256) words[q] = 0u;
+  const int nw4 = F.n_tiles * (SW / 4);
+  uint4* w4 = reinterpret_cast<uint4*>(words);
+  for (int q = threadIdx.x; q < nw4; q += NT) w4[q] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   const uint32_t r = r0 + threadIdx.x;
   if (r < nv) {
     const uint32_t s = a.depth_sorted[vbase + r];
     const int4 rc = a.rect[s];
     const uint32_t bit = 1u << (r & 31u);
-    const int wl = (int)((r >> 5) & 7u);
+    const int wl = (int)((r >> 5) & (SW - 1));
     for (int ty = rc.y; ty <= rc.w; ++ty)
-      for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(&words[(ty * F.ntx + tx) * 8 + wl], bit);
+      for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(&words[(ty * F.ntx + tx) * SW + wl], bit);
   }
   __syncthreads();
-  uint32_t* rows = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (r0 >> 5);
-  const uint32_t wmax = (uint32_t)a.bitmap_words - (r0 >> 5);   // words of the row left from 8 j
-  for (int q = threadIdx.x; q < nw; q += 256) {
-    const int t = q >> 3, k = q & 7;
-    if ((uint32_t)k < wmax) rows[(int64_t)t * a.bitmap_words + k] = words[q];
+  // the segment of every row (16-byte stores; rows and segments are 64-byte aligned)
+  const int seg = (int)blockIdx.x;
+  uint32_t* rows = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (int64_t)seg * SW;
+  for (int q = threadIdx.x; q < nw4; q += NT) {
+    const int t = q / (SW / 4), k = q % (SW / 4);
+    reinterpret_cast<uint4*>(rows + (int64_t)t * a.bitmap_words)[k] = w4[q];
+  }
+  uint16_t* cnt = a.seg_cnt + (int64_t)F.tile_base * a.seg_stride + seg;
+  for (int t = threadIdx.x; t < F.n_tiles; t += NT) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < SW / 4; ++k) {
+      const uint4 v = w4[t * (SW / 4) + k];
+      c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+    }
+    cnt[(int64_t)t * a.seg_stride] = (uint16_t)c;
   }
 }
 
@@ -303,29 +346,49 @@ __global__ __launch_bounds__(256) void bitmap_rows_atomic_kernel(PassArgs a) {
     for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(base + (int64_t)(ty * F.ntx + tx) * a.bitmap_words, bit);
 }
 
+// Bit counts of the segments of rows set in memory: a thread per (tile, segment).
+__global__ __launch_bounds__(256) void seg_count_kernel(PassArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)a.n_tiles * a.seg_stride || a.status->overflow) return;
+  const int64_t g = i / a.seg_stride;
+  const int sg = (int)(i % a.seg_stride);
+  const uint4* src = reinterpret_cast<const uint4*>(a.tbits + g * a.bitmap_words + (int64_t)sg * a.seg_words);
+  uint32_t c = 0;
+  for (int k = 0; k < a.seg_words / 4; ++k) {
+    const uint4 v = src[k];
+    c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+  }
+  a.seg_cnt[i] = (uint16_t)c;
+}
+
 void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s) {
   if (a.B == 0 || max_frame_splats == 0) return;
-  const dim3 grid(div_up(max_frame_splats, 256), a.B);
-  if ((int64_t)max_frame_tiles * 8 <= kRowBuildWords) {
-    hipLaunchKernelGGL(bitmap_rows_kernel, grid, dim3(256), 0, s, a);
+  const bool in_lds = (int64_t)max_frame_tiles * a.seg_words <= kRowBuildWords;
+  if (in_lds && a.seg_words == 32) {
+    hipLaunchKernelGGL(bitmap_rows_kernel<32>, dim3(div_up(max_frame_splats, 1024), a.B), dim3(1024), 0, s, a);
+  } else if (in_lds && a.seg_words == 16) {
+    hipLaunchKernelGGL(bitmap_rows_kernel<16>, dim3(div_up(max_frame_splats, 512), a.B), dim3(512), 0, s, a);
+  } else if (in_lds && a.seg_words == 8) {
+    hipLaunchKernelGGL(bitmap_rows_kernel<8>, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a);
   } else {
     launch_fill_u32(a.tbits, 0u, (int64_t)a.n_tiles * a.bitmap_words, s);
-    hipLaunchKernelGGL(bitmap_rows_atomic_kernel, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(bitmap_rows_atomic_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(seg_count_kernel, dim3(div_up((int64_t)a.n_tiles * a.seg_stride, 256)), dim3(256), 0, s, a);
   }
 }
 
-// A tile's entry count is the number of set bits of its row: one wave per
-// tile, lanes over the row's words.
+// A tile's entry count is the sum of its row's segment counts: one wave per
+// tile, lanes over the segments.
 __global__ __launch_bounds__(256) void tile_count_kernel(PassArgs a) {
   const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (g >= a.n_tiles) return;
   const int lane = threadIdx.x & 63;
   const int b = frame_of_tile(a.frames, a.B, g);
   const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - a.bkt_start[b * a.nbk];
-  const uint32_t W = (nv + 31) / 32;
-  const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  const uint32_t nseg = ((nv + 31) / 32 + a.seg_words - 1) / a.seg_words;
+  const uint16_t* sc = a.seg_cnt + (int64_t)g * a.seg_stride;
   uint32_t c = 0;
-  for (uint32_t q = lane; q < W; q += 64) c += __popc(row[q]);
+  for (uint32_t q = lane; q < nseg; q += 64) c += sc[q];
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
   if (lane == 0) a.tile_count[g] = c;
 }
@@ -450,11 +513,22 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
 
 // The tile's list is read in depth order from its bitmap row, a chunk at a
 // time, as the compositing consumes it: each thread owns a run of the row's
-// words and knows (block prefix count) where its ranks fall in the sorted
-// order, and each chunk's ranks are emitted from the runs that overlap it.
-// Entries behind the point where every pixel has stopped are never ordered,
-// mapped to splats or read.  The consumed part of the sorted list is written
-// out for the backward pass.
+// segments and knows from their bit counts (block prefix count) where its
+// ranks fall in the sorted order; each chunk's ranks are emitted from the
+// segments that overlap it, which are the only row words read.  Entries
+// behind the point where every pixel has stopped are never ordered, mapped
+// to splats or read.  The consumed part of the sorted list is written out
+// for the backward pass.
+// Largest k < n with off[k] <= x (off ascending, off[0] = 0 <= x).
+__device__ __forceinline__ uint32_t last_at_most(const uint32_t* off, uint32_t n, uint32_t x) {
+  uint32_t lo = 0, hi = n - 1u;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1u) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1u;
+  }
+  return lo;
+}
+
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
@@ -467,6 +541,8 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   __shared__ uint32_t s_last;
   __shared__ uint32_t flw[S::NW];
   __shared__ uint32_t list[CHUNK];      // ranks of the chunk being staged
+  __shared__ uint16_t nzs[kMaxRowSegs];       // non-empty row segments, ascending
+  __shared__ uint32_t nzo[kMaxRowSegs + 1];   // their first positions in the tile's order
   if (a.status->overflow) return;
   const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
   if (g < 0) return;
@@ -490,36 +566,64 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
     done[p] = !inside[p];
   }
   if (threadIdx.x == 0) s_last = 0;
-  uint32_t vbase = 0, fw0 = 0, fw1 = 0, fbase = 0, fcnt = 0;
+  // the row's non-empty segments (ids) and where their entries start in
+  // the tile's order; the last offset is the tile's entry count
+  uint32_t vbase = 0, nz = 0;
   const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  const int SW = a.seg_words;
   if (end > start) {
     vbase = a.bkt_start[b * a.nbk];
     const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
-    const uint32_t W = (nv + 31) / 32;
-    const uint32_t wpt = (W + S::NT - 1) / S::NT;
-    fw0 = min(W, threadIdx.x * wpt);
-    fw1 = min(W, fw0 + wpt);
-    for (uint32_t q = fw0; q < fw1; ++q) fcnt += __popc(row[q]);
-    fbase = block_excl_scan<S::NT>(fcnt, flw, nullptr);
+    const uint32_t nseg = ((nv + 31) / 32 + SW - 1) / SW;
+    const uint32_t spt = (nseg + S::NT - 1) / S::NT;
+    const uint32_t fs0 = min(nseg, threadIdx.x * spt), fs1 = min(nseg, fs0 + spt);
+    const uint16_t* segc = a.seg_cnt + (int64_t)g * a.seg_stride;
+    uint32_t fcnt = 0, zcnt = 0;
+    for (uint32_t q = fs0; q < fs1; ++q) {
+      const uint32_t c = segc[q];
+      fcnt += c;
+      zcnt += c ? 1u : 0u;
+    }
+    uint32_t fbase = block_excl_scan<S::NT>(fcnt, flw, nullptr);
+    const uint32_t zbase = block_excl_scan<S::NT>(zcnt, flw, &nz);
+    for (uint32_t q = fs0, k = zbase; q < fs1; ++q) {
+      const uint32_t c = segc[q];
+      if (c) { nzs[k] = (uint16_t)q; nzo[k] = fbase; ++k; }
+      fbase += c;
+    }
+    if (threadIdx.x == 0) nzo[nz] = end - start;
   }
   for (uint32_t cb = start; cb < end; cb += CHUNK) {
     const int n = (int)min((uint32_t)CHUNK, end - cb);
     __syncthreads();
     {
-      // ranks of sorted positions [c0, c1) into list[]
+      // ranks of sorted positions [c0, c1) into list[]: the non-empty
+      // segments ka..kb that hold them are read a word per thread, and a
+      // word's first position is its segment's offset plus the bits of the
+      // words before it in the segment (a scan over the segment's lanes)
       const uint32_t c0 = cb - start, c1 = c0 + (uint32_t)n;
-      if (fbase < c1 && fbase + fcnt > c0) {
-        uint32_t pos = fbase;
-        for (uint32_t q = fw0; q < fw1 && pos < c1; ++q) {
-          uint32_t bits = row[q];
-          const uint32_t pc = __popc(bits);
-          if (pos + pc <= c0) { pos += pc; continue; }
-          while (bits) {
-            const uint32_t bit = __ffs(bits) - 1u;
-            bits &= bits - 1u;
-            if (pos >= c0 && pos < c1) list[pos - c0] = q * 32u + bit;
-            ++pos;
-          }
+      const uint32_t ka = last_at_most(nzo, nz, c0), kb = last_at_most(nzo, nz, c1 - 1u);
+      const uint32_t nw = (kb - ka + 1u) * (uint32_t)SW;
+      const uint32_t sh = (uint32_t)__ffs(SW) - 1u;
+      for (uint32_t base = 0; base < nw; base += S::NT) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t ic = min(i, nw - 1u);
+        const uint32_t k = ka + (ic >> sh), wi = ic & (uint32_t)(SW - 1);
+        const uint32_t wq = (uint32_t)nzs[k] * (uint32_t)SW + wi;
+        uint32_t bits = row[wq];
+        if (i >= nw) bits = 0u;
+        const uint32_t c = __popc(bits);
+        uint32_t inc = c;
+        for (int d = 1; d < SW; d <<= 1) {
+          const uint32_t o = __shfl_up(inc, d, SW);
+          if ((int)wi >= d) inc += o;
+        }
+        uint32_t pos = nzo[k] + inc - c;
+        while (bits) {
+          const uint32_t bit = __ffs(bits) - 1u;
+          bits &= bits - 1u;
+          if (pos >= c0 && pos < c1) list[pos - c0] = wq * 32u + bit;
+          ++pos;
         }
       }
       __syncthreads();
