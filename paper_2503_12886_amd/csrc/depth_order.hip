@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a
   const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
   for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
-  const uint32_t mn = a.minmax[2 * b], mx = a.minmax[2 * b + 1];
+  const uint32_t mn = a.minmax[b * kMinmaxStride], mx = a.minmax[b * kMinmaxStride + 1];
   uint32_t key[kBucketItems], bk[kBucketItems];
   load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs
   const FrameDev& F = a.frames[b];
   if ((int64_t)blk * kBucketBlock >= F.gauss_count) return;
   for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
-  const uint32_t mn = a.minmax[2 * b], mx = a.minmax[2 * b + 1];
+  const uint32_t mn = a.minmax[b * kMinmaxStride], mx = a.minmax[b * kMinmaxStride + 1];
   uint32_t key[kBucketItems], bk[kBucketItems], rk[kBucketItems];
   load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();

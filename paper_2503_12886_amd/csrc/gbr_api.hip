@@ -45,7 +45,7 @@ void dfree(T*& p) {
 // counts/cursors, per-frame depth ranges, the large-bucket list, the status.
 __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.B) { a.minmax[2 * i] = 0xffffffffu; a.minmax[2 * i + 1] = 0u; }
+  if (i < a.B) { a.minmax[i * kMinmaxStride] = 0xffffffffu; a.minmax[i * kMinmaxStride + 1] = 0u; }
   if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
 }
 
@@ -434,7 +434,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->order_fwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->order_bwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->cls_cnt, 66));
-  TRY(dalloc(&c->minmax, 2LL * c->cap_frames));
+  TRY(dalloc(&c->minmax, (int64_t)kMinmaxStride * c->cap_frames));
   TRY(dalloc(&c->big_count, 1));
   TRY(dalloc(&c->bkeys, c->cap_splats));
   TRY(dalloc(&c->bkeys_alt, c->cap_splats));

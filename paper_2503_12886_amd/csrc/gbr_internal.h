@@ -47,6 +47,8 @@ struct StatusDev {
 };
 
 // Everything the pass kernels need, passed by value.
+constexpr int kMinmaxStride = 32;
+
 struct PassArgs {
   const FrameDev* frames;
   int32_t B;
@@ -80,7 +82,8 @@ struct PassArgs {
   int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32, rounded up to 16)
   int32_t seg_words;        // words per row segment (8 or 16); a segment's set bits are counted once
   int32_t seg_stride;       // segments per row = bitmap_words / seg_words
-  uint32_t* minmax;         // [B][2] min / max binary32 depth bits of the frame's valid splats
+  uint32_t* minmax;         // [B][kMinmaxStride] min, max binary32 depth bits of the frame's valid splats
+                            //   (a 128-byte line per frame, so frames' atomics do not share a line)
   uint32_t* bkt_count;      // [B * nbk][nblk] per-block bucket counts
   uint32_t* bkt_moff;       // [B * nbk * nblk + 1] their exclusive scan
   uint32_t* bkt_start;      // [B * nbk + 1] exclusive scan; frame b's valid splats start at bkt_start[b * nbk]

@@ -217,6 +217,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
   uint32_t dmin = 0xffffffffu, dmax = 0u;
   if (n < F.gauss_count) {
     const int64_t s = F.gauss_base + n;
+    const float4 col = reinterpret_cast<const float4*>(raw + s * kNF)[2];   // colour: .w, then the next row
+    const float4 col2 = reinterpret_cast<const float4*>(raw + s * kNF)[3];
     Projected p;
     project_gaussian(raw + s * kNF, F, p);
     float* rec = a.rec + s * kRecF;
@@ -226,8 +228,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
       r = make_int4(p.x0 >> tsh, p.y0 >> tsh, p.x1 >> tsh, p.y1 >> tsh);
       count = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
       const float4 r0 = make_float4((float)p.mx, (float)p.my, (float)(-0.5 * kLog2e * p.A), (float)(-kLog2e * p.Bq));
-      const float4 r1 = make_float4((float)(-0.5 * kLog2e * p.C), (float)p.o, raw[s * kNF + 11], raw[s * kNF + 12]);
-      const float4 r2 = make_float4(raw[s * kNF + 13], (float)p.tz,
+      const float4 r1 = make_float4((float)(-0.5 * kLog2e * p.C), (float)p.o, col.w, col2.x);
+      const float4 r2 = make_float4(col2.y, (float)p.tz,
                                     __uint_as_float((uint32_t)p.x0 | ((uint32_t)p.x1 << 16)),
                                     __uint_as_float((uint32_t)p.y0 | ((uint32_t)p.y1 << 16)));
       reinterpret_cast<float4*>(rec)[0] = r0;
@@ -251,8 +253,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
     dmin = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
     dmax = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
     if (dmin <= dmax) {
-      atomicMin(&a.minmax[2 * b], dmin);
-      atomicMax(&a.minmax[2 * b + 1], dmax);
+      atomicMin(&a.minmax[b * kMinmaxStride], dmin);
+      atomicMax(&a.minmax[b * kMinmaxStride + 1], dmax);
     }
   }
 }
