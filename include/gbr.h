@@ -208,9 +208,10 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
                  int32_t* best_tile, int32_t* best_chunk, float* times_ms);
 
 /* Copy an internal buffer of the last pass to host memory (synchronises).
-   what: 1 splat records [S][12] f32 (mx, my, ca, cb, cc, opacity, r, g, b,
-   depth, pixel box x, pixel box y; ca, cb, cc = -log2(e) * (A/2, B, C/2)
-   of the conic q = A dx^2 + 2B dx dy + C dy^2; the two pixel-box slots hold
+   what: 1 splat records [S][12] f32 (mx, my, ca, cb, cc, log2 opacity, r, g,
+   b, depth, pixel box x, pixel box y; ca, cb, cc = -log2(e) * (A/2, B, C/2)
+   of the conic q = A dx^2 + 2B dx dy + C dy^2, so that alpha =
+   2^(ca dx^2 + cb dx dy + cc dy^2 + log2 opacity); the two pixel-box slots hold
    the bits of u32 values x0 | x1 << 16 and y0 | y1 << 16, the inclusive
    pixel range of the alpha >= 1/255 support), 2 tile rects [S][4] i32 (inclusive
    tx0, ty0, tx1, ty1), 3 tile starts [tiles+1] u32 (tile g's entries are
@@ -219,7 +220,9 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
    each tile only as far as it composited, this call completes them first),
    5 per-pixel list position after the last contributor [pixels] u32,
    6 per-pixel final transmittance [pixels] f32, 7 per-tile entries used
-   [tiles] u32, 8 per-pixel number of contributing Gaussians [pixels] u32,
+   [tiles] u32, 8 per-pixel number of contributing Gaussians [pixels] u32
+   (counted by this call from the complete lists: the entries before the
+   pixel's stop position with alpha >= 1/255),
    9 per-entry contribution mask [entries] u8: bit w set when some pixel of
    the tile's quadrant w (tiles of 16 and 32 px: quadrants of half the side,
    w = 2 * (row half) + (column half); tiles of 8 px: one quadrant, bit 0)

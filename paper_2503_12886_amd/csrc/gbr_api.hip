@@ -786,7 +786,11 @@ int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
     case 5: src = c->n_iter; n = c->n_pixels * 4; break;
     case 6: src = c->t_final; n = c->n_pixels * 4; break;
     case 7: src = c->tile_last; n = (int64_t)c->n_tiles * 4; break;
-    case 8: src = c->n_contrib; n = c->n_pixels * 4; break;
+    case 8:   // contributors per pixel, counted on request from the complete lists
+      launch_tile_lists(make_args(c), nullptr);
+      launch_count_contrib(make_args(c), nullptr);
+      GBR_HIP(hipDeviceSynchronize());
+      src = c->n_contrib; n = c->n_pixels * 4; break;
     case 9: src = c->cmask; n = entries; break;
     default: return GBR_ERR_INVALID_ARG;
   }

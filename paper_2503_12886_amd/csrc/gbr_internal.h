@@ -14,6 +14,7 @@ constexpr float kTMin = 1e-4f;             // transmittance stop
 constexpr double kLowPass = 0.3;           // px^2 added to the 2D covariance
 constexpr double kBoxPad = 0.01;           // px added to the alpha-support box
 constexpr double kLog2e = 1.4426950408889634;
+constexpr float kLog2_255 = 7.99435343685886f;   // log2(255): alpha >= 1/255 <=> log2(alpha) >= -kLog2_255
 constexpr double kLn2 = 0.6931471805599453;
 constexpr int kRecF = 12;
 constexpr int kPartF = 12;          // floats per partial record: 9 values, padded to 48 B (3 x 16-B loads)                  // floats per splat record
@@ -60,7 +61,7 @@ struct PassArgs {
   int64_t cap_entries;
   StatusDev* status;
   // splat stage
-  float* rec;               // [S][12]: mx my ca cb | cc o r g | b depth box_x box_y
+  float* rec;               // [S][12]: mx my ca cb | cc lo r g | b depth box_x box_y (lo = log2 opacity)
                             //   box_x = x0 | x1 << 16, box_y = y0 | y1 << 16 (pixel box, as bits)
   int4* rect;               // [S] inclusive tile rect (tx0, ty0, tx1, ty1)
   uint32_t* cnt;            // [S] tiles touched
@@ -95,7 +96,7 @@ struct PassArgs {
   uint32_t* big_count;      // [1]
   // pixel stage
   uint32_t* n_iter;         // [pixels] list position after the last contributor
-  uint32_t* n_contrib;      // [pixels] number of contributors
+  uint32_t* n_contrib;      // [pixels] number of contributors (computed on request)
   float* t_final;           // [pixels]
   float* part;              // [E][kPartF] per-entry gradient partials (9 used), by emission slot
   uint8_t* part_flag;       // [E] 1 where the entry's partial is non-zero and written
@@ -253,6 +254,7 @@ int bitmap_seg_words(int max_frame_tiles, int64_t row_words);
 void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s);
 void launch_tile_lists(const PassArgs& a, hipStream_t s);
 void launch_tile_count(const PassArgs& a, hipStream_t s);
+void launch_count_contrib(const PassArgs& a, hipStream_t s);
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
 
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);

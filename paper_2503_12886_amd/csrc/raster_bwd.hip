@@ -8,28 +8,30 @@ namespace gbr {
 
 template <int T> using TileShapeB = TileMap<T>;
 
-// Must stay bit-identical to the forward kernel's alpha.
+// Must stay bit-identical to the forward kernel's alpha: power = ca dx^2 +
+// cb dx dy + cc dy^2 + lo (lo = log2 opacity), alpha = 2^min(power, lo).
 __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, float py, float& dx, float& dy,
-                                               float& pw_raw, float& g2) {
+                                               float& pw_raw) {
 #pragma clang fp contract(off)
   dx = px - r0.x;
   dy = py - r0.y;
-  float pw = (r0.z * dx) * dx;
+  float pw = __builtin_fmaf(r0.z * dx, dx, r1.y);
   pw = __builtin_fmaf(r0.w * dx, dy, pw);
   pw = __builtin_fmaf(r1.x * dy, dy, pw);
   pw_raw = pw;
-  pw = fminf(pw, 0.0f);
-  g2 = __builtin_amdgcn_exp2f(pw);
-  return r1.y * g2;
+  return __builtin_amdgcn_exp2f(fminf(pw, r1.y));
 }
 
-// Per-entry partial, summed over the tile's pixels:
-//   (sum dpw dx, sum dpw dy, d ca, d cb, d cc, d opacity, d r, d g, d b)
-// where ca, cb, cc are the log2-scaled conic coefficients of the record,
-// dpw = dL/d(power) at a pixel and (dx, dy) its offset from the mean; the
-// mean's gradient -(2 ca, cb; cb, 2 cc) (sum dpw dx, sum dpw dy) is formed
-// once per splat, after the sums.  Along the traversal each lane keeps only
-// the transmittance and <colour behind, dL/dout>.
+// Per-entry partial, summed over the tile's pixels, in units of t = alpha *
+// dL/dalpha (the gradient with respect to the power is t ln 2):
+//   (sum t dx, sum t dy, sum t dx^2, sum t dx dy, sum t dy^2, sum t,
+//    d r, d g, d b)
+// with (dx, dy) the pixel's offset from the mean.  The splat's gradients
+// follow once per splat, after the sums: the power's coefficients ca, cb, cc
+// get ln 2 times the three second moments, the mean -ln 2 (2 ca, cb; cb,
+// 2 cc) times the first moments, the opacity logit (1 - o) sum t.  Along the
+// traversal each lane keeps only the transmittance and <colour behind,
+// dL/dout>.
 // A wave's sum over its lanes is taken in a fixed order (lane folds, then
 // in-row shifts); the block then adds its waves in order and writes the
 // entry's partial, by emission slot, only if some pixel contributed; a byte
@@ -48,8 +50,8 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
   any = false;
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
-    float dx, dy, pwr, g2;
-    const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr, g2);
+    float dx, dy, pwr;
+    const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr);
     const bool take = li < nit[p] && a0 >= kAlphaMin;
     any = any || take;
     const float al = fminf(a0, kAlphaMax);
@@ -62,10 +64,11 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
     SG[p] += wgt * cg;                                // <colour behind, dL/dout>
     T_[p] = take ? Ti : T_[p];
     // min(0.99, .) passes the gradient only below the clamp
-    const float da = (take && a0 < kAlphaMax) ? dal : 0.0f;
-    acc[5] += g2 * da;
-    const float dpw = (pwr > 0.0f) ? 0.0f : da * a0 * (float)kLn2;
-    const float p1 = dpw * dx, p2 = dpw * dy;
+    const float t = (take && a0 < kAlphaMax) ? a0 * dal : 0.0f;
+    acc[5] += t;
+    // power clamped at log2 o (q < 0 by rounding): no gradient to the conic or mean
+    const float tq = (pwr > r1.y) ? 0.0f : t;
+    const float p1 = tq * dx, p2 = tq * dy;
     acc[0] += p1;
     acc[1] += p2;
     acc[2] += p1 * dx;
@@ -363,9 +366,12 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   const double QA = scc / det, QB = -sb / det, QC = sa / det;
 
   // ---- record-space gradient -> conic coefficients of q = A dx^2 + 2B dx dy + C dy^2 ----
-  const double dA = (double)acc[2] * (-0.5 * kLog2e);
-  const double dB = (double)acc[3] * (-kLog2e);      // cb = -log2e * B  (coefficient of dx dy is 2B)
-  const double dC = (double)acc[4] * (-0.5 * kLog2e);
+  // dL/dpower = ln 2 * alpha * dL/dalpha, so the moments of t carry a factor ln 2
+  double am[5];
+  for (int k = 0; k < 5; ++k) am[k] = (double)acc[k] * kLn2;
+  const double dA = am[2] * (-0.5 * kLog2e);
+  const double dB = am[3] * (-kLog2e);      // cb = -log2e * B  (coefficient of dx dy is 2B)
+  const double dC = am[4] * (-0.5 * kLog2e);
   // conic -> Sigma2 (symmetric):  dS = -Q dQ Q with dQ = [[dA, dB/2], [dB/2, dC]]
   const double h = 0.5 * dB;
   const double t00 = QA * dA + QB * h, t01 = QA * h + QB * dC;
@@ -395,8 +401,8 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   // jx = fx/tz, ux = -fx tx/tz^2, jy = fy/tz, uy = -fy ty/tz^2; mean = (fx tx/tz + cx, fy ty/tz + cy)
   // mean: d power / d mean = -(2 ca dx + cb dy, cb dx + 2 cc dy), summed as (sum dpw dx, sum dpw dy)
   const double ca = -0.5 * kLog2e * QA, cbq = -kLog2e * QB, cc = -0.5 * kLog2e * QC;
-  const double dmx = -(2.0 * ca * (double)acc[0] + cbq * (double)acc[1]);
-  const double dmy = -(cbq * (double)acc[0] + 2.0 * cc * (double)acc[1]);
+  const double dmx = -(2.0 * ca * am[0] + cbq * am[1]);
+  const double dmy = -(cbq * am[0] + 2.0 * cc * am[1]);
   double dtx = dux * (-fx * iz * iz) + dmx * fx * iz;
   double dty = duy * (-fy * iz * iz) + dmy * fy * iz;
   double dtz = djx * (-fx * iz * iz) + dux * (2.0 * fx * tx * iz * iz * iz) + djy * (-fy * iz * iz) +
@@ -419,7 +425,8 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   const double qh[4] = {qw, qx, qy, qz};
   for (int k = 0; k < 4; ++k) res[3 + k] = (float)((dq[k] - qh[k] * dotq) / qlen);
   for (int k = 0; k < 3; ++k) res[7 + k] = (float)(ds[k] * sc[k]);
-  res[10] = (float)((double)acc[5] * o * (1.0 - o));
+  // alpha = 2^(... + log2 o), o = sigmoid(logit):  dL/dlogit = (1 - o) * sum alpha dL/dalpha
+  res[10] = (float)((double)acc[5] * (1.0 - o));
   res[11] = acc[6]; res[12] = acc[7]; res[13] = acc[8];
   res[14] = 0.0f; res[15] = 0.0f;
   out[0] = make_float4(res[0], res[1], res[2], res[3]);

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
       r = make_int4(p.x0 >> tsh, p.y0 >> tsh, p.x1 >> tsh, p.y1 >> tsh);
       count = (uint32_t)((r.z - r.x + 1) * (r.w - r.y + 1));
       const float4 r0 = make_float4((float)p.mx, (float)p.my, (float)(-0.5 * kLog2e * p.A), (float)(-kLog2e * p.Bq));
-      const float4 r1 = make_float4((float)(-0.5 * kLog2e * p.C), (float)p.o, col.w, col2.x);
+      const float4 r1 = make_float4((float)(-0.5 * kLog2e * p.C), (float)log2(p.o), col.w, col2.x);
       const float4 r2 = make_float4(col2.y, (float)p.tz,
                                     __uint_as_float((uint32_t)p.x0 | ((uint32_t)p.x1 << 16)),
                                     __uint_as_float((uint32_t)p.y0 | ((uint32_t)p.y1 << 16)));
@@ -476,7 +476,7 @@ template <int T> using TileShape = TileMap<T>;
 // Whether a splat's alpha >= 1/255 region may reach the rectangle
 // [x0, x1] x [y0, y1] of pixel centres: the maximum of the concave power
 // ca dx^2 + cb dx dy + cc dy^2 over the rectangle (the mean inside: 0; else
-// the best point of the four edges) against log2(1 / (255 o)), less a margin
+// the best point of the four edges) against -log2(255) - log2(o), less a margin
 // of 0.01 that keeps the test conservative under float32 rounding (at that
 // margin alpha is 0.7 % below the threshold).  A splat that cannot reach a
 // pixel is never taken there, so skipping it changes nothing.
@@ -494,23 +494,22 @@ __device__ __forceinline__ bool strip_reach(float4 r0, float4 r1, float x0, floa
     best = fmaxf(best, ca * xa * xa + cb * xa * y0 + cc * y0 * y0);
     best = fmaxf(best, ca * xb * xb + cb * xb * y1 + cc * y1 * y1);
   }
-  return best >= -__log2f(255.0f * r1.y) - 0.01f;
+  return best >= -kLog2_255 - r1.y - 0.01f;
 }
 
 // alpha of a splat at a pixel, bit-identical wherever it is evaluated:
-// power = ca dx^2 + cb dx dy + cc dy^2 (= -q/2 in log2 units), alpha = o 2^power.
+// power = ca dx^2 + cb dx dy + cc dy^2 (= -q/2 in log2 units) plus lo =
+// log2(opacity), clamped at lo (q >= 0), and alpha = 2^power = o 2^(-q/2 log2 e).
 __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, float py, float& dx, float& dy,
-                                             float& pw_raw, float& g2) {
+                                             float& pw_raw) {
 #pragma clang fp contract(off)
   dx = px - r0.x;
   dy = py - r0.y;
-  float pw = (r0.z * dx) * dx;
+  float pw = __builtin_fmaf(r0.z * dx, dx, r1.y);
   pw = __builtin_fmaf(r0.w * dx, dy, pw);
   pw = __builtin_fmaf(r1.x * dy, dy, pw);
   pw_raw = pw;
-  pw = fminf(pw, 0.0f);
-  g2 = __builtin_amdgcn_exp2f(pw);
-  return r1.y * g2;
+  return __builtin_amdgcn_exp2f(fminf(pw, r1.y));
 }
 
 // The tile's list is read in depth order from its bitmap row, a chunk at a
@@ -521,6 +520,14 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
 // behind the point where every pixel has stopped are never ordered, mapped
 // to splats or read.  The consumed part of the sorted list is written out
 // for the backward pass.
+// A staged splat record: mean, log2-scaled conic, log2 opacity, colour.
+struct __align__(16) StagedRec {
+  float4 r0;    // mx my ca cb
+  float4 r1;    // cc lo r g (lo = log2 opacity)
+  float cb;     // b
+  float pad[3];
+};
+
 // Largest k < n with off[k] <= x (off ascending, off[0] = 0 <= x).
 __device__ __forceinline__ uint32_t last_at_most(const uint32_t* off, uint32_t n, uint32_t x) {
   uint32_t lo = 0, hi = n - 1u;
@@ -535,9 +542,7 @@ template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
   constexpr int U = 4;                  // entries evaluated together (independent alphas)
-  __shared__ float4 s0[CHUNK + U];
-  __shared__ float4 s1[CHUNK + U];
-  __shared__ float s2[CHUNK + U];
+  __shared__ StagedRec sr[CHUNK + U];   // the chunk's splat records (one LDS address per entry)
   __shared__ uint32_t wbits[S::NW][CHUNK / 32];
   __shared__ uint8_t wact[S::NW];
   __shared__ uint32_t s_last;
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lx0 = S::lx0(threadIdx.x), ly0 = S::ly0(threadIdx.x);
   float T_[S::PX], C0[S::PX], C1[S::PX], C2[S::PX], pxf[S::PX], pyf[S::PX];
-  uint32_t last[S::PX], ncon[S::PX];
+  uint32_t last[S::PX];
   bool done[S::PX], inside[S::PX];
 #pragma unroll
   for (int p = 0; p < S::PX; ++p) {
@@ -564,7 +569,7 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
     pxf[p] = (float)px + 0.5f;
     pyf[p] = (float)py + 0.5f;
     inside[p] = px < F.W && py < F.H;
-    T_[p] = 1.0f; C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0; ncon[p] = 0;
+    T_[p] = 1.0f; C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0;
     done[p] = !inside[p];
   }
   if (threadIdx.x == 0) s_last = 0;
@@ -633,13 +638,13 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
         const uint32_t sp = a.depth_sorted[vbase + list[i]];
         a.sorted[cb + i] = sp;
         const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
-        s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+        sr[i].r0 = rec[0]; sr[i].r1 = rec[1]; sr[i].cb = rec[2].x;
       }
     }
-    if (threadIdx.x < U) {                 // padding entries: opacity 0, never taken
-      s0[n + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-      s1[n + threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-      s2[n + threadIdx.x] = 0.f;
+    if (threadIdx.x < U) {                 // padding entries: opacity 0 (log2 -1e30), never taken
+      sr[n + threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      sr[n + threadIdx.x].r1 = make_float4(0.f, -1e30f, 0.f, 0.f);
+      sr[n + threadIdx.x].cb = 0.f;
     }
     __syncthreads();
     bool mine = false;
@@ -659,33 +664,31 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
         unsigned long long cand = 0ull;
         if (live) {
           const int idx = gb + lane;
-          cand = __ballot(idx < n && strip_reach(s0[idx], s1[idx], sx0, sx1, sy0, sy1));
+          cand = __ballot(idx < n && strip_reach(sr[idx].r0, sr[idx].r1, sx0, sx1, sy0, sy1));
         }
         unsigned long long tookm = 0ull;
         while (cand) {
           int e[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            e[u] = n + u;                  // padding entry: opacity 0, never taken
-            if (cand) {
-              e[u] = gb + (__ffsll((long long)cand) - 1);
-              cand &= cand - 1ull;
-            }
+            const int f = __ffsll((long long)cand) - 1;   // -1 once the candidates run out
+            cand &= cand - 1ull;
+            e[u] = f >= 0 ? gb + f : n + u;                // padding entry: opacity 0, never taken
           }
           float4 r0[U], r1[U];
           float cb2[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) { r0[u] = s0[e[u]]; r1[u] = s1[e[u]]; cb2[u] = s2[e[u]]; }
-          bool took[U];
+          for (int u = 0; u < U; ++u) { r0[u] = sr[e[u]].r0; r1[u] = sr[e[u]].r1; cb2[u] = sr[e[u]].cb; }
+          unsigned long long tm[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) took[u] = false;
+          for (int u = 0; u < U; ++u) tm[u] = 0ull;
 #pragma unroll
           for (int p = 0; p < S::PX; ++p) {
             float al[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              float dx, dy, pwr, g2;
-              al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr, g2);
+              float dx, dy, pwr;
+              al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -703,13 +706,12 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
               C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
               T_[p] = take ? tn : T_[p];
               last[p] = take ? (cb - start + (uint32_t)e[u] + 1u) : last[p];
-              ncon[p] += take ? 1u : 0u;
-              took[u] = took[u] || take;
+              tm[u] |= __builtin_amdgcn_ballot_w64(take);
             }
           }
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            if (__ballot(took[u]) != 0ull) tookm |= 1ull << (e[u] - gb);
+            if (tm[u]) tookm |= 1ull << (e[u] - gb);
           bool mine_now = false;
 #pragma unroll
           for (int p = 0; p < S::PX; ++p) mine_now |= !done[p];
@@ -749,7 +751,6 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
       img[hw + pix] = C1[p] + T_[p] * F.bg[1];
       img[2 * hw + pix] = C2[p] + T_[p] * F.bg[2];
       a.n_iter[F.pix_base + pix] = last[p];
-      a.n_contrib[F.pix_base + pix] = ncon[p];
       a.t_final[F.pix_base + pix] = T_[p];
       my_last = max(my_last, last[p]);
     }
@@ -774,6 +775,40 @@ void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream
   else { GBR_FWD_T(32) }
 #undef GBR_FWD_T
 #undef GBR_FWD
+}
+
+// Contributors per pixel, on request: the entries before the pixel's stop
+// position whose alpha reaches 1/255 (every such entry was taken, nothing
+// after the stop was).  Reads the complete per-tile lists; a workgroup per
+// tile, a thread per pixel.  Diagnostic only, not part of a pass.
+__global__ __launch_bounds__(256) void count_contrib_kernel(PassArgs a) {
+  const int g = blockIdx.x;
+  if (a.status->overflow || g >= a.n_tiles) return;
+  const int b = frame_of_tile(a.frames, a.B, g);
+  const FrameDev& F = a.frames[b];
+  const int T = a.tile;
+  const int lt = g - F.tile_base;
+  const int tx = lt % F.ntx, ty = lt / F.ntx;
+  const uint32_t start = a.tile_start[g];
+  for (int q = threadIdx.x; q < T * T; q += 256) {
+    const int px = tx * T + q % T, py = ty * T + q / T;
+    if (px >= F.W || py >= F.H) continue;
+    const int64_t pix = F.pix_base + (int64_t)py * F.W + px;
+    const uint32_t nit = a.n_iter[pix];
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < nit; ++i) {
+      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)a.sorted[start + i] * kRecF);
+      float dx, dy, pwr;
+      const float al = splat_alpha(rec[0], rec[1], (float)px + 0.5f, (float)py + 0.5f, dx, dy, pwr);
+      c += al >= kAlphaMin ? 1u : 0u;
+    }
+    a.n_contrib[pix] = c;
+  }
+}
+
+void launch_count_contrib(const PassArgs& a, hipStream_t s) {
+  if (a.n_tiles == 0) return;
+  hipLaunchKernelGGL(count_contrib_kernel, dim3(a.n_tiles), dim3(256), 0, s, a);
 }
 
 }  // namespace gbr

@@ -62,7 +62,7 @@ def test_projection_records_and_rects():
         assert np.array_equal(r[v, 9], p["key"][v].astype(np.float32))
         # float32 records of float64 quantities
         for col, ref in ((0, p["mx"]), (1, p["my"]), (2, -0.5 * log2e * p["A"]), (3, -log2e * p["B"]),
-                         (4, -0.5 * log2e * p["C"]), (5, p["opacity"])):
+                         (4, -0.5 * log2e * p["C"]), (5, np.log2(p["opacity"]))):
             assert np.allclose(r[v, col], ref[v], rtol=2e-7, atol=1e-30), col
 
 
