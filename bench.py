@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--per-frame-frames", type=int, default=48)
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--chunk", type=int, default=128)
+    ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -228,7 +228,10 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
    w = 2 * (row half) + (column half); tiles of 8 px: one quadrant, bit 0)
    took the entry in the forward pass, 10 the sorted entries [entries] u32
    as the pass left them (each tile's list is valid at least up to its
-   last used position, 7).
+   last used position, 7), 11 per-tile, per-quadrant entries used
+   [tiles][4] u32 (quadrant w's pixels took nothing at or past position
+   [g][w] of tile g's list; 7 is the largest of the four; tiles of 8 px
+   have one quadrant, w = 0, the others 0).
    *bytes in: capacity of dst; out: bytes written. */
 int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
 

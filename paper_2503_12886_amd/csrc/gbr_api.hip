@@ -55,7 +55,7 @@ __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u
 
 struct gbr_ctx {
   gbr_config cfg;
-  int tile = 16, chunk = 128;
+  int tile = 16, chunk = 64;
   int64_t cap_entries = 0, cap_splats = 0, cap_pixels = 0, cap_tiles = 0;
   int cap_frames = 0;
   // device workspace
@@ -64,7 +64,7 @@ struct gbr_ctx {
   float* rec = nullptr;
   int4* rect = nullptr;
   uint32_t *cnt = nullptr, *soff = nullptr, *dkey = nullptr;
-  uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_last = nullptr;
+  uint32_t *tile_count = nullptr, *tile_start = nullptr, *tile_last = nullptr, *qlast = nullptr;
   uint32_t* tbits = nullptr;        // [cap_tbits] per-tile rank bitmap rows
   int64_t cap_tbits = 0;
   uint16_t* seg_cnt = nullptr;      // [cap_seg] set bits per row segment
@@ -136,7 +136,7 @@ PassArgs make_args(gbr_ctx* c) {
   a.status = c->d_status;
   a.rec = c->rec; a.rect = c->rect; a.cnt = c->cnt; a.soff = c->soff; a.dkey = c->dkey;
   a.tile_count = c->tile_count; a.tile_start = c->tile_start;
-  a.tile_last = c->tile_last;
+  a.tile_last = c->tile_last; a.qlast = c->qlast;
   a.order_fwd = c->order_fwd; a.order_bwd = c->order_bwd; a.cls_cnt = c->cls_cnt;
   a.tbits = c->tbits; a.sorted = c->sorted; a.part_flag = c->part_flag; a.cmask = c->cmask;
   a.nbk = c->nbk;
@@ -177,7 +177,7 @@ int alloc_entries(gbr_ctx* c, int64_t cap) {
   int rc = GBR_OK;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
   if ((rc = dalloc(&c->part_flag, cap + 64))) return rc;   // gather reads 64-entry flag windows
-  if ((rc = dalloc(&c->cmask, cap))) return rc;
+  if ((rc = dalloc(&c->cmask, 4 * cap))) return rc;   // a byte per quadrant
   if ((rc = dalloc(&c->part, cap * kPartF))) return rc;
   c->cap_entries = cap;
   return GBR_OK;
@@ -197,7 +197,7 @@ int alloc_buckets(gbr_ctx* c, int64_t n, int64_t cells) {
 
 void free_all(gbr_ctx* c) {
   dfree(c->d_frames); dfree(c->d_status); dfree(c->rec); dfree(c->rect); dfree(c->cnt); dfree(c->soff); dfree(c->dkey);
-  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->tbits); dfree(c->seg_cnt);
+  dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->qlast); dfree(c->tbits); dfree(c->seg_cnt);
   dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
@@ -431,6 +431,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->tile_count, c->cap_tiles));
   TRY(dalloc(&c->tile_start, c->cap_tiles + 1));
   TRY(dalloc(&c->tile_last, c->cap_tiles));
+  TRY(dalloc(&c->qlast, 4 * c->cap_tiles));
   TRY(dalloc(&c->order_fwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->order_bwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->cls_cnt, 66));
@@ -791,7 +792,27 @@ int gbr_inspect(gbr_ctx* c, int32_t what, void* dst, int64_t* bytes) {
       launch_count_contrib(make_args(c), nullptr);
       GBR_HIP(hipDeviceSynchronize());
       src = c->n_contrib; n = c->n_pixels * 4; break;
-    case 9: src = c->cmask; n = entries; break;
+    case 9: {   // one byte per entry, bit w = quadrant w's byte, valid below the quadrant's last position
+      if (*bytes < entries) return GBR_ERR_CAPACITY;
+      std::vector<uint32_t> q4((size_t)entries), ts((size_t)c->n_tiles + 1), ql((size_t)c->n_tiles * 4);
+      if (entries > 0) GBR_HIP(hipMemcpy(q4.data(), c->cmask, (size_t)entries * 4, hipMemcpyDeviceToHost));
+      GBR_HIP(hipMemcpy(ts.data(), c->tile_start, ts.size() * 4, hipMemcpyDeviceToHost));
+      GBR_HIP(hipMemcpy(ql.data(), c->qlast, ql.size() * 4, hipMemcpyDeviceToHost));
+      uint8_t* d8 = static_cast<uint8_t*>(dst);
+      std::memset(d8, 0, (size_t)entries);
+      for (int g = 0; g < c->n_tiles; ++g) {
+        for (int64_t i = ts[g]; i < (int64_t)ts[g + 1] && i < entries; ++i) {
+          const uint32_t v = q4[(size_t)i];
+          uint8_t m = 0;
+          for (int w = 0; w < 4; ++w)
+            if ((uint32_t)(i - ts[g]) < ql[(size_t)g * 4 + w] && ((v >> (8 * w)) & 1u)) m |= (uint8_t)(1u << w);
+          d8[i] = m;
+        }
+      }
+      *bytes = entries;
+      return GBR_OK;
+    }
+    case 11: src = c->qlast; n = (int64_t)c->n_tiles * 16; break;
     default: return GBR_ERR_INVALID_ARG;
   }
   if (*bytes < n) return GBR_ERR_CAPACITY;

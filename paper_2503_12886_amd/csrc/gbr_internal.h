@@ -70,7 +70,8 @@ struct PassArgs {
   // tile stage
   uint32_t* tile_count;     // [tiles]
   uint32_t* tile_start;     // [tiles + 1]
-  uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel
+  uint32_t* tile_last;      // [tiles] entries used by the tile's last pixel (the largest of qlast)
+  uint32_t* qlast;          // [tiles][4] entries used by the last pixel of each quadrant (wave) of the tile
   uint32_t* tbits;          // [tiles][bitmap_words] per-tile bitmaps of frame-local depth ranks
   uint16_t* seg_cnt;        // [tiles][seg_stride] set bits of each row segment
   uint32_t* sorted;         // [E] splat index in tile order
@@ -100,7 +101,7 @@ struct PassArgs {
   float* t_final;           // [pixels]
   float* part;              // [E][kPartF] per-entry gradient partials (9 used), by emission slot
   uint8_t* part_flag;       // [E] 1 where the entry's partial is non-zero and written
-  uint8_t* cmask;           // [E] bit w: some pixel of wave w of the tile took this entry (forward)
+  uint8_t* cmask;           // [E][4] byte w = 1: some pixel of quadrant w of the tile took this entry (forward)
 };
 
 __device__ __forceinline__ int frame_of_tile(const FrameDev* frames, int B, int g) {

@@ -87,19 +87,20 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   __shared__ float s2[CHUNK];
   __shared__ float red[CHUNK][S::NW][9];
   __shared__ uint32_t wany[CHUNK];         // byte w: wave w wrote red[i][w]
-  __shared__ uint8_t cm[CHUNK];
+  __shared__ uint32_t cm[CHUNK];          // byte w: quadrant w took the entry
   __shared__ uint32_t sid[CHUNK];
   if (a.status->overflow) return;
   const int g = tile_of_rank(a.cls_cnt + 33, a.order_bwd, a.n_tiles, blockIdx.x);
   if (g < 0) return;
   const uint32_t L = a.tile_last[g];
   if (L == 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t Lw = a.qlast[g * 4 + w];    // this wave's quadrant took nothing at or past Lw
   const int b = frame_of_tile(a.frames, a.B, g);
   const FrameDev& F = a.frames[b];
   const int lt = g - F.tile_base;
   const int tx = lt % F.ntx, ty = lt / F.ntx;
   const uint32_t start = a.tile_start[g];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int lx0 = S::lx0(threadIdx.x), ly0 = S::ly0(threadIdx.x);
   float T_[S::PX], SG[S::PX], G0[S::PX], G1[S::PX], G2[S::PX];
   uint32_t nit[S::PX];
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
       const uint32_t sp = a.sorted[start + cbeg + i];
       const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
       s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
-      cm[i] = a.cmask[start + cbeg + i];
+      cm[i] = reinterpret_cast<const uint32_t*>(a.cmask)[start + cbeg + i];
       sid[i] = sp;
       wany[i] = 0u;
     }
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     // mask bit), visited back to front in pairs.
     for (int gb = (n - 1) & ~63; gb >= 0; gb -= 64) {
       const int idx = gb + lane;
-      unsigned long long m = __ballot(idx < n && ((cm[idx] >> w) & 1));
+      unsigned long long m = __ballot(idx < n && (uint32_t)(cbeg + idx) < Lw && ((cm[idx] >> (8 * w)) & 1u));
       while (m) {
         int e[U];
         int cnt = 0;

@@ -401,7 +401,8 @@ void launch_tile_count(const PassArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- tile classes
-// Forward: work = list length; backward: entries the forward pass used.  A
+// Forward: work = list length; backward: entries the forward pass used (also
+// written out as the tile's last used position).  A
 // workgroup of 1024 tiles counts its tiles per class in LDS, reserves one
 // range per class in the class lists (33 global atomics), and writes its
 // tiles there.
@@ -413,7 +414,14 @@ __global__ __launch_bounds__(1024) void classify_tiles_kernel(PassArgs a, int ba
   int c = -1;
   uint32_t slot = 0;
   if (g < a.n_tiles) {
-    const uint32_t work = backward ? a.tile_last[g] : a.tile_start[g + 1] - a.tile_start[g];
+    uint32_t work;
+    if (backward) {                       // the tile's last used position: the largest of its quadrants'
+      const uint4 ql = reinterpret_cast<const uint4*>(a.qlast)[g];
+      work = max(max(ql.x, ql.y), max(ql.z, ql.w));
+      a.tile_last[g] = work;
+    } else {
+      work = a.tile_start[g + 1] - a.tile_start[g];
+    }
     c = work_class(work);
     slot = atomicAdd(&cnt[c], 1u);
   }
@@ -512,14 +520,6 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
   return __builtin_amdgcn_exp2f(fminf(pw, r1.y));
 }
 
-// The tile's list is read in depth order from its bitmap row, a chunk at a
-// time, as the compositing consumes it: each thread owns a run of the row's
-// segments and knows from their bit counts (block prefix count) where its
-// ranks fall in the sorted order; each chunk's ranks are emitted from the
-// segments that overlap it, which are the only row words read.  Entries
-// behind the point where every pixel has stopped are never ordered, mapped
-// to splats or read.  The consumed part of the sorted list is written out
-// for the backward pass.
 // A staged splat record: mean, log2-scaled conic, log2 opacity, colour.
 struct __align__(16) StagedRec {
   float4 r0;    // mx my ca cb
@@ -528,41 +528,49 @@ struct __align__(16) StagedRec {
   float pad[3];
 };
 
-// Largest k < n with off[k] <= x (off ascending, off[0] = 0 <= x).
-__device__ __forceinline__ uint32_t last_at_most(const uint32_t* off, uint32_t n, uint32_t x) {
-  uint32_t lo = 0, hi = n - 1u;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1u) >> 1;
-    if (off[mid] <= x) lo = mid; else hi = mid - 1u;
-  }
-  return lo;
-}
-
+// One wave per (tile, quadrant): each wave composites its quadrant's pixels
+// on its own, with no barrier shared with the other quadrants of the tile,
+// and stops as soon as its own pixels have stopped.  The tile's list is read
+// in depth order from its bitmap row, a chunk at a time, as the compositing
+// consumes it: a cursor walks the row's segments 64 at a time (their bit
+// counts, prefix-summed across the wave, place each segment in the tile's
+// order), and the words of the segments that overlap the chunk are read a
+// word per lane.  Entries behind the wave's stop are never ordered, mapped
+// to splats or read.  The consumed part of the sorted list is written out
+// for the backward pass (the quadrant waves of a tile write identical
+// values), with a per-quadrant contribution byte per entry and the
+// quadrant's last used position.  The quadrant waves of a tile get block
+// indices of the same residue mod 8, so that they run on one XCD and share
+// its L2.
 template <int T, int CHUNK>
-__global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
+__global__ __launch_bounds__(64) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
+  constexpr int NQ = S::NW;             // quadrants per tile
   constexpr int U = 4;                  // entries evaluated together (independent alphas)
   __shared__ StagedRec sr[CHUNK + U];   // the chunk's splat records (one LDS address per entry)
-  __shared__ uint32_t wbits[S::NW][CHUNK / 32];
-  __shared__ uint8_t wact[S::NW];
-  __shared__ uint32_t s_last;
-  __shared__ uint32_t flw[S::NW];
   __shared__ uint32_t list[CHUNK];      // ranks of the chunk being staged
-  __shared__ uint16_t nzs[kMaxRowSegs];       // non-empty row segments, ascending
-  __shared__ uint32_t nzo[kMaxRowSegs + 1];   // their first positions in the tile's order
+  __shared__ uint32_t ovs[64], ovp[64]; // segments of a window that overlap the chunk: id, first position
   if (a.status->overflow) return;
-  const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, blockIdx.x);
+  const int lane = threadIdx.x;
+  int r = blockIdx.x, q = 0;
+  if (NQ > 1) {
+    const int grp = blockIdx.x / (8 * NQ), within = blockIdx.x % (8 * NQ);
+    q = within / 8;
+    r = grp * 8 + within % 8;
+  }
+  const int g = tile_of_rank(a.cls_cnt, a.order_fwd, a.n_tiles, r);
   if (g < 0) return;
   const int b = frame_of_tile(a.frames, a.B, g);
   const FrameDev& F = a.frames[b];
   const int lt = g - F.tile_base;
   const int tx = lt % F.ntx, ty = lt / F.ntx;
   const uint32_t start = a.tile_start[g], end = a.tile_start[g + 1];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lx0 = S::lx0(threadIdx.x), ly0 = S::ly0(threadIdx.x);
+  const int vt = q * 64 + lane;         // this lane's thread index in the tile's pixel map
+  const int lx0 = S::lx0(vt), ly0 = S::ly0(vt);
   float T_[S::PX], C0[S::PX], C1[S::PX], C2[S::PX], pxf[S::PX], pyf[S::PX];
   uint32_t last[S::PX];
   bool done[S::PX], inside[S::PX];
+  bool mine = false;
 #pragma unroll
   for (int p = 0; p < S::PX; ++p) {
     const int px = tx * T + lx0 + (p % S::PXW), py = ty * T + ly0 + (p / S::PXW);
@@ -571,61 +579,56 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
     inside[p] = px < F.W && py < F.H;
     T_[p] = 1.0f; C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0;
     done[p] = !inside[p];
+    mine |= !done[p];
   }
-  if (threadIdx.x == 0) s_last = 0;
-  // the row's non-empty segments (ids) and where their entries start in
-  // the tile's order; the last offset is the tile's entry count
-  uint32_t vbase = 0, nz = 0;
   const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  const uint16_t* segc = a.seg_cnt + (int64_t)g * a.seg_stride;
   const int SW = a.seg_words;
+  const uint32_t sh = (uint32_t)__ffs(SW) - 1u;
+  uint32_t vbase = 0, nseg = 0, nv = 0;
   if (end > start) {
     vbase = a.bkt_start[b * a.nbk];
-    const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
-    const uint32_t nseg = ((nv + 31) / 32 + SW - 1) / SW;
-    const uint32_t spt = (nseg + S::NT - 1) / S::NT;
-    const uint32_t fs0 = min(nseg, threadIdx.x * spt), fs1 = min(nseg, fs0 + spt);
-    const uint16_t* segc = a.seg_cnt + (int64_t)g * a.seg_stride;
-    uint32_t fcnt = 0, zcnt = 0;
-    for (uint32_t q = fs0; q < fs1; ++q) {
-      const uint32_t c = segc[q];
-      fcnt += c;
-      zcnt += c ? 1u : 0u;
-    }
-    uint32_t fbase = block_excl_scan<S::NT>(fcnt, flw, nullptr);
-    const uint32_t zbase = block_excl_scan<S::NT>(zcnt, flw, &nz);
-    for (uint32_t q = fs0, k = zbase; q < fs1; ++q) {
-      const uint32_t c = segc[q];
-      if (c) { nzs[k] = (uint16_t)q; nzo[k] = fbase; ++k; }
-      fbase += c;
-    }
-    if (threadIdx.x == 0) nzo[nz] = end - start;
+    nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
+    nseg = ((nv + 31) / 32 + SW - 1) / SW;
   }
-  for (uint32_t cb = start; cb < end; cb += CHUNK) {
+  // the wave's pixel-centre rectangle, for culling entries that cannot reach it
+  const float sx0 = (float)(tx * T + S::qx(vt) * S::QW) + 0.5f, sx1 = sx0 + (float)(S::QW - 1);
+  const float sy0 = (float)(ty * T + S::qy(vt) * S::QW) + 0.5f, sy1 = sy0 + (float)(S::QW - 1);
+  uint32_t wseg = 0, wpos = 0;          // cursor: a segment starting at or before the chunk, its first position
+  bool live = __ballot(mine) != 0ull;
+  for (uint32_t cb = start; live && cb < end; cb += CHUNK) {
     const int n = (int)min((uint32_t)CHUNK, end - cb);
-    __syncthreads();
-    {
-      // ranks of sorted positions [c0, c1) into list[]: the non-empty
-      // segments ka..kb that hold them are read a word per thread, and a
-      // word's first position is its segment's offset plus the bits of the
-      // words before it in the segment (a scan over the segment's lanes)
-      const uint32_t c0 = cb - start, c1 = c0 + (uint32_t)n;
-      const uint32_t ka = last_at_most(nzo, nz, c0), kb = last_at_most(nzo, nz, c1 - 1u);
-      const uint32_t nw = (kb - ka + 1u) * (uint32_t)SW;
-      const uint32_t sh = (uint32_t)__ffs(SW) - 1u;
-      for (uint32_t base = 0; base < nw; base += S::NT) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t ic = min(i, nw - 1u);
-        const uint32_t k = ka + (ic >> sh), wi = ic & (uint32_t)(SW - 1);
-        const uint32_t wq = (uint32_t)nzs[k] * (uint32_t)SW + wi;
+    const uint32_t c0 = cb - start, c1 = c0 + (uint32_t)n;
+    // ---- ranks of positions [c0, c1) into list[] ----
+    while (true) {
+      const uint32_t sg = wseg + (uint32_t)lane;
+      const uint32_t cnt = segc[min(sg, nseg - 1u)] * (sg < nseg ? 1u : 0u);
+      const uint32_t inc = wave_incl_scan(cnt);
+      const uint32_t p0 = wpos + inc - cnt;          // first position of segment sg
+      const uint32_t wtot = __shfl(inc, 63);
+      const bool ov = cnt != 0u && p0 < c1 && p0 + cnt > c0;
+      const unsigned long long om = __ballot(ov);
+      const int nov = __popcll(om);
+      if (ov) {
+        const uint32_t k = lanes_below(om);
+        ovs[k] = sg;
+        ovp[k] = p0;
+      }
+      __syncthreads();
+      for (int k0 = 0; k0 < nov; k0 += 64 >> sh) {
+        const int k = k0 + (lane >> sh);
+        const int kc = min(k, nov - 1);
+        const uint32_t wi = (uint32_t)lane & (uint32_t)(SW - 1);
+        const uint32_t wq = ovs[kc] * (uint32_t)SW + wi;
         uint32_t bits = row[wq];
-        if (i >= nw) bits = 0u;
+        if (k >= nov) bits = 0u;
         const uint32_t c = __popc(bits);
-        uint32_t inc = c;
+        uint32_t incw = c;
         for (int d = 1; d < SW; d <<= 1) {
-          const uint32_t o = __shfl_up(inc, d, SW);
-          if ((int)wi >= d) inc += o;
+          const uint32_t o = __shfl_up(incw, d, SW);
+          if ((int)wi >= d) incw += o;
         }
-        uint32_t pos = nzo[k] + inc - c;
+        uint32_t pos = ovp[kc] + incw - c;
         while (bits) {
           const uint32_t bit = __ffs(bits) - 1u;
           bits &= bits - 1u;
@@ -634,110 +637,101 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
         }
       }
       __syncthreads();
-      for (int i = threadIdx.x; i < n; i += S::NT) {
-        const uint32_t sp = a.depth_sorted[vbase + list[i]];
-        a.sorted[cb + i] = sp;
-        const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
-        sr[i].r0 = rec[0]; sr[i].r1 = rec[1]; sr[i].cb = rec[2].x;
+      const bool more = wpos + wtot < c1 && wseg + 64u < nseg;   // the chunk goes on past this window
+      if (!more) {
+        // next chunk: from the segment holding position c1 (or the next window)
+        const unsigned long long past = __ballot(sg < nseg && p0 + cnt > c1);
+        if (past) {
+          const int j = __ffsll((long long)past) - 1;
+          wpos = __shfl(p0, j);
+          wseg += (uint32_t)j;
+        } else {
+          wseg += 64u;
+          wpos += wtot;
+        }
+        break;
       }
+      wseg += 64u;
+      wpos += wtot;
     }
-    if (threadIdx.x < U) {                 // padding entries: opacity 0 (log2 -1e30), never taken
-      sr[n + threadIdx.x].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      sr[n + threadIdx.x].r1 = make_float4(0.f, -1e30f, 0.f, 0.f);
-      sr[n + threadIdx.x].cb = 0.f;
+    // ---- the chunk's records ----
+    for (int i = lane; i < n; i += 64) {
+      const uint32_t sp = a.depth_sorted[vbase + min(list[i], nv - 1u)];   // (every rank is written)
+      a.sorted[cb + i] = sp;
+      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
+      sr[i].r0 = rec[0]; sr[i].r1 = rec[1]; sr[i].cb = rec[2].x;
+    }
+    if (lane < U) {                       // padding entries: opacity 0 (log2 -1e30), never taken
+      sr[n + lane].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      sr[n + lane].r1 = make_float4(0.f, -1e30f, 0.f, 0.f);
+      sr[n + lane].cb = 0.f;
     }
     __syncthreads();
-    bool mine = false;
+    // ---- compositing: entries whose alpha >= 1/255 region may reach the
+    // wave's rectangle (a lane tests an entry), in list order, U at a time ----
+    for (int gb = 0; gb < n; gb += 64) {
+      unsigned long long cand = 0ull;
+      if (live) {
+        const int idx = gb + lane;
+        cand = __ballot(idx < n && strip_reach(sr[idx].r0, sr[idx].r1, sx0, sx1, sy0, sy1));
+      }
+      unsigned long long tookm = 0ull;
+      while (cand) {
+        int e[U];
 #pragma unroll
-    for (int p = 0; p < S::PX; ++p) mine |= !done[p];
-    const bool wave_active = __ballot(mine) != 0ull;
-    if (lane == 0) wact[w] = wave_active ? 1 : 0;
-    if (wave_active) {
-      // Entries whose alpha >= 1/255 region may reach this wave's pixel rows:
-      // one lane tests one entry against the rectangle of the wave's pixel
-      // centres; the wave then visits only those, in list order, U at a time,
-      // and stops as soon as all its pixels have stopped.
-      const float sx0 = (float)(tx * T + S::qx(threadIdx.x) * S::QW) + 0.5f, sx1 = sx0 + (float)(S::QW - 1);
-      const float sy0 = (float)(ty * T + S::qy(threadIdx.x) * S::QW) + 0.5f, sy1 = sy0 + (float)(S::QW - 1);
-      bool live = true;
-      for (int gb = 0; gb < n; gb += 64) {
-        unsigned long long cand = 0ull;
-        if (live) {
-          const int idx = gb + lane;
-          cand = __ballot(idx < n && strip_reach(sr[idx].r0, sr[idx].r1, sx0, sx1, sy0, sy1));
+        for (int u = 0; u < U; ++u) {
+          const int f = __ffsll((long long)cand) - 1;   // -1 once the candidates run out
+          cand &= cand - 1ull;
+          e[u] = f >= 0 ? gb + f : n + u;                // padding entry: opacity 0, never taken
         }
-        unsigned long long tookm = 0ull;
-        while (cand) {
-          int e[U];
+        float4 r0[U], r1[U];
+        float cb2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) { r0[u] = sr[e[u]].r0; r1[u] = sr[e[u]].r1; cb2[u] = sr[e[u]].cb; }
+        unsigned long long tm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) tm[u] = 0ull;
+#pragma unroll
+        for (int p = 0; p < S::PX; ++p) {
+          float al[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int f = __ffsll((long long)cand) - 1;   // -1 once the candidates run out
-            cand &= cand - 1ull;
-            e[u] = f >= 0 ? gb + f : n + u;                // padding entry: opacity 0, never taken
-          }
-          float4 r0[U], r1[U];
-          float cb2[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) { r0[u] = sr[e[u]].r0; r1[u] = sr[e[u]].r1; cb2[u] = sr[e[u]].cb; }
-          unsigned long long tm[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) tm[u] = 0ull;
-#pragma unroll
-          for (int p = 0; p < S::PX; ++p) {
-            float al[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              float dx, dy, pwr;
-              al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              // branch-free front-to-back step; the arithmetic of a taken entry is
-              // exactly that of the plain loop, an untaken one changes nothing
-              const bool ok = !done[p] && al[u] >= kAlphaMin;
-              const float alc = fminf(al[u], kAlphaMax);
-              const float tn = T_[p] * (1.0f - alc);
-              const bool stop = ok && tn < kTMin;
-              const bool take = ok && !stop;
-              done[p] = done[p] || stop;
-              const float wgt = take ? alc * T_[p] : 0.0f;
-              C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
-              C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
-              C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
-              T_[p] = take ? tn : T_[p];
-              last[p] = take ? (cb - start + (uint32_t)e[u] + 1u) : last[p];
-              tm[u] |= __builtin_amdgcn_ballot_w64(take);
-            }
+            float dx, dy, pwr;
+            al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr);
           }
 #pragma unroll
-          for (int u = 0; u < U; ++u)
-            if (tm[u]) tookm |= 1ull << (e[u] - gb);
-          bool mine_now = false;
-#pragma unroll
-          for (int p = 0; p < S::PX; ++p) mine_now |= !done[p];
-          if (__ballot(mine_now) == 0ull) {
-            live = false;
-            break;
+          for (int u = 0; u < U; ++u) {
+            // branch-free front-to-back step; the arithmetic of a taken entry is
+            // exactly that of the plain loop, an untaken one changes nothing
+            const bool ok = !done[p] && al[u] >= kAlphaMin;
+            const float alc = fminf(al[u], kAlphaMax);
+            const float tn = T_[p] * (1.0f - alc);
+            const bool stop = ok && tn < kTMin;
+            const bool take = ok && !stop;
+            done[p] = done[p] || stop;
+            const float wgt = take ? alc * T_[p] : 0.0f;
+            C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
+            C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
+            C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
+            T_[p] = take ? tn : T_[p];
+            last[p] = take ? (c0 + (uint32_t)e[u] + 1u) : last[p];
+            tm[u] |= __builtin_amdgcn_ballot_w64(take);
           }
         }
-        if (lane == 0) {
-          wbits[w][gb >> 5] = (uint32_t)tookm;
-          wbits[w][(gb >> 5) + 1] = (uint32_t)(tookm >> 32);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (tm[u]) tookm |= 1ull << (e[u] - gb);
+        bool mine_now = false;
+#pragma unroll
+        for (int p = 0; p < S::PX; ++p) mine_now |= !done[p];
+        if (__ballot(mine_now) == 0ull) {
+          live = false;
+          break;
         }
       }
+      if (gb + lane < n) a.cmask[((int64_t)(cb + gb + lane) << 2) + q] = (uint8_t)((tookm >> lane) & 1ull);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += S::NT) {
-      uint32_t m = 0;
-#pragma unroll
-      for (int ww = 0; ww < S::NW; ++ww)
-        if (wact[ww] && ((wbits[ww][i >> 5] >> (i & 31)) & 1u)) m |= 1u << ww;
-      a.cmask[cb + i] = (uint8_t)m;
-    }
-    mine = false;
-#pragma unroll
-    for (int p = 0; p < S::PX; ++p) mine |= !done[p];
-    if (__syncthreads_count(mine) == 0) break;
   }
   uint32_t my_last = 0;
 #pragma unroll
@@ -755,17 +749,15 @@ __global__ __launch_bounds__(TileShape<T>::NT) void composite_fwd_kernel(PassArg
       my_last = max(my_last, last[p]);
     }
   }
-  __syncthreads();
-  if (my_last) atomicMax(&s_last, my_last);
-  __syncthreads();
-  if (threadIdx.x == 0) a.tile_last[g] = s_last;
+  my_last = wave_max_u32(my_last);
+  if (lane < 4 && (lane == q || NQ == 1)) a.qlast[g * 4 + lane] = lane == q ? my_last : 0u;
 }
 
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s) {
   if (a.n_tiles == 0) return;
-  const dim3 grid(a.n_tiles);
-#define GBR_FWD(TT, CC) \
-  hipLaunchKernelGGL((composite_fwd_kernel<TT, CC>), grid, dim3(TileShape<TT>::NT), 0, s, a, images)
+  const int nq = a.tile == 8 ? 1 : 4;
+  const dim3 grid(nq == 1 ? a.n_tiles : div_up(a.n_tiles, 8) * 8 * nq);
+#define GBR_FWD(TT, CC) hipLaunchKernelGGL((composite_fwd_kernel<TT, CC>), grid, dim3(64), 0, s, a, images)
 #define GBR_FWD_T(TT)                      \
   if (chunk == 64) GBR_FWD(TT, 64);        \
   else if (chunk == 128) GBR_FWD(TT, 128); \

@@ -190,7 +190,7 @@ def image_offsets(cams: Sequence) -> list:
 class Context:
     """Owns one gbr_ctx (workspace sized from the capacities)."""
 
-    def __init__(self, tile: int = 16, chunk: int = 128, device: int = 0, max_frames: int = 64,
+    def __init__(self, tile: int = 16, chunk: int = 64, device: int = 0, max_frames: int = 64,
                  max_splats: int = 1 << 20, max_pixels: int = 1 << 22, max_entries: int = 1 << 24):
         self.cfg = gbr_config(tile, chunk, device, max_frames, max_splats, max_pixels, max_entries)
         h = _vp()
@@ -356,7 +356,7 @@ def gbr_autotune(ctx: Context, raw, gauss_offsets, cams, images, dimages, draw, 
 INSPECT = {"records": (1, np.float32, 12), "rects": (2, np.int32, 4), "tile_start": (3, np.uint32, 1),
            "sorted": (4, np.uint32, 1), "n_iter": (5, np.uint32, 1), "t_final": (6, np.float32, 1),
            "tile_last": (7, np.uint32, 1), "n_contrib": (8, np.uint32, 1), "cmask": (9, np.uint8, 1),
-           "sorted_pass": (10, np.uint32, 1)}
+           "sorted_pass": (10, np.uint32, 1), "quad_last": (11, np.uint32, 4)}
 
 
 def gbr_timing(ctx: Context, which: int, enable: bool) -> None:

@@ -170,7 +170,7 @@ class GpuExecutor:
     """Executes batches with libgbr: one stream, context and buffer set per slot."""
 
     def __init__(self, avatars_bases, avatars_mlp, n_slots: int = 3, max_batch: int = 16, width: int = 512,
-                 height: int = 512, d_in: int = 56, hidden: int = 256, tile: int = 16, chunk: int = 128,
+                 height: int = 512, d_in: int = 56, hidden: int = 256, tile: int = 16, chunk: int = 64,
                  device: int = 0):
         import torch
 

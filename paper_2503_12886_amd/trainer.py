@@ -50,7 +50,7 @@ class StepConfig:
     hidden: int = 256
     loss: int = 1            # 1 = L1 (paper), 2 = L2
     tile: int = 16
-    chunk: int = 128
+    chunk: int = 64
 
 
 def mlp_numel(d_in: int, hidden: int, K: int) -> int:

@@ -219,7 +219,8 @@ def test_contribution_masks_match_reference_contributors(tile):
     """The forward pass's per-entry contribution bits (one per wave quadrant)
     are exactly 'some pixel of the quadrant has this Gaussian among its
     contributors' in the reference, on quadrants with no ambiguous pixel;
-    no reference contributor lies past a tile's last used list position."""
+    no reference contributor lies past a quadrant's last used list position,
+    and a tile's last position is the largest of its quadrants'."""
     raw, cams, N = batch_case(B=3, N=2500, seed=7)
     ctx = make_ctx(tile=tile)
     render(ctx, raw, cams)
@@ -229,8 +230,12 @@ def test_contribution_masks_match_reference_contributors(tile):
     srt = gbr.gbr_inspect(ctx, "sorted", int(ts[-1])).astype(np.int64)
     cm = gbr.gbr_inspect(ctx, "cmask", int(ts[-1]))
     last = gbr.gbr_inspect(ctx, "tile_last", int(tile_base[-1])).astype(np.int64)
+    ql = gbr.gbr_inspect(ctx, "quad_last", int(tile_base[-1])).astype(np.int64)
     q = tile // 2 if tile > 8 else tile          # quadrant side
     nq = 4 if tile > 8 else 1
+    assert np.array_equal(last, ql.max(axis=1))   # the tile's last position is its quadrants' largest
+    if nq == 1:
+        assert not ql[:, 1:].any()
     checked = 0
     for b, cam in enumerate(cams):
         r = raw[b * N:(b + 1) * N]
@@ -256,6 +261,9 @@ def test_contribution_masks_match_reference_contributors(tile):
                     continue
                 for w in range(nq):
                     if not ambiguous[w]:
+                        # past its own last position a quadrant has no contributor and no bit
+                        if i - ts[g] >= ql[g, w]:
+                            assert not want[w] and not (cm[i] >> w) & 1, (b, lt, i, w)
                         assert bool((cm[i] >> w) & 1) == want[w], (b, lt, i, w)
                         checked += 1
     assert checked > 1000
