@@ -24,13 +24,19 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- exclusive scan (u32)
-// Three phases: per-block totals, a one-block scan of the totals (which also
-// publishes the grand total and checks it against a capacity), per-block
-// rescan with the block offset.  Integer sums, so the order does not matter
-// for the result.
+// out[k] = sum of in[0..k), out[n] = the grand total.  Two passes:
+// per-block totals, then every block adds the totals of the blocks before it
+// (read directly, summed in 64 bits) to its own rescan.  The grand total is
+// published (and checked against a capacity) by the workgroup that writes
+// out[n].  Integer sums, so the order does not matter for the result.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kScanThreads * kScanItems;
+__device__ __forceinline__ void publish_total(unsigned long long total, StatusDev* status, int64_t cap_check,
+                                              unsigned long long* total_out) {
+  if (total_out) *total_out = total;
+  if (cap_check >= 0 && total > (unsigned long long)cap_check) status->overflow |= 1u;
+}
 
 __global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                     uint32_t* __restrict__ block_sums) {
@@ -51,52 +57,40 @@ __global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(const uint32_
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void scan_blocksums_kernel(uint32_t* __restrict__ block_sums, int nb,
-                                                              StatusDev* status, int64_t cap_check,
-                                                              unsigned long long* total_out) {
-  __shared__ uint32_t lw[16];
-  __shared__ unsigned long long carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += 1024) {
-    const int k = base + threadIdx.x;
-    const uint32_t v = (k < nb) ? block_sums[k] : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<1024>(v, lw, &tot);
-    const unsigned long long c = carry;
-    if (k < nb) block_sums[k] = (uint32_t)(c + ex);
-    __syncthreads();
-    if (threadIdx.x == 0) carry = c + tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (total_out) *total_out = carry;
-    if (cap_check >= 0 && carry > (unsigned long long)cap_check) status->overflow |= 1u;
-  }
-}
-
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                    const uint32_t* __restrict__ block_sums,
-                                                                   uint32_t* __restrict__ out) {
+                                                                   uint32_t* __restrict__ out, StatusDev* status,
+                                                                   int64_t cap_check,
+                                                                   unsigned long long* total_out) {
   __shared__ uint32_t tile[kScanBlock];
   __shared__ uint32_t lw[kScanThreads / 64];
+  __shared__ unsigned long long wsum[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock;
   uint32_t v[kScanItems];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) v[i] = (n > 0) ? in[min(base + i * kScanThreads + threadIdx.x, n - 1)] : 0u;
+  // this block's offset: the totals of the blocks before it
+  unsigned long long part = 0;
+  for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanThreads) part += block_sums[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int idx = i * kScanThreads + threadIdx.x;
     tile[idx] = (base + idx < n) ? v[i] : 0u;
   }
   __syncthreads();
+  unsigned long long off = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) off += wsum[w];
   uint32_t local[kScanItems];
   uint32_t s = 0;
   for (int i = 0; i < kScanItems; ++i) {
     local[i] = tile[threadIdx.x * kScanItems + i];
     s += local[i];
   }
-  uint32_t ex = block_excl_scan<kScanThreads>(s, lw, nullptr) + block_sums[blockIdx.x];
+  uint32_t ex = block_excl_scan<kScanThreads>(s, lw, nullptr);
   for (int i = 0; i < kScanItems; ++i) {
     tile[threadIdx.x * kScanItems + i] = ex;
     ex += local[i];
@@ -105,11 +99,13 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
   for (int i = 0; i < kScanItems; ++i) {
     const int idx = i * kScanThreads + threadIdx.x;
     const int64_t k = base + idx;
-    if (k < n) out[k] = tile[idx];
+    if (k < n) out[k] = (uint32_t)(off + tile[idx]);
   }
-  // out[n] = grand total, written by the block that holds the last element
+  // out[n] = grand total, written by the block that holds position n
   if (threadIdx.x == kScanThreads - 1 && base <= n && n < base + kScanBlock) {
-    out[n] = ex;  // ex of the last thread is the running total after its items
+    const unsigned long long total = off + ex;   // ex of the last thread: the block's running total
+    out[n] = (uint32_t)total;
+    publish_total(total, status, cap_check, total_out);
   }
 }
 
@@ -119,8 +115,8 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blo
                      int64_t cap_check, unsigned long long* total_out, hipStream_t s) {
   const int nb = div_up(n + 1, kScanBlock);
   hipLaunchKernelGGL(scan_totals_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums);
-  hipLaunchKernelGGL(scan_blocksums_kernel, dim3(1), dim3(1024), 0, s, block_sums, nb, status, cap_check, total_out);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums, out);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums, out, status,
+                     cap_check, total_out);
 }
 
 // ---------------------------------------------------------------- preprocess

@@ -6,85 +6,128 @@
 namespace gbr {
 
 // ---------------------------------------------------------------- MLP forward
-// One launch per layer.  A block owns 16 output units for every frame: the 16
-// weight rows are staged in LDS once, each thread forms one (frame, unit) dot
-// product in input order.  The ReLU of the previous layer is applied when its
-// stored pre-activation is read.
-constexpr int kRowsPerBlock = 8;
+// One workgroup per frame runs the three layers back to back: the layer's
+// input vector sits in LDS, each wave forms output units eight at a time
+// (lanes over the input, weight rows read coalesced, then a fixed-order sum
+// across the wave).  Pre-activations are kept (z1, z2 for the backward; the
+// ReLU of a layer is applied when the next layer reads them).
+constexpr int kMlpThreads = 1024;
+constexpr int kMlpWaves = kMlpThreads / 64;
 constexpr int kMlpMaxIn = 1024;
 
-__global__ __launch_bounds__(1024) void dense_fwd_kernel(const float* __restrict__ W, const float* __restrict__ bias,
-                                                         const float* __restrict__ in, int relu_in, int B, int n_in,
-                                                         int n_out, float* __restrict__ out) {
-  __shared__ float w[kRowsPerBlock * (kMlpMaxIn + 1)];
-  const int ld = n_in | 1;   // odd row stride: the rows a wave reads at once sit in different LDS banks
-  const int j0 = blockIdx.x * kRowsPerBlock;
-  const int rows = min(kRowsPerBlock, n_out - j0);
-  for (int t = threadIdx.x; t < rows * n_in; t += blockDim.x) w[(t / n_in) * ld + t % n_in] = W[(int64_t)j0 * n_in + t];
-  __syncthreads();
-  for (int q = threadIdx.x; q < B * rows; q += blockDim.x) {
-    const int b = q / rows, jj = q % rows;
-    const float* x = in + (int64_t)b * n_in;
-    const float* wr = w + jj * ld;
-    float s = 0.0f;
-    if (relu_in) {
-#pragma unroll 8
-      for (int i = 0; i < n_in; ++i) s = __builtin_fmaf(wr[i], fmaxf(x[i], 0.0f), s);
-    } else {
-#pragma unroll 8
-      for (int i = 0; i < n_in; ++i) s = __builtin_fmaf(wr[i], x[i], s);
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// out[j] = bias[j] + sum_c W[j][c] act(in[c]) for j < n_out; act = ReLU when relu_in.
+// A wave forms kMlpRows units at a time, all their loads in flight together.
+constexpr int kMlpRows = 8;
+__device__ __forceinline__ void mlp_layer(const float* __restrict__ W, const float* __restrict__ bias,
+                                          const float* in, int n_in, int n_out, bool relu_in,
+                                          float* __restrict__ out_g, float* out_l) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int j0 = w * kMlpRows; j0 < n_out; j0 += kMlpWaves * kMlpRows) {
+    float s[kMlpRows];
+#pragma unroll
+    for (int r = 0; r < kMlpRows; ++r) s[r] = 0.0f;
+#pragma unroll 4
+    for (int c = lane; c < n_in; c += 64) {
+      const float xv = relu_in ? fmaxf(in[c], 0.0f) : in[c];
+#pragma unroll
+      for (int r = 0; r < kMlpRows; ++r) {
+        const int j = min(j0 + r, n_out - 1);
+        s[r] = __builtin_fmaf(W[(int64_t)j * n_in + c], xv, s[r]);
+      }
     }
-    out[(int64_t)b * n_out + j0 + jj] = s + bias[j0 + jj];
+#pragma unroll
+    for (int r = 0; r < kMlpRows; ++r) {
+      s[r] = wave_sum_f32(s[r]);
+      if (lane == r && j0 + r < n_out) {
+        const float v = s[r] + bias[j0 + r];
+        out_g[j0 + r] = v;
+        if (out_l) out_l[j0 + r] = v;
+      }
+    }
   }
 }
 
-void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, int hidden, int K, float* psi,
-                    float* z1, float* z2, hipStream_t s) {
-  if (B == 0) return;
+__global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(const float* __restrict__ params,
+                                                              const float* __restrict__ theta, int d_in, int hidden,
+                                                              int K, float* __restrict__ psi, float* __restrict__ z1,
+                                                              float* __restrict__ z2) {
+  __shared__ float xa[kMlpMaxIn], xb[kMlpMaxIn];
+  const int b = blockIdx.x;
   const float* W1 = params;
   const float* b1 = W1 + (int64_t)hidden * d_in;
   const float* W2 = b1 + hidden;
   const float* b2 = W2 + (int64_t)hidden * hidden;
   const float* W3 = b2 + hidden;
   const float* b3 = W3 + (int64_t)K * hidden;
-  const int thr = std::min(1024, std::max(64, ((B * kRowsPerBlock + 63) / 64) * 64));   // one thread per (frame, row)
-  hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(hidden, kRowsPerBlock)), dim3(thr), 0, s, W1, b1, theta, 0, B,
-                     d_in, hidden, z1);
-  hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(hidden, kRowsPerBlock)), dim3(thr), 0, s, W2, b2, z1, 1, B,
-                     hidden, hidden, z2);
-  hipLaunchKernelGGL(dense_fwd_kernel, dim3(div_up(K, kRowsPerBlock)), dim3(thr), 0, s, W3, b3, z2, 1, B, hidden, K,
-                     psi);
+  for (int t = threadIdx.x; t < d_in; t += kMlpThreads) xa[t] = theta[(int64_t)b * d_in + t];
+  __syncthreads();
+  mlp_layer(W1, b1, xa, d_in, hidden, false, z1 + (int64_t)b * hidden, xb);
+  __syncthreads();
+  mlp_layer(W2, b2, xb, hidden, hidden, true, z2 + (int64_t)b * hidden, xa);
+  __syncthreads();
+  mlp_layer(W3, b3, xa, hidden, K, true, psi + (int64_t)b * K, nullptr);
+}
+
+void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, int hidden, int K, float* psi,
+                    float* z1, float* z2, hipStream_t s) {
+  if (B == 0) return;
+  hipLaunchKernelGGL(mlp_fwd_kernel, dim3(B), dim3(kMlpThreads), 0, s, params, theta, d_in, hidden, K, psi, z1, z2);
 }
 
 // ---------------------------------------------------------------- MLP backward
-// dz2 = (W3^T dpsi) * [z2 > 0], dz1 = (W2^T dz2) * [z1 > 0].  A block owns 64
-// units of one frame (a lane per unit, weight rows read coalesced); its 8
-// waves each sum an eighth of the contraction, and the eighths are added in
-// wave order.  Then one thread per parameter sums over the frames in frame
-// order.
-constexpr int kActSplit = 8;
+// dz2 = (W3^T dpsi) * [z2 > 0], then dz1 = (W2^T dz2) * [z1 > 0], in one
+// workgroup per frame: a unit's sum is split over four threads (weight rows
+// read coalesced across units), whose quarters are added in order.  Then one
+// thread per parameter sums over the frames in frame order.
+constexpr int kActSplit = 4;
 
-__global__ __launch_bounds__(64 * kActSplit) void dense_bwd_act_kernel(const float* __restrict__ W,
-                                                                       const float* __restrict__ g,
-                                                                       const float* __restrict__ z, int B, int n_g,
-                                                                       int n_x, float* __restrict__ dz) {
-  __shared__ float part[kActSplit][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
-  const int b = blockIdx.y;
+// dz[i] = [z[i] > 0] * sum_k W[k][i] g[k] for i < n_x (g, dz in LDS; dz also to global)
+__device__ __forceinline__ void mlp_act_back(const float* __restrict__ W, const float* g, int n_g, int n_x,
+                                             const float* __restrict__ z, float* part, float* dz_l,
+                                             float* __restrict__ dz_g) {
   const int per = (n_g + kActSplit - 1) / kActSplit;
-  const int k0 = w * per, k1 = min(n_g, k0 + per);
-  float s = 0.0f;
-  if (i < n_x)
-    for (int k = k0; k < k1; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[(int64_t)b * n_g + k], s);
-  part[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && i < n_x) {
-    float t = 0.0f;
-#pragma unroll
-    for (int q = 0; q < kActSplit; ++q) t += part[q][lane];
-    dz[(int64_t)b * n_x + i] = z[(int64_t)b * n_x + i] > 0.0f ? t : 0.0f;
+  for (int base = 0; base < n_x * kActSplit; base += kMlpThreads) {
+    const int t = base + (int)threadIdx.x;
+    const int i = t % n_x, qk = t / n_x;
+    if (qk < kActSplit) {
+      const int k0 = qk * per, k1 = min(n_g, k0 + per);
+      float s = 0.0f;
+#pragma unroll 8
+      for (int k = k0; k < k1; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[k], s);
+      part[qk * kMlpMaxIn + i] = s;
+    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_x; i += kMlpThreads) {
+    float v = 0.0f;
+#pragma unroll
+    for (int qk = 0; qk < kActSplit; ++qk) v += part[qk * kMlpMaxIn + i];
+    v = z[i] > 0.0f ? v : 0.0f;
+    dz_l[i] = v;
+    dz_g[i] = v;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kMlpThreads) void mlp_bwd_act_kernel(const float* __restrict__ W2,
+                                                                  const float* __restrict__ W3,
+                                                                  const float* __restrict__ dpsi,
+                                                                  const float* __restrict__ z1,
+                                                                  const float* __restrict__ z2, int hidden, int K,
+                                                                  float* __restrict__ dz1, float* __restrict__ dz2) {
+  __shared__ float part[kActSplit * kMlpMaxIn];
+  __shared__ float gk[kMlpMaxIn], gh[kMlpMaxIn];
+  const int b = blockIdx.x;
+  for (int k = threadIdx.x; k < K; k += kMlpThreads) gk[k] = dpsi[(int64_t)b * K + k];
+  __syncthreads();
+  mlp_act_back(W3, gk, K, hidden, z2 + (int64_t)b * hidden, part, gh, dz2 + (int64_t)b * hidden);
+  mlp_act_back(W2, gh, hidden, hidden, z1 + (int64_t)b * hidden, part, gk, dz1 + (int64_t)b * hidden);
 }
 
 __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restrict__ theta,
@@ -127,9 +170,8 @@ void launch_mlp_bwd(const float* params, const float* theta, const float* z1, co
   if (B == 0) return;
   const float* W2 = params + (int64_t)hidden * d_in + hidden;
   const float* W3 = W2 + (int64_t)hidden * hidden + hidden;
-  const dim3 ga(div_up(hidden, 64), B);
-  hipLaunchKernelGGL(dense_bwd_act_kernel, ga, dim3(64 * kActSplit), 0, s, W3, dpsi, z2, B, K, hidden, dz2);
-  hipLaunchKernelGGL(dense_bwd_act_kernel, ga, dim3(64 * kActSplit), 0, s, W2, dz2, z1, B, hidden, hidden, dz1);
+  hipLaunchKernelGGL(mlp_bwd_act_kernel, dim3(B), dim3(kMlpThreads), 0, s, W2, W3, dpsi, z1, z2, hidden, K, dz1,
+                     dz2);
   const int64_t total = (int64_t)hidden * d_in + hidden + (int64_t)hidden * hidden + hidden + (int64_t)K * hidden + K;
   hipLaunchKernelGGL(mlp_bwd_param_kernel, dim3(div_up(total, 256)), dim3(256), 0, s, theta, z1, z2, dz1, dz2, dpsi,
                      B, d_in, hidden, K, dparams);
