@@ -7,7 +7,7 @@ namespace gbr {
 
 // ---------------------------------------------------------------- MLP forward
 // One workgroup per frame runs the three layers back to back: the layer's
-// input vector sits in LDS, each wave forms output units eight at a time
+// input vector sits in LDS, each wave forms output units four at a time
 // (lanes over the input, weight rows read coalesced, then a fixed-order sum
 // across the wave).  Pre-activations are kept (z1, z2 for the backward; the
 // ReLU of a layer is applied when the next layer reads them).
@@ -22,33 +22,26 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
 }
 
 // out[j] = bias[j] + sum_c W[j][c] act(in[c]) for j < n_out; act = ReLU when relu_in.
-// A wave forms kMlpRows units at a time, all their loads in flight together.
-constexpr int kMlpRows = 8;
 __device__ __forceinline__ void mlp_layer(const float* __restrict__ W, const float* __restrict__ bias,
                                           const float* in, int n_in, int n_out, bool relu_in,
                                           float* __restrict__ out_g, float* out_l) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int j0 = w * kMlpRows; j0 < n_out; j0 += kMlpWaves * kMlpRows) {
-    float s[kMlpRows];
-#pragma unroll
-    for (int r = 0; r < kMlpRows; ++r) s[r] = 0.0f;
-#pragma unroll 4
+  for (int j0 = w * 4; j0 < n_out; j0 += kMlpWaves * 4) {
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int c = lane; c < n_in; c += 64) {
       const float xv = relu_in ? fmaxf(in[c], 0.0f) : in[c];
 #pragma unroll
-      for (int r = 0; r < kMlpRows; ++r) {
+      for (int r = 0; r < 4; ++r) {
         const int j = min(j0 + r, n_out - 1);
         s[r] = __builtin_fmaf(W[(int64_t)j * n_in + c], xv, s[r]);
       }
     }
 #pragma unroll
-    for (int r = 0; r < kMlpRows; ++r) {
-      s[r] = wave_sum_f32(s[r]);
-      if (lane == r && j0 + r < n_out) {
-        const float v = s[r] + bias[j0 + r];
-        out_g[j0 + r] = v;
-        if (out_l) out_l[j0 + r] = v;
-      }
+    for (int r = 0; r < 4; ++r) s[r] = wave_sum_f32(s[r]);
+    if (lane < 4 && j0 + lane < n_out) {
+      const float v = (lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3]) + bias[j0 + lane];
+      out_g[j0 + lane] = v;
+      if (out_l) out_l[j0 + lane] = v;
     }
   }
 }
