@@ -9,10 +9,12 @@ starts from a perturbed copy of it, as in fitting a captured head.
 
 Reports the batched, graph-captured step (one host synchronisation per
 step) in images/s, next to the per-frame scheme (one frame per optimisation
-step, host synchronisation between preprocess and rasterize) on the same
-GPU, the dominant kernel's roofline position measured with HIP events over
-the timed region, a per-kernel time breakdown, and the float64 CPU
-reference timed on a bounded sample.
+step, host synchronisation between preprocess and rasterize) and the naive
+batch-parallel scheme (one update per batch, frames rasterised one by one
+with a synchronisation each) on the same GPU, the dominant kernel's roofline
+position measured with HIP events over the timed region, a per-kernel time
+breakdown, and the float64 CPU reference timed on a bounded sample.  With
+--k-sweep, also the graph-captured step time at other blendshape counts.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -55,6 +57,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--per-frame-frames", type=int, default=48)
+    ap.add_argument("--naive-steps", type=int, default=4, help="timed steps of the naive batch-parallel scheme")
+    ap.add_argument("--k-sweep", type=str, default="",
+                    help="comma-separated blendshape counts: graph-captured ms per step at each K")
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
@@ -76,10 +81,10 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-def make_workload(seed=0):
+def make_workload(seed=0, K=20):
     from paper_2503_12886_amd import synth
     from paper_2503_12886_amd.trainer import StepConfig, mlp_pack
-    cfg = StepConfig(N=50_000, K=20, B=16, width=512, height=512)
+    cfg = StepConfig(N=50_000, K=K, B=16, width=512, height=512)
     bases = synth.make_scene(cfg.N, cfg.K, seed=seed)
     mlp = mlp_pack(synth.make_mlp(K=cfg.K, seed=5))
     theta = synth.make_tracking(cfg.B, seed=2)
@@ -91,8 +96,8 @@ def make_workload(seed=0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 "
+                                   "(no multi-GPU path is implemented)"}))
         sys.exit(2)
     import torch
     from paper_2503_12886_amd import gbr, synth
@@ -199,6 +204,16 @@ def main():
         pf = nf / (time.perf_counter() - t0)
         out["per_frame"] = {"value": round(pf, 2), "unit": "img/s", "frames": nf,
                             "ms_per_frame": round(1e3 / pf, 4), "batched_over_per_frame": round(value / pf, 3)}
+        # naive batch-parallel scheme (frames rasterised one by one, a host sync each; one update per batch)
+        tr.naive_batch_steps(1)                   # warm-up
+        torch.cuda.synchronize()
+        ns = args.naive_steps
+        t0 = time.perf_counter()
+        tr.naive_batch_steps(ns)
+        torch.cuda.synchronize()
+        nb = cfg.B * ns / (time.perf_counter() - t0)
+        out["naive_batch"] = {"value": round(nb, 2), "unit": "img/s", "steps": ns, "frames": cfg.B * ns,
+                              "batched_over_naive": round(value / nb, 3)}
 
     tr.close()
 
@@ -210,6 +225,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.k_sweep:
+        out["k_sweep"] = k_sweep_leg([int(k) for k in args.k_sweep.split(",") if k], args)
 
     if not args.quick and not args.no_serve:
         out["serve"] = serve_leg(args.serve_seconds)
@@ -246,6 +264,36 @@ def serve_leg(seconds: float) -> dict:
                   "window_ms": 2.0, "budget_bytes": 2 << 30, "slots": 3,
                   "latency": "arrival to render complete on the GPU"})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
+
+
+def k_sweep_leg(ks, args) -> dict:
+    """Graph-captured ms per batched step at each blendshape count K (the
+    paper reports training time linear in K); same N, B, resolution."""
+    import torch
+    from paper_2503_12886_amd import synth
+    from paper_2503_12886_amd.trainer import Trainer
+    res = {}
+    for k in ks:
+        cfg, bases, mlp, theta, cams, targets = make_workload(K=k)
+        cfg.tile, cfg.chunk = args.tile, args.chunk
+        tr = Trainer(cfg, bases, mlp)
+        tr.set_batch(theta, targets, cams)
+        tr.render_targets()
+        tr.load_bases(synth.perturb_scene(bases))
+        for _ in range(3):
+            tr.step()
+        tr.capture()
+        for _ in range(5):
+            tr.step()
+        torch.cuda.synchronize()
+        n = 30
+        t0 = time.perf_counter()
+        for _ in range(n):
+            tr.step()
+        torch.cuda.synchronize()
+        res[str(k)] = round((time.perf_counter() - t0) * 1e3 / n, 4)
+        tr.close()
+    return {"unit": "ms per step", "steps": 30, "ms": res}
 
 
 def cpu_baseline(budget_s: float) -> dict:

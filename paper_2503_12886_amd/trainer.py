@@ -9,6 +9,10 @@ optimisation step of the reduced-Gaussian-blendshape avatar, in two schemes.
 * per-frame (Fig. 4a, "w/o batch parallel"): one frame per optimisation
   step, preprocess -> host synchronisation to size the tile lists ->
   rasterize, and an Adam step per frame.
+* naive batch-parallel (Fig. 4b, Table 4 middle row): one optimisation step
+  per batch (batched MLP, blend, blend adjoint, MLP adjoint, Adam), but the
+  frames are rasterised one after another, each with its own host
+  synchronisation between preprocess and rasterize.
 
 This module only sequences calls into libgbr and owns the device buffers;
 every step of the computation runs in the library's kernels.
@@ -33,9 +37,19 @@ ADAM_BETAS = (0.9, 0.999)
 ADAM_EPS = 1e-15
 
 
-def bases_lr_table() -> list:
+# Features the paper leaves out of the blend (Sec. A.3): scale and opacity.
+UNBLENDED = (7, 8, 9, 10)
+
+
+def bases_lr_table(paper_mask: bool = False) -> list:
+    """32-entry Adam rate table: 16 per-feature rates of G_0, then 16 of the
+    deltas.  With paper_mask the deltas of scale and opacity get rate 0 (they
+    stay at zero: those attributes are not blended)."""
     base = [(_BASE[g] if g else 0.0) for g in _GROUPS]
     delta = [(_BASE[g] * _DELTA[g] if g else 0.0) for g in _GROUPS]
+    if paper_mask:
+        for f in UNBLENDED:
+            delta[f] = 0.0
     return base + delta
 
 
@@ -51,6 +65,7 @@ class StepConfig:
     loss: int = 1            # 1 = L1 (paper), 2 = L2
     tile: int = 16
     chunk: int = 64
+    paper_mask: bool = False  # scale and opacity not blended (their deltas held at zero)
 
 
 def mlp_numel(d_in: int, hidden: int, K: int) -> int:
@@ -68,6 +83,7 @@ class Trainer:
         f32 = dict(device=dev, dtype=torch.float32)
         self.bases = torch.from_numpy(np.ascontiguousarray(bases, dtype=np.float32)).to(dev)
         assert tuple(self.bases.shape) == (K + 1, N, 16)
+        self._mask_deltas()
         self.bases_m = torch.zeros_like(self.bases)
         self.bases_v = torch.zeros_like(self.bases)
         self.dbases = torch.zeros_like(self.bases)
@@ -89,7 +105,7 @@ class Trainer:
             max_entries = max(1 << 20, 40 * B * N)
         self.ctx = gbr.Context(tile=cfg.tile, chunk=cfg.chunk, device=device, max_frames=max(B, 1),
                                max_splats=B * N, max_pixels=B * npix, max_entries=max_entries)
-        self.lr_bases = bases_lr_table()
+        self.lr_bases = bases_lr_table(cfg.paper_mask)
         self.lr_mlp = [MLP_LR] * 32
         self.cams = None
         self.graph = None
@@ -122,10 +138,15 @@ class Trainer:
             gbr.gbr_reserve(c, st.entries + st.entries // 4 + 4096)
             self.render_targets()
 
+    def _mask_deltas(self) -> None:
+        if self.cfg.paper_mask:
+            self.bases[1:, :, list(UNBLENDED)] = 0.0
+
     def load_bases(self, bases: np.ndarray) -> None:
         """Replace the blendshape bases (Adam state restarts)."""
         self.torch.cuda.synchronize()
         self.bases.copy_(self.torch.from_numpy(np.ascontiguousarray(bases, dtype=np.float32)))
+        self._mask_deltas()
         self.bases_m.zero_()
         self.bases_v.zero_()
         self.torch.cuda.synchronize()
@@ -136,7 +157,12 @@ class Trainer:
         with self.torch.cuda.stream(self.stream):
             self._enqueue_step()
 
-    def _enqueue_step(self) -> None:
+    def batch_grads(self) -> None:
+        """The batched step's gradients (dbases, dpsi, dmlp) without the update."""
+        with self.torch.cuda.stream(self.stream):
+            self._enqueue_grads()
+
+    def _enqueue_grads(self) -> None:
         c, cfg = self.ctx, self.cfg
         gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
         gbr.gbr_blend(c, self.bases, self.psi, self.raw)
@@ -144,6 +170,10 @@ class Trainer:
         gbr.gbr_loss(c, self.images, self.targets, cfg.loss, self.dimages)
         gbr.gbr_backward(c, self.dimages, self.bases, self.psi, self.dbases, self.dpsi)
         gbr.gbr_mlp_backward(c, self.mlp, self.dpsi, self.dmlp)
+
+    def _enqueue_step(self) -> None:
+        c, cfg = self.ctx, self.cfg
+        self._enqueue_grads()
         gbr.gbr_adam_step(c, 0, self.bases, self.dbases, self.bases_m, self.bases_v, cfg.N * 16, self.lr_bases,
                           ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
         gbr.gbr_adam_step(c, 1, self.mlp, self.dmlp, self.mlp_m, self.mlp_v, self.mlp.numel(), self.lr_mlp,
@@ -211,6 +241,48 @@ class Trainer:
             st = gbr.gbr_query_status(c)
             if st.overflow:
                 raise RuntimeError("unexpected overflow in the per-frame scheme")
+
+    # ---------------------------------------------------------------- naive batch-parallel scheme
+    def naive_batch_grads(self) -> None:
+        """Gradients of one batch, rasterising frame by frame with a host
+        synchronisation per frame (Fig. 4b).  Each frame's loss is normalised
+        over that frame alone: the gradients are B times the batched step's
+        (a constant factor that Adam's update does not see)."""
+        with self.torch.cuda.stream(self.stream):
+            self._naive_batch_grads()
+
+    def _naive_batch_grads(self) -> None:
+        c, cfg = self.ctx, self.cfg
+        npix = cfg.width * cfg.height
+        if getattr(self, "draw", None) is None:
+            self.draw = self.torch.zeros_like(self.raw)
+        gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
+        gbr.gbr_blend(c, self.bases, self.psi, self.raw)
+        for b in range(cfg.B):
+            img = self.images[b * 3 * npix:(b + 1) * 3 * npix]
+            dimg = self.dimages[b * 3 * npix:(b + 1) * 3 * npix]
+            tgt = self.targets[b * 3 * npix:(b + 1) * 3 * npix]
+            gbr.gbr_preprocess(c, self.raw[b:b + 1], [0, cfg.N], [self.cams[b]])
+            gbr.gbr_entry_count(c)                      # the synchronisation of each frame (Fig. 4b)
+            gbr.gbr_rasterize(c, img)
+            gbr.gbr_loss(c, img, tgt, cfg.loss, dimg)
+            gbr.gbr_render_backward(c, dimg, self.draw[b:b + 1])
+        gbr.gbr_blend_backward(c, self.draw, self.bases, self.psi, self.dbases, self.dpsi)
+        gbr.gbr_mlp_backward(c, self.mlp, self.dpsi, self.dmlp)
+
+    def naive_batch_steps(self, n: int) -> None:
+        """n optimisation steps of the naive batch-parallel scheme."""
+        c, cfg = self.ctx, self.cfg
+        with self.torch.cuda.stream(self.stream):
+            for _ in range(n):
+                self._naive_batch_grads()
+                gbr.gbr_adam_step(c, 0, self.bases, self.dbases, self.bases_m, self.bases_v, cfg.N * 16,
+                                  self.lr_bases, ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+                gbr.gbr_adam_step(c, 1, self.mlp, self.dmlp, self.mlp_m, self.mlp_v, self.mlp.numel(),
+                                  self.lr_mlp, ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+                st = gbr.gbr_query_status(c)
+                if st.overflow:
+                    raise RuntimeError("unexpected overflow in the naive batch-parallel scheme")
 
     def close(self) -> None:
         if self.graph is not None:

@@ -1,7 +1,9 @@
 """The training step: graph replay equals eager execution bit for bit (over
 several replays with eager work and synchronisations in between), re-staged
-cameras reach the replay, overflow is recovered, and the per-frame scheme
-runs the same kernels one frame per step."""
+cameras reach the replay, overflow is recovered, the per-frame scheme runs
+the same kernels one frame per step, and the naive batch-parallel scheme
+(frames rasterised one by one, a synchronisation each) gives the batched
+step's gradients."""
 import numpy as np
 import pytest
 
@@ -88,4 +90,46 @@ def test_per_frame_scheme_runs_one_step_per_frame():
     st = gbr.gbr_query_status(a.ctx)
     assert st.adam_steps[0] == 3 and st.adam_steps[1] == 3
     assert np.isfinite(a.bases.cpu().numpy()).all()
+    a.close()
+
+
+def test_naive_batch_scheme_gives_the_batched_gradients():
+    """Rasterising the frames one after another (Fig. 4b) changes when the
+    work runs, not what it computes: with each frame's loss normalised over
+    that frame alone, every gradient is exactly B (= 4, a power of two) times
+    the batched step's."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=4, B=4)
+    a = Trainer(cfg, bases, mlp)
+    a.set_batch(theta, targets, cams)
+    a.batch_grads()
+    gbr.gbr_query_status(a.ctx, a.stream)
+    ref = [t.detach().cpu().numpy().copy() for t in (a.dbases, a.dpsi, a.dmlp)]
+    a.naive_batch_grads()
+    gbr.gbr_query_status(a.ctx, a.stream)
+    got = [t.detach().cpu().numpy().copy() for t in (a.dbases, a.dpsi, a.dmlp)]
+    for r, g in zip(ref, got):
+        assert np.abs(r).max() > 0
+        assert np.array_equal(g, np.float32(cfg.B) * r)
+    a.naive_batch_steps(2)
+    assert gbr.gbr_query_status(a.ctx).adam_steps[0] == 2
+    a.close()
+
+
+def test_paper_feature_mask_keeps_scale_and_opacity_unblended():
+    """With the paper's feature mask (Sec. A.3: scale and opacity are not
+    blended) their delta slices stay exactly zero through training while the
+    base model and the other deltas move."""
+    from paper_2503_12886_amd.trainer import UNBLENDED
+    cfg, bases, mlp, theta, cams, targets = small(seed=5)
+    cfg.paper_mask = True
+    a = Trainer(cfg, bases, mlp)
+    a.set_batch(theta, targets, cams)
+    b0 = a.bases.cpu().numpy().copy()
+    assert not b0[1:][:, :, list(UNBLENDED)].any()
+    for _ in range(3):
+        a.step()
+    b1 = a.bases.cpu().numpy()
+    assert not b1[1:][:, :, list(UNBLENDED)].any()
+    assert not np.array_equal(b1[0], b0[0])
+    assert not np.array_equal(b1[1:][:, :, :3], b0[1:][:, :, :3])
     a.close()
