@@ -125,6 +125,21 @@ class Trainer:
         if self.graph is not None:
             gbr.gbr_stage_frames(self.ctx, self.offsets, self.cams)
 
+    def set_batch_device(self, theta, targets, cams: list) -> None:
+        """The same from device tensors (theta [B][d_in], targets [B][3 H W]),
+        ordered on the trainer's stream."""
+        assert len(cams) == self.cfg.B
+        cur = self.torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        with self.torch.cuda.stream(self.stream):
+            self.theta.copy_(theta)
+            self.targets.copy_(targets.reshape(-1))
+        theta.record_stream(self.stream)      # the sources stay allocated until the copies ran
+        targets.record_stream(self.stream)
+        self.cams = list(cams)
+        if self.graph is not None:
+            gbr.gbr_stage_frames(self.ctx, self.offsets, self.cams)
+
     def render_targets(self) -> None:
         """Targets = this model's own renders of the current batch (used to make
         a ground-truth avatar's frames the training targets)."""

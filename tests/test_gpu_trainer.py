@@ -133,3 +133,31 @@ def test_paper_feature_mask_keeps_scale_and_opacity_unblended():
     assert not np.array_equal(b1[0], b0[0])
     assert not np.array_equal(b1[1:][:, :, :3], b0[1:][:, :, :3])
     a.close()
+
+
+def test_online_trainer_streams_frames_through_the_pools():
+    """On-the-fly training (Alg. 2): frames stream into a device store through
+    the two pools; every step trains on frames the pools hold (the gathered
+    tracking vectors are those frames'), slots are reused only once a frame
+    left both pools, and the captured step replays with each batch's cameras."""
+    from paper_2503_12886_amd.online import OnlineTrainer
+    cfg, bases, mlp, theta, cams, targets = small(seed=6, B=4)
+    n = 30
+    th = synth.make_tracking(n, seed=7)
+    cm = synth.make_cameras(n, cfg.width, cfg.height, seed=8)
+    tg = np.stack(synth.make_targets(cm, seed=9))
+    tr = Trainer(cfg, bases, mlp)
+    on = OnlineTrainer(tr, local_cap=6, global_cap=10, eta=0.75, seed=1)
+    for i in range(n):
+        on.add_frame(th[i], tg[i], cm[i])
+        st, slots = on.step()
+        assert not st.overflow and np.isfinite(st.loss)
+        held = list(on.pools.local) + on.pools.glob
+        assert set(slots) <= set(held)
+        assert len(set(held)) == len(held) and not set(held) & set(on.free)
+        got = tr.theta.cpu().numpy()
+        want = np.stack([th[on.frame_id[s]] for s in slots]).astype(np.float32)
+        assert np.array_equal(got, want)
+    assert on.captured and tr.graph is not None
+    assert list(on.pools.local) and len(on.pools.glob) == 10
+    tr.close()
