@@ -156,6 +156,22 @@ int gbr_blend_backward(gbr_ctx* ctx, const float* draw, const float* bases, cons
 int gbr_backward(gbr_ctx* ctx, const float* dimages, const float* bases, const float* weights, int32_t K,
                  float* dbases, float* dweights, void* stream);
 
+/* Colour initialisation (Sec. 3.1, "Initialization", Eq. 3) after a render
+   of a batch blended from one set of bases (every frame b holds Gaussians
+   [b N, (b + 1) N) of the blend, as for gbr_backward).  For every Gaussian n
+   with done[n] == 0, the first frame b whose total splatting weight
+   W = sum_p w_p (w_p = the Gaussian's compositing weight alpha T at pixel p)
+   exceeds delta (the paper uses 0.1) sets the base model's colour,
+   bases[0][n][11..13], to sum_p w_p I_p / W, with I the frame's image in
+   targets (same packing as the render's images), and sets done[n] = 1;
+   other Gaussians are left alone.  The sums are the colour adjoint of the
+   render under I and under all-ones images (two gbr_render_backward
+   passes; the context's backward workspace is reused, so a later
+   gbr_backward recomputes its own).  bases [(K+1)][N][16] and done [N] u8
+   are device pointers owned by the caller.  Not inside graph capture
+   (GBR_ERR_STATE); allocates its two scratch buffers on first use. */
+int gbr_color_init(gbr_ctx* ctx, const float* targets, float* bases, float delta, uint8_t* done, void* stream);
+
 /* Photometric loss over the frames of the last render (Sec. 3.2: L1 colour
    loss; kind 1 = L1, 2 = L2), mean over every channel of every pixel.
    Writes dimages (same packing) and keeps the loss value for

@@ -88,6 +88,7 @@ struct gbr_ctx {
   uint32_t* scan_scratch = nullptr;
   int64_t cap_scan_words = 0;
   float* draw_scratch = nullptr;
+  float *ci_ones = nullptr, *ci_draw = nullptr;   // colour initialisation: all-ones images, second adjoint
   float* loss_part = nullptr;
   float* blend_part = nullptr;
   double* blend_w64 = nullptr;     // [kBlendMaxFrames][kBlendW64Stride]
@@ -203,6 +204,7 @@ void free_all(gbr_ctx* c) {
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
+  dfree(c->ci_ones); dfree(c->ci_draw);
   dfree(c->loss_part); dfree(c->blend_part); dfree(c->blend_w64);
   dfree(c->mlp_z1); dfree(c->mlp_z2); dfree(c->mlp_dz1); dfree(c->mlp_dz2);
   if (c->h_frames) (void)hipHostFree(c->h_frames);
@@ -594,6 +596,31 @@ int gbr_backward(gbr_ctx* c, const float* dimages, const float* bases, const flo
   int rc = gbr_render_backward(c, dimages, c->draw_scratch, stream);
   if (rc) return rc;
   return gbr_blend_backward(c, c->draw_scratch, bases, weights, c->B, K, N, dbases, dweights, 0, stream);
+}
+
+int gbr_color_init(gbr_ctx* c, const float* targets, float* bases, float delta, uint8_t* done, void* stream) {
+  if (!c || !targets || !bases || !done || !(delta >= 0.0f)) return GBR_ERR_INVALID_ARG;
+  if (!c->have_raster) return GBR_ERR_STATE;
+  const int64_t N = c->frames_host.empty() ? 0 : c->frames_host[0].gauss_count;
+  for (int b = 0; b < c->B; ++b)
+    if (c->frames_host[b].gauss_count != N || c->frames_host[b].gauss_base != (int64_t)b * N)
+      return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  if (!c->ci_ones) {
+    GBR_HIP(hipDeviceSynchronize());
+    int rc = dalloc(&c->ci_ones, 3 * c->cap_pixels);
+    if (!rc) rc = dalloc(&c->ci_draw, c->cap_splats * kNF);
+    if (rc) { dfree(c->ci_ones); dfree(c->ci_draw); return rc; }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  launch_fill_f32(c->ci_ones, 1.0f, 3 * c->n_pixels, s);
+  int rc = gbr_render_backward(c, targets, c->draw_scratch, stream);
+  if (rc) return rc;
+  rc = gbr_render_backward(c, c->ci_ones, c->ci_draw, stream);
+  if (rc) return rc;
+  launch_color_init_apply(c->draw_scratch, c->ci_draw, c->B, N, delta, bases, done, s);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
 }
 
 int gbr_loss(gbr_ctx* c, const float* images, const float* targets, int32_t kind, float* dimages, void* stream) {

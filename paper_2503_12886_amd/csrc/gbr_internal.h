@@ -262,6 +262,8 @@ void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* s
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s);
+void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, int64_t N, float delta, float* bases,
+                             uint8_t* done, hipStream_t s);
 void launch_clear_flags(const PassArgs& a, hipStream_t s);
 void launch_loss(const PassArgs& a, const float* images, const float* targets, int kind, float* dimages,
                  float* partials, int64_t n_partials, hipStream_t s);

@@ -436,6 +436,38 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   out[3] = make_float4(res[12], res[13], res[14], res[15]);
 }
 
+// ---------------------------------------------------------------- colour initialisation (Eq. 3)
+// draw_i / draw_1: the colour adjoint of the last render under the target
+// images and under all-ones images, i.e. per (frame, Gaussian) the sums of
+// w_p I_p and of w_p over the pixels (w_p the Gaussian's compositing weight).
+// A thread per Gaussian: if not yet initialised, the first frame whose
+// weight exceeds delta sets the base colour to their ratio.
+__global__ __launch_bounds__(256) void color_init_apply_kernel(const float* __restrict__ draw_i,
+                                                               const float* __restrict__ draw_1, int B, int64_t N,
+                                                               float delta, float* __restrict__ bases,
+                                                               uint8_t* __restrict__ done) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N || done[n]) return;
+  for (int b = 0; b < B; ++b) {
+    const int64_t r = ((int64_t)b * N + n) * kNF;
+    const float w = draw_1[r + 11];
+    if (w > delta) {
+      bases[n * kNF + 11] = draw_i[r + 11] / w;
+      bases[n * kNF + 12] = draw_i[r + 12] / w;
+      bases[n * kNF + 13] = draw_i[r + 13] / w;
+      done[n] = 1;
+      return;
+    }
+  }
+}
+
+void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, int64_t N, float delta, float* bases,
+                             uint8_t* done, hipStream_t s) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(color_init_apply_kernel, dim3(div_up(N, 256)), dim3(256), 0, s, draw_i, draw_1, B, N, delta,
+                     bases, done);
+}
+
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s) {
   if (a.n_splats == 0) return;
   hipLaunchKernelGGL(gather_sum_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, draw);

@@ -68,6 +68,7 @@ _SIGS = {
     "gbr_render_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "gbr_blend_backward": ([_vp, _vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _i32, _vp], ctypes.c_int),
     "gbr_backward": ([_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp], ctypes.c_int),
+    "gbr_color_init": ([_vp, _vp, _vp, ctypes.c_float, _vp, _vp], ctypes.c_int),
     "gbr_loss": ([_vp, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "gbr_mlp_forward": ([_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
     "gbr_mlp_backward": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -282,6 +283,16 @@ def gbr_backward(ctx: Context, dimages, bases, weights, dbases, dweights, stream
     _check(lib().gbr_backward(ctx.handle, _f32dev(dimages, "dimages"), _f32dev(bases, "bases"),
                               _f32dev(weights, "weights") if K > 0 else None, K, _f32dev(dbases, "dbases"),
                               _f32dev(dweights, "dweights") if K > 0 else None, _stream(stream)), "gbr_backward")
+
+
+def gbr_color_init(ctx: Context, targets, bases, done, delta: float = 0.1, stream=None) -> None:
+    """Eq. 3 colour initialisation after a render (see include/gbr.h); done is a
+    device uint8 tensor [N], updated in place, as are the base colours."""
+    import torch
+    if done.dtype != torch.uint8 or not done.is_cuda or not done.is_contiguous():
+        raise ValueError("done must be a contiguous uint8 device tensor")
+    _check(lib().gbr_color_init(ctx.handle, _f32dev(targets, "targets"), _f32dev(bases, "bases"), float(delta),
+                                _ptr(done), _stream(stream)), "gbr_color_init")
 
 
 def gbr_loss(ctx: Context, images, targets, kind: int, dimages, stream=None) -> None:

@@ -257,6 +257,27 @@ class Trainer:
             if st.overflow:
                 raise RuntimeError("unexpected overflow in the per-frame scheme")
 
+    # ---------------------------------------------------------------- colour initialisation
+    def color_init(self, delta: float = 0.1) -> int:
+        """Eq. 3 on the current batch: render it, then set the base colour of every
+        not-yet-initialised Gaussian whose total splatting weight in some frame
+        exceeds delta.  Returns how many Gaussians are initialised so far."""
+        c, cfg = self.ctx, self.cfg
+        if getattr(self, "ci_done", None) is None:
+            self.ci_done = self.torch.zeros(cfg.N, dtype=self.torch.uint8, device=self.bases.device)
+        for _ in range(3):
+            with self.torch.cuda.stream(self.stream):
+                gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
+                gbr.gbr_blend(c, self.bases, self.psi, self.raw)
+                gbr.gbr_render(c, self.raw, self.offsets, self.cams, self.images)
+                st = gbr.gbr_query_status(c, self.stream)
+                if not st.overflow:
+                    gbr.gbr_color_init(c, self.targets, self.bases, self.ci_done, delta)
+                    gbr.gbr_query_status(c, self.stream)
+                    return int(self.ci_done.sum().item())
+            self._grow(st.entries)
+        raise RuntimeError("tile-entry overflow persists after growing the capacity")
+
     # ---------------------------------------------------------------- naive batch-parallel scheme
     def naive_batch_grads(self) -> None:
         """Gradients of one batch, rasterising frame by frame with a host

@@ -161,3 +161,22 @@ def test_online_trainer_streams_frames_through_the_pools():
     assert on.captured and tr.graph is not None
     assert list(on.pools.local) and len(on.pools.glob) == 10
     tr.close()
+
+
+def test_color_init_then_training():
+    """Colour initialisation on the batch (Eq. 3) sets the base colours of the
+    visible Gaussians once, and training proceeds from there."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=7)
+    a = Trainer(cfg, bases, mlp)
+    a.set_batch(theta, targets, cams)
+    n1 = a.color_init()
+    assert 0 < n1 < cfg.N
+    c1 = a.bases[0, :, 11:14].cpu().numpy().copy()
+    assert not np.array_equal(c1, bases[0, :, 11:14])
+    n2 = a.color_init()
+    assert n2 == n1 and np.array_equal(a.bases[0, :, 11:14].cpu().numpy(), c1)
+    l0 = a.step().loss
+    for _ in range(3):
+        l1 = a.step().loss
+    assert np.isfinite(l1) and l1 < l0
+    a.close()
