@@ -161,3 +161,69 @@ def make_request_stream(n: int, rate_per_s: float, n_avatars: int, seed: int = 4
     th[:, 50:] = rng.normal(0.0, 0.1, size=(n, 6))
     yaw = rng.uniform(-10.0, 10.0, size=n)
     return t, av, th, yaw
+
+
+# ---------------------------------------------------------------- head mesh (tangent-space binding)
+def make_head_mesh(n_lat: int = 24, n_lon: int = 48, radii=(0.08, 0.10, 0.09)):
+    """A closed-cap-free ellipsoidal band mesh standing in for a tracked head
+    mesh: latitude rows between the poles, quads split in two.  Returns
+    (verts [V,3] f32, faces [F,3] i32, face_uv [F,3,2] f32) with UVs
+    u = longitude / 2 pi (the seam column repeated at u = 1 per face) and
+    v = row / (n_lat - 1)."""
+    lat = np.linspace(0.15 * np.pi, 0.85 * np.pi, n_lat)
+    lon = np.linspace(0.0, 2.0 * np.pi, n_lon, endpoint=False)
+    th, ph = np.meshgrid(lat, lon, indexing="ij")
+    verts = np.stack([np.sin(th) * np.cos(ph) * radii[0], np.cos(th) * radii[1], np.sin(th) * np.sin(ph) * radii[2]],
+                     axis=-1).reshape(-1, 3)
+    faces, uvs = [], []
+    for i in range(n_lat - 1):
+        for j in range(n_lon):
+            j2 = (j + 1) % n_lon
+            a, b, c, d = i * n_lon + j, i * n_lon + j2, (i + 1) * n_lon + j, (i + 1) * n_lon + j2
+            ua, ub = j / n_lon, (j + 1) / n_lon
+            va, vc = i / (n_lat - 1), (i + 1) / (n_lat - 1)
+            faces += [(a, b, c), (b, d, c)]          # counter-clockwise seen from outside
+            uvs += [((ua, va), (ub, va), (ua, vc)), ((ub, va), (ub, vc), (ua, vc))]
+    return verts.astype(np.float32), np.array(faces, dtype=np.int32), np.array(uvs, dtype=np.float32)
+
+
+def deform_mesh(verts: np.ndarray, B: int, seed: int = 21, amp: float = 2e-3) -> np.ndarray:
+    """B per-frame deformations of the mesh: smooth displacements along the
+    radial direction plus a small per-frame rotation and translation."""
+    rng = np.random.default_rng(seed)
+    v = np.asarray(verts, dtype=np.float64)
+    out = np.zeros((B,) + v.shape)
+    rad = v / np.linalg.norm(v, axis=1, keepdims=True)
+    for b in range(B):
+        w = rng.normal(size=3)
+        w /= np.linalg.norm(w)
+        disp = amp * np.sin(40.0 * v @ w + rng.uniform(0, 2 * np.pi))[:, None] * rad
+        a = np.deg2rad(rng.uniform(-5, 5))
+        Q = np.array([[np.cos(a), -np.sin(a), 0.0], [np.sin(a), np.cos(a), 0.0], [0.0, 0.0, 1.0]])
+        out[b] = (v + disp) @ Q.T + rng.normal(0.0, 2e-3, size=3)
+    return out.astype(np.float32)
+
+
+def bind_gaussians(faces: np.ndarray, verts: np.ndarray, N: int, seed: int = 22):
+    """Triangle (area-weighted) and uniform barycentric coordinates per Gaussian."""
+    rng = np.random.default_rng(seed)
+    v = np.asarray(verts, dtype=np.float64)
+    e1 = v[faces[:, 1]] - v[faces[:, 0]]
+    e2 = v[faces[:, 2]] - v[faces[:, 0]]
+    area = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
+    tri = rng.choice(len(faces), size=N, p=area / area.sum()).astype(np.int32)
+    r1, r2 = rng.uniform(size=N), rng.uniform(size=N)
+    s1 = np.sqrt(r1)
+    bary = np.stack([1 - s1, s1 * (1 - r2), s1 * r2], axis=1)
+    return tri, bary.astype(np.float32)
+
+
+def make_tangent_scene(N: int, K: int, seed: int = 0, offset_std: float = 5e-3, delta_std: float = 1e-3):
+    """Bases like make_scene, with positions as small tangent-space offsets
+    (UV units along T and B, and along N) from the bound triangle's point."""
+    bases = make_scene(N, K, seed=seed, delta_std=delta_std).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    bases[0, :, 0:3] = rng.normal(0.0, offset_std, size=(N, 3)) * np.array([1.0, 1.0, 0.2])
+    if K > 0:
+        bases[1:, :, 0:3] *= 0.5
+    return bases.astype(np.float32)
