@@ -156,6 +156,32 @@ int gbr_blend_backward(gbr_ctx* ctx, const float* draw, const float* bases, cons
 int gbr_backward(gbr_ctx* ctx, const float* dimages, const float* bases, const float* weights, int32_t K,
                  float* dbases, float* dweights, void* stream);
 
+/* Tangent-space Gaussians (Sec. 3.1; Eq. 4 and Alg. 1 of the appendix).
+   A mesh of V vertices and F triangles: faces [F][3] i32 vertex indices,
+   face_uv [F][3][2] f32 texture coordinates per triangle corner (the UV
+   triangles must be non-degenerate), verts [B][V][3] f32 one deformed mesh
+   per frame.  gbr_tangent_frames writes, per (frame, triangle), frames
+   [B][F][16] f32: the TBN matrix R = [T B N] row-major (9 values; T and B
+   solve e1 = du1 T + dv1 B, e2 = du2 T + dv2 B for the edges e1 = v1 - v0,
+   e2 = v2 - v0, N the unit normal e1 x e2), then the unit quaternion
+   (w, x, y, z) of R's Gram-Schmidt frame [T^, B^, T^ x B^], then 3 unused.
+   gbr_tangent_transform carries blended Gaussians raw_t [B][N][16] (as
+   gbr_blend writes them; Gaussian n bound to triangle tri[n] with
+   barycentric coordinates bary [N][3]) to raw_d [B][N][16]:
+   x_D = R x_T + (the barycentric point of the frame's triangle),
+   q_D = q_R (x) q_T (Hamilton product), the other features copied.
+   gbr_tangent_backward maps dL/draw_d to dL/draw_t (dx_T = R^T dx_D,
+   dq_T = conj(q_R) (x) dq_D, the rest copied).  All pointers are device
+   pointers owned by the caller; indices out of range are clamped (no
+   fault, meaningless result).  Enqueue only; graph-capturable. */
+int gbr_tangent_frames(gbr_ctx* ctx, const float* verts, const int32_t* faces, const float* face_uv, int32_t B,
+                       int32_t V, int32_t F, float* frames, void* stream);
+int gbr_tangent_transform(gbr_ctx* ctx, const float* raw_t, const int32_t* tri, const float* bary, const float* verts,
+                          const int32_t* faces, const float* frames, int32_t B, int64_t N, int32_t V, int32_t F,
+                          float* raw_d, void* stream);
+int gbr_tangent_backward(gbr_ctx* ctx, const float* draw_d, const int32_t* tri, const float* frames, int32_t B,
+                         int64_t N, int32_t F, float* draw_t, void* stream);
+
 /* Colour initialisation (Sec. 3.1, "Initialization", Eq. 3) after a render
    of a batch blended from one set of bases (every frame b holds Gaussians
    [b N, (b + 1) N) of the blend, as for gbr_backward).  For every Gaussian n

@@ -14,7 +14,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["blend.hip", "depth_order.hip", "raster_fwd.hip", "raster_bwd.hip", "train_ops.hip", "gbr_api.hip"]
+SOURCES = ["blend.hip", "depth_order.hip", "raster_fwd.hip", "raster_bwd.hip", "train_ops.hip", "tangent.hip",
+           "gbr_api.hip"]
 OUT = os.path.join(PKG, "libgbr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -598,6 +598,32 @@ int gbr_backward(gbr_ctx* c, const float* dimages, const float* bases, const flo
   return gbr_blend_backward(c, c->draw_scratch, bases, weights, c->B, K, N, dbases, dweights, 0, stream);
 }
 
+int gbr_tangent_frames(gbr_ctx* c, const float* verts, const int32_t* faces, const float* face_uv, int32_t B,
+                       int32_t V, int32_t F, float* frames, void* stream) {
+  if (!c || !verts || !faces || !face_uv || !frames || B < 1 || V < 3 || F < 1) return GBR_ERR_INVALID_ARG;
+  launch_tangent_frames(verts, faces, face_uv, B, V, F, frames, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_tangent_transform(gbr_ctx* c, const float* raw_t, const int32_t* tri, const float* bary, const float* verts,
+                          const int32_t* faces, const float* frames, int32_t B, int64_t N, int32_t V, int32_t F,
+                          float* raw_d, void* stream) {
+  if (!c || !raw_t || !tri || !bary || !verts || !faces || !frames || !raw_d || B < 1 || N < 1 || V < 3 || F < 1)
+    return GBR_ERR_INVALID_ARG;
+  launch_tangent_fwd(raw_t, tri, bary, verts, faces, frames, B, N, V, F, raw_d, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_tangent_backward(gbr_ctx* c, const float* draw_d, const int32_t* tri, const float* frames, int32_t B,
+                         int64_t N, int32_t F, float* draw_t, void* stream) {
+  if (!c || !draw_d || !tri || !frames || !draw_t || B < 1 || N < 1 || F < 1) return GBR_ERR_INVALID_ARG;
+  launch_tangent_bwd(draw_d, tri, frames, B, N, F, draw_t, (hipStream_t)stream);
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
 int gbr_color_init(gbr_ctx* c, const float* targets, float* bases, float delta, uint8_t* done, void* stream) {
   if (!c || !targets || !bases || !done || !(delta >= 0.0f)) return GBR_ERR_INVALID_ARG;
   if (!c->have_raster) return GBR_ERR_STATE;

@@ -262,6 +262,13 @@ void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* s
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s);
+void launch_tangent_frames(const float* verts, const int32_t* faces, const float* face_uv, int B, int V, int F,
+                           float* frames, hipStream_t s);
+void launch_tangent_fwd(const float* raw_t, const int32_t* tri, const float* bary, const float* verts,
+                        const int32_t* faces, const float* frames, int B, int64_t N, int V, int F, float* raw_d,
+                        hipStream_t s);
+void launch_tangent_bwd(const float* draw_d, const int32_t* tri, const float* frames, int B, int64_t N, int F,
+                        float* draw_t, hipStream_t s);
 void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, int64_t N, float delta, float* bases,
                              uint8_t* done, hipStream_t s);
 void launch_clear_flags(const PassArgs& a, hipStream_t s);

@@ -69,6 +69,9 @@ _SIGS = {
     "gbr_blend_backward": ([_vp, _vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _i32, _vp], ctypes.c_int),
     "gbr_backward": ([_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp], ctypes.c_int),
     "gbr_color_init": ([_vp, _vp, _vp, ctypes.c_float, _vp, _vp], ctypes.c_int),
+    "gbr_tangent_frames": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
+    "gbr_tangent_transform": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp], ctypes.c_int),
+    "gbr_tangent_backward": ([_vp, _vp, _vp, _vp, _i32, _i64, _i32, _vp, _vp], ctypes.c_int),
     "gbr_loss": ([_vp, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "gbr_mlp_forward": ([_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
     "gbr_mlp_backward": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -283,6 +286,41 @@ def gbr_backward(ctx: Context, dimages, bases, weights, dbases, dweights, stream
     _check(lib().gbr_backward(ctx.handle, _f32dev(dimages, "dimages"), _f32dev(bases, "bases"),
                               _f32dev(weights, "weights") if K > 0 else None, K, _f32dev(dbases, "dbases"),
                               _f32dev(dweights, "dweights") if K > 0 else None, _stream(stream)), "gbr_backward")
+
+
+def _i32dev(t, name: str):
+    import torch
+    if t.dtype != torch.int32:
+        raise ValueError(f"{name}: expected int32, got {t.dtype}")
+    return _ptr(t)
+
+
+def gbr_tangent_frames(ctx: Context, verts, faces, face_uv, frames, stream=None) -> None:
+    """verts [B][V][3], faces [F][3] int32, face_uv [F][3][2] -> frames [B][F][16] (device tensors)."""
+    B, V, _ = verts.shape
+    F = faces.shape[0]
+    _check(lib().gbr_tangent_frames(ctx.handle, _f32dev(verts, "verts"), _i32dev(faces, "faces"),
+                                    _f32dev(face_uv, "face_uv"), B, V, F, _f32dev(frames, "frames", B * F * 16),
+                                    _stream(stream)), "gbr_tangent_frames")
+
+
+def gbr_tangent_transform(ctx: Context, raw_t, tri, bary, verts, faces, frames, raw_d, stream=None) -> None:
+    """raw_t [B][N][16] tangent-space Gaussians -> raw_d [B][N][16] deformed-space ones."""
+    B, N, _ = raw_t.shape
+    V, F = verts.shape[1], faces.shape[0]
+    _check(lib().gbr_tangent_transform(ctx.handle, _f32dev(raw_t, "raw_t"), _i32dev(tri, "tri"),
+                                       _f32dev(bary, "bary"), _f32dev(verts, "verts"), _i32dev(faces, "faces"),
+                                       _f32dev(frames, "frames"), B, N, V, F, _f32dev(raw_d, "raw_d", B * N * 16),
+                                       _stream(stream)), "gbr_tangent_transform")
+
+
+def gbr_tangent_backward(ctx: Context, draw_d, tri, frames, draw_t, stream=None) -> None:
+    """dL/draw_d [B][N][16] -> dL/draw_t [B][N][16]."""
+    B, N, _ = draw_d.shape
+    F = frames.shape[1]
+    _check(lib().gbr_tangent_backward(ctx.handle, _f32dev(draw_d, "draw_d"), _i32dev(tri, "tri"),
+                                      _f32dev(frames, "frames"), B, N, F, _f32dev(draw_t, "draw_t", B * N * 16),
+                                      _stream(stream)), "gbr_tangent_backward")
 
 
 def gbr_color_init(ctx: Context, targets, bases, done, delta: float = 0.1, stream=None) -> None:
