@@ -13,8 +13,9 @@ step, host synchronisation between preprocess and rasterize) and the naive
 batch-parallel scheme (one update per batch, frames rasterised one by one
 with a synchronisation each) on the same GPU, the dominant kernel's roofline
 position measured with HIP events over the timed region, a per-kernel time
-breakdown, and the float64 CPU reference timed on a bounded sample.  With
---k-sweep, also the graph-captured step time at other blendshape counts.
+breakdown, the float64 CPU reference timed on a bounded sample, and the
+same step with the Gaussians in a mesh's tangent space.  With --k-sweep,
+also the graph-captured step time at other blendshape counts.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -226,6 +227,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if not args.quick:
+        out["tangent"] = tangent_leg(args)
     if args.k_sweep:
         out["k_sweep"] = k_sweep_leg([int(k) for k in args.k_sweep.split(",") if k], args)
 
@@ -264,6 +267,57 @@ def serve_leg(seconds: float) -> dict:
                   "window_ms": 2.0, "budget_bytes": 2 << 30, "slots": 3,
                   "latency": "arrival to render complete on the GPU"})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
+
+
+def tangent_leg(args) -> dict:
+    """The same batched step with the Gaussians in tangent space (Eq. 4): bound
+    to a synthetic head mesh deformed per frame, transformed before the render
+    and the gradient carried back; graph-captured ms per step."""
+    import torch
+    from paper_2503_12886_amd import synth
+    from paper_2503_12886_amd.trainer import Trainer, mlp_pack
+    cfg, _, mlp, theta, cams, targets = make_workload()
+    cfg.tile, cfg.chunk = args.tile, args.chunk
+    verts, faces, uv = synth.make_head_mesh()
+    vb = synth.deform_mesh(verts, cfg.B, seed=21)
+    tri, bary = synth.bind_gaussians(faces, verts, cfg.N, seed=22)
+    bases = synth.make_tangent_scene(cfg.N, cfg.K, seed=0)
+    tr = Trainer(cfg, bases, mlp)
+    tr.bind_mesh(faces, uv, tri, bary, verts.shape[0])
+    tr.set_batch(theta, targets, cams, verts=vb)
+    tr.render_targets()
+    tr.load_bases(synth.perturb_scene(bases, pos_std=5e-4))
+    for _ in range(3):
+        tr.step()
+    tr.capture()
+    for _ in range(5):
+        tr.step()
+    torch.cuda.synchronize()
+    n = 30
+    t0 = time.perf_counter()
+    for _ in range(n):
+        tr.step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n
+    # the transform's own cost: frames, forward transform and adjoint, alone
+    from paper_2503_12886_amd import gbr
+    with torch.cuda.stream(tr.stream):
+        for _ in range(3):
+            tr._to_deformed()
+            gbr.gbr_tangent_backward(tr.ctx, tr.draw_d, tr.tri, tr.frames, tr.draw_t)
+        tr.stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            tr._to_deformed()
+            gbr.gbr_tangent_backward(tr.ctx, tr.draw_d, tr.tri, tr.frames, tr.draw_t)
+        tr.stream.synchronize()
+        dtx = (time.perf_counter() - t0) / n
+    tr.close()
+    v = cfg.B / dt
+    return {"value": round(v, 2), "unit": "img/s", "ms_per_step": round(dt * 1e3, 4), "steps": n,
+            "triangles": int(faces.shape[0]), "transform_ms": round(dtx * 1e3, 4),
+            "note": "a surface-bound scene of its own, so the step time is not comparable to the main line; "
+                    "transform_ms is the tangent frames, transform and adjoint per step"}
 
 
 def k_sweep_leg(ks, args) -> dict:

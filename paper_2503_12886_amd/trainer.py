@@ -114,12 +114,36 @@ class Trainer:
         self.stream = torch.cuda.Stream(device=dev)
 
     # ---------------------------------------------------------------- inputs
-    def set_batch(self, theta: np.ndarray, targets: np.ndarray, cams: list) -> None:
-        """Copy one batch of (tracking vector, target image, camera) into the step's buffers."""
+    def bind_mesh(self, faces: np.ndarray, face_uv: np.ndarray, tri: np.ndarray, bary: np.ndarray,
+                  n_verts: int) -> None:
+        """Tangent-space Gaussians (Sec. 3.1, Eq. 4): Gaussian n is bound to
+        triangle tri[n] at barycentric coordinates bary[n]; every batch then
+        carries one deformed mesh per frame (set_batch(..., verts=...)) and the
+        step transforms the blended Gaussians to it before rendering."""
+        torch, cfg = self.torch, self.cfg
+        assert self.graph is None, "bind the mesh before capturing"
+        dev = self.bases.device
+        self.faces = torch.from_numpy(np.ascontiguousarray(faces, dtype=np.int32)).to(dev)
+        self.face_uv = torch.from_numpy(np.ascontiguousarray(face_uv, dtype=np.float32)).to(dev)
+        self.tri = torch.from_numpy(np.ascontiguousarray(tri, dtype=np.int32)).to(dev)
+        self.bary = torch.from_numpy(np.ascontiguousarray(bary, dtype=np.float32)).to(dev)
+        F = self.faces.shape[0]
+        self.verts = torch.zeros(cfg.B, n_verts, 3, device=dev, dtype=torch.float32)
+        self.frames = torch.zeros(cfg.B, F, 16, device=dev, dtype=torch.float32)
+        self.raw_d = torch.zeros_like(self.raw)
+        self.draw_d = torch.zeros_like(self.raw)
+        self.draw_t = torch.zeros_like(self.raw)
+
+    def set_batch(self, theta: np.ndarray, targets: np.ndarray, cams: list, verts=None) -> None:
+        """Copy one batch of (tracking vector, target image, camera[, deformed mesh])
+        into the step's buffers."""
         assert len(cams) == self.cfg.B
+        assert (verts is None) == (getattr(self, "verts", None) is None), "verts go with a bound mesh"
         self.torch.cuda.synchronize()
         self.theta.copy_(self.torch.from_numpy(np.ascontiguousarray(theta, dtype=np.float32)))
         self.targets.copy_(self.torch.from_numpy(np.ascontiguousarray(targets, dtype=np.float32).ravel()))
+        if verts is not None:
+            self.verts.copy_(self.torch.from_numpy(np.ascontiguousarray(verts, dtype=np.float32)))
         self.torch.cuda.synchronize()
         self.cams = list(cams)
         if self.graph is not None:
@@ -129,6 +153,7 @@ class Trainer:
         """The same from device tensors (theta [B][d_in], targets [B][3 H W]),
         ordered on the trainer's stream."""
         assert len(cams) == self.cfg.B
+        self._no_mesh("streaming batches")
         cur = self.torch.cuda.current_stream()
         self.stream.wait_stream(cur)
         with self.torch.cuda.stream(self.stream):
@@ -147,7 +172,7 @@ class Trainer:
         with self.torch.cuda.stream(self.stream):
             gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
             gbr.gbr_blend(c, self.bases, self.psi, self.raw)
-            gbr.gbr_render(c, self.raw, self.offsets, self.cams, self.targets)
+            gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.targets)
             st = gbr.gbr_query_status(c, self.stream)
         if st.overflow:
             gbr.gbr_reserve(c, st.entries + st.entries // 4 + 4096)
@@ -177,13 +202,28 @@ class Trainer:
         with self.torch.cuda.stream(self.stream):
             self._enqueue_grads()
 
+    def _to_deformed(self):
+        """The blended Gaussians as rendered: carried to the frames' meshes when
+        a mesh is bound (enqueued on the current stream)."""
+        if getattr(self, "verts", None) is None:
+            return self.raw
+        c = self.ctx
+        gbr.gbr_tangent_frames(c, self.verts, self.faces, self.face_uv, self.frames)
+        gbr.gbr_tangent_transform(c, self.raw, self.tri, self.bary, self.verts, self.faces, self.frames, self.raw_d)
+        return self.raw_d
+
     def _enqueue_grads(self) -> None:
         c, cfg = self.ctx, self.cfg
         gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
         gbr.gbr_blend(c, self.bases, self.psi, self.raw)
-        gbr.gbr_render(c, self.raw, self.offsets, self.cams, self.images)
+        gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.images)
         gbr.gbr_loss(c, self.images, self.targets, cfg.loss, self.dimages)
-        gbr.gbr_backward(c, self.dimages, self.bases, self.psi, self.dbases, self.dpsi)
+        if getattr(self, "verts", None) is None:
+            gbr.gbr_backward(c, self.dimages, self.bases, self.psi, self.dbases, self.dpsi)
+        else:
+            gbr.gbr_render_backward(c, self.dimages, self.draw_d)
+            gbr.gbr_tangent_backward(c, self.draw_d, self.tri, self.frames, self.draw_t)
+            gbr.gbr_blend_backward(c, self.draw_t, self.bases, self.psi, self.dbases, self.dpsi)
         gbr.gbr_mlp_backward(c, self.mlp, self.dpsi, self.dmlp)
 
     def _enqueue_step(self) -> None:
@@ -231,7 +271,12 @@ class Trainer:
         with self.torch.cuda.stream(self.stream):
             self._per_frame_steps(frames)
 
+    def _no_mesh(self, what: str) -> None:
+        if getattr(self, "verts", None) is not None:
+            raise NotImplementedError(f"{what} runs on world-space Gaussians only (no bound mesh)")
+
     def _per_frame_steps(self, frames) -> None:
+        self._no_mesh("the per-frame scheme")
         c, cfg = self.ctx, self.cfg
         npix = cfg.width * cfg.height
         for b in frames:
@@ -269,7 +314,7 @@ class Trainer:
             with self.torch.cuda.stream(self.stream):
                 gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
                 gbr.gbr_blend(c, self.bases, self.psi, self.raw)
-                gbr.gbr_render(c, self.raw, self.offsets, self.cams, self.images)
+                gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.images)
                 st = gbr.gbr_query_status(c, self.stream)
                 if not st.overflow:
                     gbr.gbr_color_init(c, self.targets, self.bases, self.ci_done, delta)
@@ -288,6 +333,7 @@ class Trainer:
             self._naive_batch_grads()
 
     def _naive_batch_grads(self) -> None:
+        self._no_mesh("the naive batch-parallel scheme")
         c, cfg = self.ctx, self.cfg
         npix = cfg.width * cfg.height
         if getattr(self, "draw", None) is None:
