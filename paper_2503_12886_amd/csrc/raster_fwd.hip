@@ -539,7 +539,7 @@ struct __align__(16) StagedRec {
 // indices of the same residue mod 8, so that they run on one XCD and share
 // its L2.
 template <int T, int CHUNK>
-__global__ __launch_bounds__(64) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
+__global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(PassArgs a, float* __restrict__ images) {
   using S = TileShape<T>;
   constexpr int NQ = S::NW;             // quadrants per tile
   constexpr int U = 4;                  // entries evaluated together (independent alphas)
