@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--quick", action="store_true", help="few steps, no per-frame/CPU legs (for profilers)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="the timed region at full length, no other legs (for a profiler's per-kernel averages)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -112,28 +114,19 @@ def main():
     tr.render_targets()                          # ground-truth avatar's frames
     tr.load_bases(synth.perturb_scene(bases))    # fit from a perturbed start
 
-    # warm-up (sizes the tile-entry buffers), then per-kernel breakdown of one eager step
+    # warm-up (sizes the tile-entry buffers), then the dominant kernel from a
+    # per-kernel breakdown of one eager step
     for _ in range(3):
         tr.step()
-    breakdown = {}
-    for k in range(len(gbr.KERNEL_NAMES)):
-        gbr.gbr_timing(tr.ctx, k, True)
-    st = tr.step()
-    for k, name in enumerate(gbr.KERNEL_NAMES):
-        try:
-            breakdown[name] = round(gbr.gbr_timing_read(tr.ctx, k), 4)
-        except gbr.GbrError:
-            pass
-        gbr.gbr_timing(tr.ctx, k, False)
-    entries = int(st.entries)
-    n_contrib = gbr.gbr_inspect(tr.ctx, "n_contrib", cfg.B * cfg.width * cfg.height).astype(np.int64)
-    X = int(n_contrib.sum())
+    breakdown = eager_breakdown(tr)
     dominant = max(("composite_fwd", "composite_bwd", "tile_sort", "binning", "gather_bwd", "adam", "blend",
                     "blend_bwd", "preprocess"), key=lambda k: breakdown.get(k, 0.0))
     dom_id = gbr.KERNEL_NAMES.index(dominant)
 
-    # timed region: graph-captured batched steps, one status read per step;
-    # the dominant kernel is bracketed by HIP events on the launch stream
+    # timed region: graph-captured batched steps, one status read per step.
+    # The dominant kernel is bracketed on its launch stream by the library's
+    # wall-clock stamp kernels, which a graph replays with every step; their
+    # device accumulator is cleared when the timed region starts.
     gbr.gbr_timing(tr.ctx, dom_id, True)
     if not args.no_graph:
         tr.capture()
@@ -141,17 +134,29 @@ def main():
     for _ in range(2 if args.quick else args.warmup):
         tr.step()
     torch.cuda.synchronize()
-    dom_ms = []
+    gbr.gbr_timing_accum(tr.ctx, dom_id, reset=True)
+    first_step = tr.steps_launched
     t0 = time.perf_counter()
     for _ in range(steps):
         st = tr.step()
-        dom_ms.append(gbr.gbr_timing_read(tr.ctx, dom_id))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    dom_total, dom_n = gbr.gbr_timing_accum(tr.ctx, dom_id)
     gbr.gbr_timing(tr.ctx, dom_id, False)
+    assert dom_n == steps == tr.steps_launched - first_step, f"{dominant}: {dom_n} bracketed launches in {steps} steps"
     ms_step = (t1 - t0) * 1e3 / steps
     value = cfg.B * steps / (t1 - t0)
-    dom_avg = float(np.mean(dom_ms))
+    dom_avg = dom_total / dom_n
+    # contributing pairs of the last timed step (the fit changes the scene, so
+    # the pre-region count would not match the timed launches)
+    n_contrib = gbr.gbr_inspect(tr.ctx, "n_contrib", cfg.B * cfg.width * cfg.height).astype(np.int64)
+    X = int(n_contrib.sum())
+    entries = int(st.entries)
+    # per-kernel breakdown of one eager step where the timed region ended
+    if tr.graph is not None:
+        gbr.gbr_graph_destroy(tr.graph)
+        tr.graph = None
+    breakdown = eager_breakdown(tr)
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "img/s", "n_gpus": 1, "steps": steps,
@@ -172,13 +177,15 @@ def main():
         achieved = X * per / (dom_avg * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "work_per_launch": f"{X} contributing pairs x {per} FLOP", "avg_ms": round(dom_avg, 4)}
+                "work_per_launch": f"{X} contributing pairs x {per} FLOP", "avg_ms": round(dom_avg, 4),
+                "timed_launches": [first_step, steps]}
     else:
         per_entry = {"tile_sort": 8 + 8 + 4 + 4, "binning": 8 + 4}.get(dominant, 0)
         achieved = entries * per_entry / (dom_avg * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "work_per_launch": f"{entries} entries x {per_entry} B", "avg_ms": round(dom_avg, 4)}
+                "work_per_launch": f"{entries} entries x {per_entry} B", "avg_ms": round(dom_avg, 4),
+                "timed_launches": [first_step, steps]}
     prof = os.path.join(ROOT, "profiles", f"{dominant}_{WORKLOAD_TAG}.traffic.json")
     roof["traffic"] = None
     if os.path.exists(prof):
@@ -188,10 +195,7 @@ def main():
     out["roofline"] = roof
 
     # per-frame scheme on the same GPU
-    if not args.quick:
-        if tr.graph is not None:
-            gbr.gbr_graph_destroy(tr.graph)
-            tr.graph = None
+    if not args.quick and not args.timed_only:
         nf = args.per_frame_frames
         tr.per_frame_steps(range(cfg.B))          # warm-up
         torch.cuda.synchronize()
@@ -227,19 +231,36 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if not args.quick:
+    if not args.quick and not args.timed_only:
         out["tangent"] = tangent_leg(args)
     if args.k_sweep:
         out["k_sweep"] = k_sweep_leg([int(k) for k in args.k_sweep.split(",") if k], args)
 
-    if not args.quick and not args.no_serve:
+    if not args.quick and not args.timed_only and not args.no_serve:
         out["serve"] = serve_leg(args.serve_seconds)
-    if not args.quick and not args.no_cpu:
+    if not args.quick and not args.timed_only and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
 SERVE_NS = (20_000, 40_000, 60_000, 80_000, 100_000, 100_000, 50_000, 30_000)
+
+
+def eager_breakdown(tr) -> dict:
+    """Kernel times (ms) of one eager training step, from HIP events around
+    each launch on the trainer's stream."""
+    from paper_2503_12886_amd import gbr
+    for k in range(len(gbr.KERNEL_NAMES)):
+        gbr.gbr_timing(tr.ctx, k, True)
+    tr.step()
+    out = {}
+    for k, name in enumerate(gbr.KERNEL_NAMES):
+        try:
+            out[name] = round(gbr.gbr_timing_read(tr.ctx, k), 4)
+        except gbr.GbrError:
+            pass
+        gbr.gbr_timing(tr.ctx, k, False)
+    return out
 
 
 def serve_leg(seconds: float) -> dict:

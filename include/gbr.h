@@ -277,11 +277,24 @@ int gbr_autotune(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, c
    *bytes in: capacity of dst; out: bytes written. */
 int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
 
-/* Kernel timing for measurement tools.  which: GBR_K_* below.  While
-   enabled, the library records a pair of HIP events on the launch stream
-   around every launch of that kernel (also inside a captured graph);
-   gbr_timing_read returns the duration of the most recent launch in ms
-   (call after the stream has been synchronised, e.g. by gbr_query_status). */
+/* Kernel timing for measurement tools.  which: GBR_K_* below.  Not a
+   passage of the paper: it exists so that a benchmark can time one kernel
+   on its own launch stream.  While timing of a kernel is enabled, every
+   launch of it is bracketed
+   - in eager calls, by a pair of HIP events on the launch stream:
+     gbr_timing_read returns the duration of the most recent eager launch
+     in ms;
+   - in eager calls and in captured graphs alike, by two one-lane stamp
+     kernels on the launch stream that read the device's constant-rate
+     wall clock before and after the launch and add the difference to a
+     device accumulator: gbr_timing_accum returns the accumulated ms and
+     the number of bracketed launches (reset != 0 then clears them).
+   A graph captured while timing was enabled keeps its stamp kernels on
+   every replay, whatever gbr_timing says later.  Brackets include the
+   kernel's dispatch latency (a few microseconds).
+   gbr_timing(enable=1) synchronises the device and clears that kernel's
+   accumulator; it fails with GBR_ERR_STATE during capture, as does
+   gbr_timing_accum, which synchronises the device before reading. */
 #define GBR_K_BLEND 0
 #define GBR_K_PREPROCESS 1
 #define GBR_K_BINNING 2      /* splat-offset scan + per-tile rank bitmap rows */
@@ -298,6 +311,7 @@ int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
 #define GBR_K_COUNT 13
 int gbr_timing(gbr_ctx* ctx, int32_t which, int32_t enable);
 int gbr_timing_read(gbr_ctx* ctx, int32_t which, float* ms);
+int gbr_timing_accum(gbr_ctx* ctx, int32_t which, int32_t reset, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -4,7 +4,7 @@
 // instead of once per tile:
 //   1. splats are distributed over nbk buckets per frame by their depth bits,
 //      scaled between the frame's min and max (monotone in depth);
-//   2. buckets are ranked by direct comparison, 64 buckets per workgroup
+//   2. buckets are ranked by direct comparison, 32 buckets per workgroup
 //      in LDS (or a wave per bucket when they do not fit); large buckets go
 //      to a block that compares in LDS (<= 2048) or runs the stable radix
 //      passes through global memory.
@@ -100,13 +100,13 @@ __device__ __forceinline__ void emit_ranked(const PassArgs& a, unsigned long lon
 }
 
 // Ranks within buckets.  Keys are unique, so a key's rank is the number of
-// smaller keys in its bucket.  A workgroup takes 64 consecutive buckets:
+// smaller keys in its bucket.  A workgroup takes 32 consecutive buckets:
 // when their keys fit in LDS, every thread ranks keys against the keys of
 // their bucket there; otherwise a wave per bucket compares through lane
 // reads.  Buckets of more than kRankMax keys (kWaveMax on the wave path) go
 // to the large-bucket pass.  The bucket count per frame is a power of two
 // of at least 64, so a workgroup's buckets belong to one frame.
-constexpr int kRankBuckets = 64;
+constexpr int kRankBuckets = 32;
 constexpr int kRankKeys = 2048;
 constexpr uint32_t kRankMax = 128;
 constexpr uint32_t kWaveMax = 64;

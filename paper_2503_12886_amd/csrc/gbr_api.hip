@@ -111,6 +111,8 @@ struct gbr_ctx {
   // kernel timing
   bool timing_on[GBR_K_COUNT] = {};
   hipEvent_t t_ev[GBR_K_COUNT][2] = {};
+  unsigned long long* t_stamp = nullptr;   // [GBR_K_COUNT][4]: start, sum of ticks, launches, unused
+  int wall_khz = 0;                        // wall-clock rate of the device
   // MLP state
   const float* mlp_theta = nullptr;
   int mlp_B = 0, mlp_din = 0, mlp_hidden = 0, mlp_K = 0;
@@ -153,15 +155,38 @@ PassArgs make_args(gbr_ctx* c) {
   return a;
 }
 
-// Events recorded around one kernel's launch when its timing is enabled.
+// Launch brackets of one kernel while its timing is enabled.
+//  * Eagerly: a pair of HIP events on the launch stream, read by
+//    gbr_timing_read (duration of the most recent launch).
+//  * Always: two one-lane stamp kernels on the same stream that read the
+//    GPU's constant-rate wall clock before and after the launch and add the
+//    difference to a device accumulator (gbr_timing_accum). Stamp kernels are
+//    ordinary launches, so a captured graph repeats them on every replay;
+//    an event recorded during capture is only a dependency inside the graph
+//    and keeps the timestamp of its last eager record.
+__global__ void timer_stamp_kernel(unsigned long long* slot, int phase) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long now = wall_clock64();
+  if (phase == 0) {
+    slot[0] = now;
+  } else {
+    slot[1] += now - slot[0];
+    slot[2] += 1ULL;
+  }
+}
+
 struct KTimer {
   gbr_ctx* c; int k; hipStream_t s; bool on;
   KTimer(gbr_ctx* c_, int k_, hipStream_t s_)
       : c(c_), k(k_), s(s_), on(k_ >= 0 && k_ < GBR_K_COUNT && c_->timing_on[k_]) {
-    if (on) (void)hipEventRecord(c->t_ev[k][0], s);
+    if (!on) return;
+    timer_stamp_kernel<<<1, 64, 0, s>>>(c->t_stamp + 4 * k, 0);
+    if (!c->capturing) (void)hipEventRecord(c->t_ev[k][0], s);   // events bracket the kernel alone
   }
   ~KTimer() {
-    if (on) (void)hipEventRecord(c->t_ev[k][1], s);
+    if (!on) return;
+    if (!c->capturing) (void)hipEventRecord(c->t_ev[k][1], s);
+    timer_stamp_kernel<<<1, 64, 0, s>>>(c->t_stamp + 4 * k, 1);
   }
 };
 
@@ -207,6 +232,7 @@ void free_all(gbr_ctx* c) {
   dfree(c->ci_ones); dfree(c->ci_draw);
   dfree(c->loss_part); dfree(c->blend_part); dfree(c->blend_w64);
   dfree(c->mlp_z1); dfree(c->mlp_z2); dfree(c->mlp_dz1); dfree(c->mlp_dz2);
+  dfree(c->t_stamp);
   if (c->h_frames) (void)hipHostFree(c->h_frames);
   if (c->h_status) (void)hipHostFree(c->h_status);
   c->h_frames = nullptr; c->h_status = nullptr;
@@ -334,7 +360,7 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   if (rc) return rc;
   if ((mfs + 31) / 32 > kMaxBitmapWords) return GBR_ERR_CAPACITY;
   int nbk = 64;
-  while (nbk < 8192 && (int64_t)nbk * 16 < mfs) nbk *= 2;
+  while (nbk < 8192 && (int64_t)nbk * 8 < mfs) nbk *= 2;
   const int nblk = (int)std::max<int64_t>(1, (mfs + 4095) / 4096);
   if ((int64_t)B * nbk > c->cap_bkt || (int64_t)B * nbk * nblk > c->cap_bkt_cells) {
     if (c->capturing) return GBR_ERR_STATE;
@@ -881,7 +907,32 @@ int gbr_timing(gbr_ctx* c, int32_t which, int32_t enable) {
     GBR_HIP(hipEventCreate(&c->t_ev[which][0]));
     GBR_HIP(hipEventCreate(&c->t_ev[which][1]));
   }
+  if (enable && !c->t_stamp) {
+    int rc = dalloc(&c->t_stamp, 4 * GBR_K_COUNT);
+    if (rc) return rc;
+    GBR_HIP(hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, c->cfg.device));
+    if (c->wall_khz <= 0) return GBR_ERR_HIP;
+    GBR_HIP(hipMemset(c->t_stamp, 0, sizeof(unsigned long long) * 4 * GBR_K_COUNT));
+  }
+  if (enable) {
+    // restart the accumulator after everything queued so far
+    GBR_HIP(hipDeviceSynchronize());
+    GBR_HIP(hipMemset(c->t_stamp + 4 * which, 0, sizeof(unsigned long long) * 4));
+  }
   c->timing_on[which] = enable != 0;
+  return GBR_OK;
+}
+
+int gbr_timing_accum(gbr_ctx* c, int32_t which, int32_t reset, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches || which < 0 || which >= GBR_K_COUNT) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  if (!c->t_stamp) return GBR_ERR_STATE;
+  unsigned long long h[4];
+  GBR_HIP(hipDeviceSynchronize());
+  GBR_HIP(hipMemcpy(h, c->t_stamp + 4 * which, sizeof(h), hipMemcpyDeviceToHost));
+  *total_ms = (double)h[1] / (double)c->wall_khz;
+  *launches = (int64_t)h[2];
+  if (reset) GBR_HIP(hipMemset(c->t_stamp + 4 * which, 0, sizeof(h)));
   return GBR_OK;
 }
 

@@ -88,6 +88,8 @@ _SIGS = {
     "gbr_inspect": ([_vp, _i32, _vp, ctypes.POINTER(_i64)], ctypes.c_int),
     "gbr_timing": ([_vp, _i32, _i32], ctypes.c_int),
     "gbr_timing_read": ([_vp, _i32, ctypes.POINTER(_f32)], ctypes.c_int),
+    "gbr_timing_accum": ([_vp, _i32, _i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+                         ctypes.c_int),
 }
 
 # kernel ids of gbr_timing (GBR_K_*)
@@ -416,6 +418,16 @@ def gbr_timing_read(ctx: Context, which: int) -> float:
     ms = _f32()
     _check(lib().gbr_timing_read(ctx.handle, int(which), ctypes.byref(ms)), "gbr_timing_read")
     return float(ms.value)
+
+
+def gbr_timing_accum(ctx: Context, which: int, reset: bool = False) -> tuple:
+    """(total ms, launches) of one kernel accumulated on the device since its
+    timing was enabled (or last reset); counts graph replays too."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().gbr_timing_accum(ctx.handle, int(which), int(bool(reset)), ctypes.byref(ms), ctypes.byref(n)),
+           "gbr_timing_accum")
+    return float(ms.value), int(n.value)
 
 
 def gbr_inspect(ctx: Context, what: str, count: int) -> np.ndarray:

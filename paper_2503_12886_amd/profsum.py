@@ -2,15 +2,18 @@
 
 Two reports, both from rocprofv3's CSV output (``--output-format csv``):
 
-* ``stats DIR``: the per-kernel table of a ``--kernel-trace --stats`` run
-  (calls, average / min / max duration, share of GPU time), short names;
+* ``stats DIR [--window KERNEL:FIRST:COUNT]``: the per-kernel table of a
+  ``--kernel-trace --stats`` run (calls, average / min / max duration, share
+  of GPU time), short names; with ``--window``, also the average duration of
+  one kernel over a range of its launches (a benchmark's timed region);
 * ``traffic --fetch DIR --write DIR --kernel NAME --copy-bytes N``: HBM bytes
   per launch of one kernel from two ``--pmc`` passes (``FETCH_SIZE``, then
   ``WRITE_SIZE``, KiB per dispatch summed over counter instances), each scaled
   by what the same counter reads for a plain device-to-device copy of N bytes
   in the same run (the copy reads N and writes N bytes).  With ``--json`` it
   also writes the per-launch bytes, the factors and a hash of the kernel's
-  source files, so a reader can tell when the figure went stale.
+  source files, so a reader can tell when the figure went stale; with
+  ``--window FIRST:COUNT`` only those launches of the kernel are averaged.
 
 Usage:
   python -m paper_2503_12886_amd.profsum stats gpurun_out/stats
@@ -85,6 +88,19 @@ def stats(d: str, top: int = 40) -> str:
     return "\n".join(out)
 
 
+def window(d: str, kernel: str, first: int, count: int) -> str:
+    """Average duration of launches first .. first+count-1 (in dispatch order)
+    of one kernel, from the per-dispatch kernel trace."""
+    rows = [r for r in _rows(_find(d, "kernel_trace.csv")) if short_name(r["Kernel_Name"]).startswith(kernel)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = rows[first:first + count]
+    if len(sel) != count:
+        raise LookupError(f"{kernel}: {len(rows)} launches traced, window {first}+{count}")
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+    return (f"{kernel} launches {first}..{first + count - 1} of {len(rows)}: avg {sum(dur) / count:.2f} us, "
+            f"min {min(dur):.2f} us, max {max(dur):.2f} us")
+
+
 def _per_dispatch(d: str, counter: str):
     """{dispatch id: (short kernel name, counter value summed over instances)}."""
     rows = _rows(_find(d, "counter_collection.csv"))
@@ -99,14 +115,19 @@ def _per_dispatch(d: str, counter: str):
     return {k: (name[k], v) for k, v in val.items()}
 
 
-def _mean_for(disp, match) -> tuple:
-    vals = [v for (n, v) in disp.values() if match(n)]
+def _mean_for(disp, match, win=None) -> tuple:
+    vals = [disp[k][1] for k in sorted(disp, key=int) if match(disp[k][0])]
+    if win is not None:
+        first, count = win
+        if len(vals) < first + count:
+            raise LookupError(f"{len(vals)} dispatches matched, window {first}+{count}")
+        vals = vals[first:first + count]
     if not vals:
         raise LookupError("no dispatch matched")
     return sum(vals) / len(vals), len(vals)
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, copy_match: str):
+def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, copy_match: str, win=None):
     fetch = _per_dispatch(fetch_dir, "FETCH_SIZE")
     write = _per_dispatch(write_dir, "WRITE_SIZE")
 
@@ -117,14 +138,14 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, copy_m
         return copy_match.lower() in n.lower()
 
     kib = 1024.0
-    f_k, nf = _mean_for(fetch, is_kernel)
-    w_k, nw = _mean_for(write, is_kernel)
+    f_k, nf = _mean_for(fetch, is_kernel, win)
+    w_k, nw = _mean_for(write, is_kernel, win)
     # the copy of known size: the largest matching dispatch in each pass
     f_c = max(v for (n, v) in fetch.values() if is_copy(n))
     w_c = max(v for (n, v) in write.values() if is_copy(n))
     ff = copy_bytes / (f_c * kib)
     fw = copy_bytes / (w_c * kib)
-    res = {"kernel": kernel, "launches": [nf, nw],
+    res = {"kernel": kernel, "launches": [nf, nw], "window": list(win) if win else None,
            "fetch_kib_raw": f_k, "write_kib_raw": w_k,
            "copy_bytes": copy_bytes, "copy_fetch_kib_raw": f_c, "copy_write_kib_raw": w_c,
            "fetch_factor": ff, "write_factor": fw,
@@ -143,6 +164,8 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("--top", type=int, default=40)
+    s.add_argument("--window", help="KERNEL:FIRST:COUNT, the average over those launches of KERNEL "
+                                    "(a benchmark's timed region) from the kernel trace")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -150,11 +173,16 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--copy-match", default="copy")
     t.add_argument("--json")
+    t.add_argument("--window", help="FIRST:COUNT, average over those launches of the kernel only")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.dir, a.top))
+        if a.window:
+            k, first, count = a.window.split(":")
+            print(window(a.dir, k, int(first), int(count)))
         return 0
-    res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.copy_match)
+    win = tuple(int(x) for x in a.window.split(":")) if a.window else None
+    res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.copy_match, win)
     if a.json:
         srcs = KERNEL_SOURCES.get(a.kernel, [])
         meta = dict(res, sources=srcs, source_hash=source_hash(srcs))

@@ -109,6 +109,7 @@ class Trainer:
         self.lr_mlp = [MLP_LR] * 32
         self.cams = None
         self.graph = None
+        self.steps_launched = 0     # batched steps enqueued, retries included
         self.offsets = [b * N for b in range(B + 1)]
         # a stream of its own (default priority): the legacy null stream cannot be captured
         self.stream = torch.cuda.Stream(device=dev)
@@ -242,6 +243,7 @@ class Trainer:
                 gbr.gbr_graph_launch(self.graph, self.stream)
             else:
                 self.enqueue_step()
+            self.steps_launched += 1
             st = gbr.gbr_query_status(self.ctx, self.stream)
             if not st.overflow:
                 return st

@@ -180,3 +180,32 @@ def test_color_init_then_training():
         l1 = a.step().loss
     assert np.isfinite(l1) and l1 < l0
     a.close()
+
+
+def test_kernel_timing_brackets_count_graph_replays():
+    """The wall-clock brackets of a timed kernel run in eager steps and again
+    on every replay of a graph captured with timing on, and leave the step's
+    results untouched."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=4)
+    a = Trainer(cfg, bases, mlp)
+    a.set_batch(theta, targets, cams)
+    b = Trainer(cfg, bases, mlp)
+    b.set_batch(theta, targets, cams)
+    k = gbr.KERNEL_NAMES.index("composite_bwd")
+    la = [a.step().loss for _ in range(6)]
+    lb = [b.step().loss]
+    gbr.gbr_timing(b.ctx, k, True)
+    lb += [b.step().loss for _ in range(2)]
+    ev_ms = gbr.gbr_timing_read(b.ctx, k)
+    tot, n = gbr.gbr_timing_accum(b.ctx, k, reset=True)
+    assert n == 2 and tot > 0.0 and ev_ms > 0.0
+    assert 0.2 < (tot / n) / ev_ms < 5.0
+    b.capture()
+    lb += [b.step().loss for _ in range(3)]
+    tot, n = gbr.gbr_timing_accum(b.ctx, k)
+    assert n == 3 and tot > 0.0
+    gbr.gbr_timing(b.ctx, k, False)
+    assert la == lb
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+    a.close(); b.close()
