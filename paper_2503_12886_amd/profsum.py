@@ -43,7 +43,7 @@ KERNEL_SOURCES = {
 
 def short_name(name: str) -> str:
     """Kernel symbol without namespace, template arguments or parameter list."""
-    n = name.split("(")[0]
+    n = name.replace("(anonymous namespace)::", "").split("(")[0]
     n = re.sub(r"<.*>", "", n)
     n = n.replace("void ", "").strip()
     return n.split("::")[-1]
