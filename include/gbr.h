@@ -145,10 +145,26 @@ int gbr_render_backward(gbr_ctx* ctx, const float* dimages, float* draw, void* s
 /* Adjoint of gbr_blend.  draw [B][N][16] -> dbases [(K+1)][N][16] (pads
    written 0) and dweights [B][K] (the contraction over N*16 runs on the
    matrix cores with per-wave partials summed in a fixed order);
-   accumulate != 0 adds into the outputs.  1 <= B <= 64, 0 <= K <= 63,
-   B * N within the context's max_splats (GBR_ERR_CAPACITY). */
+   accumulate != 0 adds into the outputs.  dbases may be NULL: then only
+   dweights is formed (for gbr_blend_adam_step, which forms dbases itself).
+   1 <= B <= 64, 0 <= K <= 63, B * N within the context's max_splats
+   (GBR_ERR_CAPACITY). */
 int gbr_blend_backward(gbr_ctx* ctx, const float* draw, const float* bases, const float* weights, int32_t B,
                        int32_t K, int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream);
+
+/* The Adam step of gbr_adam_step (Sec. A.3) on the bases [(K+1)][N][16],
+   with their gradient -- the dbases of gbr_blend_backward (Eq. 1's adjoint,
+   accumulate = 0) for the same draw and weights -- formed inside the update
+   and never stored: one pass over draw, bases, m and v instead of writing
+   dbases and reading it back.  The values equal gbr_blend_backward followed
+   by gbr_adam_step with split = N * 16 on the same table.  Call it after
+   every use of the old bases (gbr_blend_backward's dweights reads them).
+   group, lr_table, betas and eps as for gbr_adam_step (the update is
+   skipped on an overflowed pass); B, K, N limits as for
+   gbr_blend_backward.  Device pointers; bases, m, v updated in place. */
+int gbr_blend_adam_step(gbr_ctx* ctx, int32_t group, const float* draw, const float* weights, int32_t B, int32_t K,
+                        int64_t N, float* bases, float* m, float* v, const float* lr_table, float beta1, float beta2,
+                        float eps, void* stream);
 
 /* gbr_render_backward followed by gbr_blend_backward for a batch rendered
    from one blend (all frames share N = gauss_offsets[1]); draw lives in the

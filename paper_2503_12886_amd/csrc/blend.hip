@@ -73,18 +73,13 @@ void launch_blend_fwd(const float* bases, const float* weights, int B, int K, in
 // ---------------------------------------------------------------- adjoint: dbases
 // One thread per (Gaussian, feature): the frames' draw values are read once
 // per group of 16, every slice's sum is kept in a register and added over
-// the groups in frame order.
+// the groups in frame order.  dbases_element forms those sums; the plain
+// adjoint writes them, the fused step feeds them to Adam (so both see the
+// same gradient).  Every thread of the workgroup must call it (barriers).
 template <int KM>
-__global__ __launch_bounds__(kBlendThreads) void blend_dbases_kernel(const float* __restrict__ draw,
-                                                                      const float* __restrict__ weights, int B,
-                                                                      int K, int64_t N, float* __restrict__ dbases,
-                                                                      int accumulate) {
-  __shared__ float wt[KM][kFrameGroup];   // slice-major: a slice's 16 weights in 4 loads
-  const int64_t L = N * kNF;
-  const int64_t i = (int64_t)blockIdx.x * kBlendThreads + threadIdx.x;
-  const bool live = i < L;
-  const bool pad = (i % kNF) >= 14;
-  float acc[KM];
+__device__ __forceinline__ void dbases_element(const float* __restrict__ draw, const float* __restrict__ weights,
+                                               int B, int K, int64_t L, int64_t i, bool live,
+                                               float (&wt)[KM][kFrameGroup], float (&acc)[KM]) {
 #pragma unroll
   for (int k = 0; k < KM; ++k) acc[k] = 0.0f;
   for (int b0 = 0; b0 < B; b0 += kFrameGroup) {
@@ -113,6 +108,20 @@ __global__ __launch_bounds__(kBlendThreads) void blend_dbases_kernel(const float
       }
     }
   }
+}
+
+template <int KM>
+__global__ __launch_bounds__(kBlendThreads) void blend_dbases_kernel(const float* __restrict__ draw,
+                                                                      const float* __restrict__ weights, int B,
+                                                                      int K, int64_t N, float* __restrict__ dbases,
+                                                                      int accumulate) {
+  __shared__ float wt[KM][kFrameGroup];   // slice-major: a slice's 16 weights in 4 loads
+  const int64_t L = N * kNF;
+  const int64_t i = (int64_t)blockIdx.x * kBlendThreads + threadIdx.x;
+  const bool live = i < L;
+  const bool pad = (i % kNF) >= 14;
+  float acc[KM];
+  dbases_element<KM>(draw, weights, B, K, L, i, live, wt, acc);
   if (!live) return;
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
@@ -122,6 +131,54 @@ __global__ __launch_bounds__(kBlendThreads) void blend_dbases_kernel(const float
       *dst = accumulate ? *dst + v : v;
     }
   }
+}
+
+// The Adam step on the bases with the blend adjoint's dbases formed on the
+// fly: each thread's K+1 gradients go straight into the update of its
+// elements, so dbases is neither written nor read back.  Element k*L + i
+// takes the rate lr[(k > 0) * 16 + i % 16].  The whole grid returns on an
+// overflowed pass (the flag is uniform), before any barrier.
+template <int KM>
+__global__ __launch_bounds__(kBlendThreads) void blend_adam_kernel(const float* __restrict__ draw,
+                                                                    const float* __restrict__ weights, int B, int K,
+                                                                    int64_t N, float* __restrict__ p,
+                                                                    float* __restrict__ m, float* __restrict__ v,
+                                                                    const StatusDev* status, LrTable lr, float b1,
+                                                                    float b2, float eps) {
+  __shared__ float wt[KM][kFrameGroup];
+  if (status->overflow) return;
+  const int64_t L = N * kNF;
+  const int64_t i = (int64_t)blockIdx.x * kBlendThreads + threadIdx.x;
+  const bool live = i < L;
+  const bool pad = (i % kNF) >= 14;
+  float acc[KM];
+  dbases_element<KM>(draw, weights, B, K, L, i, live, wt, acc);
+  if (!live) return;
+  const float rc1 = 1.0f / status->adam_bc[0], rsc2 = 1.0f / sqrtf(status->adam_bc[1]);
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    if (k <= K) {
+      const int64_t e = (int64_t)k * L + i;
+      const float rate = lr.v[(k > 0 ? 16 : 0) + (int)(i & 15)];
+      adam_update(p[e], m[e], v[e], pad ? 0.0f : acc[k], rate, b1, b2, rc1, rsc2, eps);
+    }
+  }
+}
+
+void launch_blend_adam(const float* draw, const float* weights, int B, int K, int64_t N, float* p, float* m, float* v,
+                       StatusDev* status, int group, const float* lr_table_host, float b1, float b2, float eps,
+                       hipStream_t s) {
+  LrTable lr;
+  for (int i = 0; i < 32; ++i) lr.v[i] = lr_table_host[i];
+  launch_adam_tick(status, group, b1, b2, s);
+  if (N == 0 || B == 0) return;
+  const dim3 g1(div_up(N * kNF, kBlendThreads));
+  if (K + 1 <= 24)
+    hipLaunchKernelGGL(blend_adam_kernel<24>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, p, m, v, status,
+                       lr, b1, b2, eps);
+  else
+    hipLaunchKernelGGL(blend_adam_kernel<64>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, p, m, v, status,
+                       lr, b1, b2, eps);
 }
 
 // ---------------------------------------------------------------- adjoint: dweights
@@ -222,10 +279,10 @@ void launch_blend_bwd(const float* draw, const float* bases, const float* weight
                       hipStream_t s) {
   if (N == 0 || B == 0) return;
   const dim3 g1(div_up(N * kNF, kBlendThreads));
-  if (K + 1 <= 24)
+  if (dbases && K + 1 <= 24)
     hipLaunchKernelGGL(blend_dbases_kernel<24>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, dbases,
                        accumulate);
-  else
+  else if (dbases)
     hipLaunchKernelGGL(blend_dbases_kernel<64>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, dbases,
                        accumulate);
   if (K == 0) return;

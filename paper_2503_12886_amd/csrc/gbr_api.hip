@@ -598,7 +598,7 @@ int gbr_render_backward(gbr_ctx* c, const float* dimages, float* draw, void* str
 
 int gbr_blend_backward(gbr_ctx* c, const float* draw, const float* bases, const float* weights, int32_t B,
                        int32_t K, int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream) {
-  if (!c || !draw || !bases || !dbases || B < 1 || B > 64 || K < 0 || K > kMaxK || N < 1) return GBR_ERR_INVALID_ARG;
+  if (!c || !draw || !bases || B < 1 || B > 64 || K < 0 || K > kMaxK || N < 1) return GBR_ERR_INVALID_ARG;
   if (K > 0 && (!weights || !dweights)) return GBR_ERR_INVALID_ARG;
   if ((int64_t)B * N > c->cap_splats) return GBR_ERR_CAPACITY;
   if (blend_bwd_partials(B, K, N) > c->blend_part_n) return GBR_ERR_CAPACITY;
@@ -622,6 +622,25 @@ int gbr_backward(gbr_ctx* c, const float* dimages, const float* bases, const flo
   int rc = gbr_render_backward(c, dimages, c->draw_scratch, stream);
   if (rc) return rc;
   return gbr_blend_backward(c, c->draw_scratch, bases, weights, c->B, K, N, dbases, dweights, 0, stream);
+}
+
+int gbr_blend_adam_step(gbr_ctx* c, int32_t group, const float* draw, const float* weights, int32_t B, int32_t K,
+                        int64_t N, float* bases, float* m, float* v, const float* lr_table, float beta1, float beta2,
+                        float eps, void* stream) {
+  if (!c || group < 0 || group > 3 || !draw || !bases || !m || !v || !lr_table || B < 1 || B > 64 || K < 0 ||
+      K > kMaxK || N < 1 || (K > 0 && !weights))
+    return GBR_ERR_INVALID_ARG;
+  if ((int64_t)B * N > c->cap_splats) return GBR_ERR_CAPACITY;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f)) return GBR_ERR_INVALID_ARG;
+  for (int i = 0; i < 32; ++i)
+    if (!finite(lr_table[i])) return GBR_ERR_INVALID_ARG;
+  {
+    KTimer t(c, GBR_K_ADAM, (hipStream_t)stream);
+    launch_blend_adam(draw, weights, B, K, N, bases, m, v, c->d_status, group, lr_table, beta1, beta2, eps,
+                      (hipStream_t)stream);
+  }
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
 }
 
 int gbr_tangent_frames(gbr_ctx* c, const float* verts, const int32_t* faces, const float* face_uv, int32_t B,

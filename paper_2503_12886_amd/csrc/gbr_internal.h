@@ -279,6 +279,22 @@ void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, in
                     float* z1, float* z2, hipStream_t s);
 void launch_mlp_bwd(const float* params, const float* theta, const float* z1, const float* z2, const float* dpsi,
                     int B, int d_in, int hidden, int K, float* dz1, float* dz2, float* dparams, hipStream_t s);
+// Adam's update of one element (Sec. A.3), shared by the plain step and the
+// step fused with the blend adjoint so that both form the same values.
+// rc1 = 1 / (1 - b1^t), rsc2 = 1 / sqrt(1 - b2^t).
+struct LrTable { float v[32]; };
+__device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, float rate, float b1, float b2,
+                                            float rc1, float rsc2, float eps) {
+  const float mi = b1 * m + (1.0f - b1) * g;
+  const float vi = b2 * v + (1.0f - b2) * g * g;
+  m = mi;
+  v = vi;
+  p -= rate * (mi * rc1) / (sqrtf(vi) * rsc2 + eps);
+}
+void launch_adam_tick(StatusDev* status, int group, float b1, float b2, hipStream_t s);
+void launch_blend_adam(const float* draw, const float* weights, int B, int K, int64_t N, float* p, float* m, float* v,
+                       StatusDev* status, int group, const float* lr_table_host, float b1, float b2, float eps,
+                       hipStream_t s);
 void launch_adam(StatusDev* status, int group, float* p, const float* g, float* m, float* v, int64_t n,
                  int64_t split, const float* lr_table_host, float b1, float b2, float eps, hipStream_t s);
 }  // namespace gbr

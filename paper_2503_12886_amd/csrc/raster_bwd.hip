@@ -268,13 +268,18 @@ __global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __re
   if (!a.status->overflow && c > 0) {
     const uint32_t off = a.soff[s], end = off + c;
     const uint32_t* fw = reinterpret_cast<const uint32_t*>(a.part_flag);   // padded by 64 bytes past the capacity
-    // windows of 64 entries starting at a multiple of 4: the 16 flag words
-    // are read together and turned into a bit mask of the flagged entries,
-    // whose partials are then read 4 at a time (all 4 in flight together)
-    for (uint32_t e0 = off & ~3u; e0 < end; e0 += 64) {
+    // windows of 64 entries starting at a multiple of 16: the 16 flag words
+    // are read as four aligned 16-byte loads and turned into a bit mask of
+    // the flagged entries, whose partials are then read 4 at a time (all 4
+    // in flight together)
+    for (uint32_t e0 = off & ~15u; e0 < end; e0 += 64) {
       uint32_t w[16];
+      const uint4* fq = reinterpret_cast<const uint4*>(fw + (e0 >> 2));
 #pragma unroll
-      for (int k = 0; k < 16; ++k) w[k] = fw[(e0 >> 2) + k];
+      for (int k = 0; k < 4; ++k) {
+        const uint4 x = fq[k];
+        w[4 * k] = x.x; w[4 * k + 1] = x.y; w[4 * k + 2] = x.z; w[4 * k + 3] = x.w;
+      }
       unsigned long long m = 0ull;
 #pragma unroll
       for (int k = 0; k < 16; ++k) m |= (unsigned long long)flag_nibble(w[k]) << (4 * k);

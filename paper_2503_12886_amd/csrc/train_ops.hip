@@ -171,8 +171,6 @@ void launch_mlp_bwd(const float* params, const float* theta, const float* z1, co
 }
 
 // ---------------------------------------------------------------- Adam
-struct LrTable { float v[32]; };
-
 __global__ void adam_tick_kernel(StatusDev* status, int group, float b1, float b2, float* bc) {
   if (status->overflow) return;
   const int t = ++status->adam_step[group];
@@ -188,25 +186,24 @@ __global__ __launch_bounds__(256) void adam_kernel(const StatusDev* status, cons
   const float c1 = bc[0], c2 = bc[1];
   const float rc1 = 1.0f / c1, rsc2 = 1.0f / sqrtf(c2);
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
     const float rate = lr.v[(i >= split ? 16 : 0) + (int)(i & 15)];
-    p[i] -= rate * (mi * rc1) / (sqrtf(vi) * rsc2 + eps);
+    adam_update(p[i], m[i], v[i], g[i], rate, b1, b2, rc1, rsc2, eps);
   }
+}
+
+void launch_adam_tick(StatusDev* status, int group, float b1, float b2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_tick_kernel, dim3(1), dim3(1), 0, s, status, group, b1, b2, &status->adam_bc[0]);
 }
 
 void launch_adam(StatusDev* status, int group, float* p, const float* g, float* m, float* v, int64_t n,
                  int64_t split, const float* lr_table_host, float b1, float b2, float eps, hipStream_t s) {
   LrTable lr;
   for (int i = 0; i < 32; ++i) lr.v[i] = lr_table_host[i];
-  float* bc = &status->adam_bc[0];
-  hipLaunchKernelGGL(adam_tick_kernel, dim3(1), dim3(1), 0, s, status, group, b1, b2, bc);
+  launch_adam_tick(status, group, b1, b2, s);
   if (n == 0) return;
   const unsigned nb = (unsigned)std::min<int64_t>(div_up(n, 256), 8192);
-  hipLaunchKernelGGL(adam_kernel, dim3(nb), dim3(256), 0, s, status, bc, p, g, m, v, n, split, lr, b1, b2, eps);
+  hipLaunchKernelGGL(adam_kernel, dim3(nb), dim3(256), 0, s, status, &status->adam_bc[0], p, g, m, v, n, split, lr,
+                     b1, b2, eps);
 }
 
 }  // namespace gbr

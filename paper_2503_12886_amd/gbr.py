@@ -77,6 +77,8 @@ _SIGS = {
     "gbr_mlp_backward": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "gbr_adam_step": ([_vp, _i32, _vp, _vp, _vp, _vp, _i64, _i64, ctypes.POINTER(_f32), _f32, _f32, _f32, _vp],
                       ctypes.c_int),
+    "gbr_blend_adam_step": ([_vp, _i32, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _vp, ctypes.POINTER(_f32), _f32, _f32,
+                             _f32, _vp], ctypes.c_int),
     "gbr_query_status": ([_vp, _vp, ctypes.POINTER(gbr_status)], ctypes.c_int),
     "gbr_stage_frames": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(gbr_camera), _i32], ctypes.c_int),
     "gbr_graph_begin": ([_vp, _vp], ctypes.c_int),
@@ -274,19 +276,38 @@ def gbr_render_backward(ctx: Context, dimages, draw, stream=None) -> None:
 
 def gbr_blend_backward(ctx: Context, draw, bases, weights, dbases, dweights, accumulate: bool = False,
                        stream=None) -> None:
+    """dbases may be None: only dweights is formed."""
     K1, N, _ = bases.shape
     K = K1 - 1
     B = draw.shape[0]
     _check(lib().gbr_blend_backward(ctx.handle, _f32dev(draw, "draw"), _f32dev(bases, "bases"),
                                     _f32dev(weights, "weights") if K > 0 else None, B, K, N,
-                                    _f32dev(dbases, "dbases"), _f32dev(dweights, "dweights") if K > 0 else None,
+                                    _f32dev(dbases, "dbases") if dbases is not None else None,
+                                    _f32dev(dweights, "dweights") if K > 0 else None,
                                     int(bool(accumulate)), _stream(stream)), "gbr_blend_backward")
+
+
+def gbr_blend_adam_step(ctx: Context, group: int, draw, weights, bases, m, v, lr_table: Sequence[float],
+                        beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, stream=None) -> None:
+    """Adam on bases [(K+1)][N][16] with the blend adjoint of draw [B][N][16] as the gradient."""
+    K1, N, _ = bases.shape
+    K = K1 - 1
+    B = draw.shape[0]
+    for t, nm in ((m, "m"), (v, "v")):
+        if t.numel() != bases.numel():
+            raise ValueError(f"gbr_blend_adam_step: {nm} size mismatch")
+    tab = (_f32 * 32)(*[float(x) for x in lr_table])
+    _check(lib().gbr_blend_adam_step(ctx.handle, int(group), _f32dev(draw, "draw"),
+                                     _f32dev(weights, "weights") if K > 0 else None, B, K, N,
+                                     _f32dev(bases, "bases"), _f32dev(m, "m"), _f32dev(v, "v"), tab, beta1, beta2,
+                                     eps, _stream(stream)), "gbr_blend_adam_step")
 
 
 def gbr_backward(ctx: Context, dimages, bases, weights, dbases, dweights, stream=None) -> None:
     K = bases.shape[0] - 1
     _check(lib().gbr_backward(ctx.handle, _f32dev(dimages, "dimages"), _f32dev(bases, "bases"),
-                              _f32dev(weights, "weights") if K > 0 else None, K, _f32dev(dbases, "dbases"),
+                              _f32dev(weights, "weights") if K > 0 else None, K,
+                              _f32dev(dbases, "dbases") if dbases is not None else None,
                               _f32dev(dweights, "dweights") if K > 0 else None, _stream(stream)), "gbr_backward")
 
 

@@ -66,6 +66,7 @@ class StepConfig:
     tile: int = 16
     chunk: int = 64
     paper_mask: bool = False  # scale and opacity not blended (their deltas held at zero)
+    fused_adam: bool = True   # the bases' Adam step forms dbases itself (gbr_blend_adam_step)
 
 
 def mlp_numel(d_in: int, hidden: int, K: int) -> int:
@@ -97,6 +98,7 @@ class Trainer:
         self.psi = torch.zeros(B, K, **f32)
         self.dpsi = torch.zeros(B, K, **f32)
         self.raw = torch.zeros(B, N, 16, **f32)
+        self.draw = torch.zeros(B, N, 16, **f32)
         npix = cfg.width * cfg.height
         self.images = torch.zeros(B * 3 * npix, **f32)
         self.dimages = torch.zeros_like(self.images)
@@ -213,25 +215,35 @@ class Trainer:
         gbr.gbr_tangent_transform(c, self.raw, self.tri, self.bary, self.verts, self.faces, self.frames, self.raw_d)
         return self.raw_d
 
-    def _enqueue_grads(self) -> None:
+    def _enqueue_grads(self, fused: bool = False):
+        """Forward, loss and backward. With fused, dbases is left to the
+        update (gbr_blend_adam_step); returns the draw that update needs."""
         c, cfg = self.ctx, self.cfg
         gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
         gbr.gbr_blend(c, self.bases, self.psi, self.raw)
         gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.images)
         gbr.gbr_loss(c, self.images, self.targets, cfg.loss, self.dimages)
+        dbases = None if fused else self.dbases
         if getattr(self, "verts", None) is None:
-            gbr.gbr_backward(c, self.dimages, self.bases, self.psi, self.dbases, self.dpsi)
+            gbr.gbr_render_backward(c, self.dimages, self.draw)
+            draw = self.draw
         else:
             gbr.gbr_render_backward(c, self.dimages, self.draw_d)
             gbr.gbr_tangent_backward(c, self.draw_d, self.tri, self.frames, self.draw_t)
-            gbr.gbr_blend_backward(c, self.draw_t, self.bases, self.psi, self.dbases, self.dpsi)
+            draw = self.draw_t
+        gbr.gbr_blend_backward(c, draw, self.bases, self.psi, dbases, self.dpsi)
         gbr.gbr_mlp_backward(c, self.mlp, self.dpsi, self.dmlp)
+        return draw
 
     def _enqueue_step(self) -> None:
         c, cfg = self.ctx, self.cfg
-        self._enqueue_grads()
-        gbr.gbr_adam_step(c, 0, self.bases, self.dbases, self.bases_m, self.bases_v, cfg.N * 16, self.lr_bases,
-                          ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+        draw = self._enqueue_grads(cfg.fused_adam)
+        if cfg.fused_adam:
+            gbr.gbr_blend_adam_step(c, 0, draw, self.psi, self.bases, self.bases_m, self.bases_v, self.lr_bases,
+                                    ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
+        else:
+            gbr.gbr_adam_step(c, 0, self.bases, self.dbases, self.bases_m, self.bases_v, cfg.N * 16, self.lr_bases,
+                              ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
         gbr.gbr_adam_step(c, 1, self.mlp, self.dmlp, self.mlp_m, self.mlp_v, self.mlp.numel(), self.lr_mlp,
                           ADAM_BETAS[0], ADAM_BETAS[1], ADAM_EPS)
 

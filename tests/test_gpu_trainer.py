@@ -209,3 +209,29 @@ def test_kernel_timing_brackets_count_graph_replays():
     for x, y in zip(state(a), state(b)):
         assert np.array_equal(x, y)
     a.close(); b.close()
+
+
+@pytest.mark.parametrize("K,paper_mask", [(8, False), (30, True)])
+def test_fused_blend_adam_equals_separate_steps(K, paper_mask):
+    """The bases' Adam step with the blend adjoint formed inside it
+    (gbr_blend_adam_step) leaves every parameter and moment bit for bit where
+    the blend adjoint followed by the plain Adam step does, over several
+    steps, eagerly and replayed (K = 30 takes the wider slice template)."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=6, K=K)
+    cfg.paper_mask = paper_mask
+    cfg_sep = StepConfig(**{**cfg.__dict__, "fused_adam": False})
+    a = Trainer(cfg, bases, mlp)
+    b = Trainer(cfg_sep, bases, mlp)
+    for tr in (a, b):
+        tr.set_batch(theta, targets, cams)
+    la = [a.step().loss for _ in range(2)]
+    lb = [b.step().loss for _ in range(2)]
+    a.capture(); b.capture()
+    la += [a.step().loss for _ in range(3)]
+    lb += [b.step().loss for _ in range(3)]
+    assert la == lb
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+    sa, sb = a.step(), b.step()
+    assert sa.adam_steps[0] == sb.adam_steps[0] == 6
+    a.close(); b.close()
