@@ -244,6 +244,16 @@ int gbr_adam_step(gbr_ctx* ctx, int32_t group, float* params, const float* grads
    device status (entries, overflow flag, Adam step counters, loss). */
 int gbr_query_status(gbr_ctx* ctx, void* stream, gbr_status* out);
 
+/* The same read split in two, so that the host can enqueue the next step
+   before it waits for this one's status.  gbr_status_post enqueues on
+   `stream` a copy of the device status (as it stands when the stream
+   reaches the copy) into host slot `slot` (0..3) and records that slot's
+   event; it first waits for the slot's previous copy, if any.
+   gbr_status_wait waits for the slot's event and reads the copy
+   (GBR_ERR_STATE if nothing was posted to it).  Not during capture. */
+int gbr_status_post(gbr_ctx* ctx, void* stream, int32_t slot);
+int gbr_status_wait(gbr_ctx* ctx, int32_t slot, gbr_status* out);
+
 /* Re-stage the per-frame table (cameras, Gaussian offsets) of the last
    render without enqueueing work, so that a graph captured around gbr_render
    replays with new cameras.  B and every frame's size must match the

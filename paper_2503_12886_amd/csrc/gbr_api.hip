@@ -53,6 +53,8 @@ __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u
 
 }  // namespace
 
+constexpr int kStatusSlots = 4;   // status records in flight (gbr_status_post / gbr_status_wait)
+
 struct gbr_ctx {
   gbr_config cfg;
   int tile = 16, chunk = 64;
@@ -99,7 +101,9 @@ struct gbr_ctx {
   hipEvent_t slot_ev[kSlots] = {};
   bool slot_used[kSlots] = {};
   int next_slot = 0;
-  StatusDev* h_status = nullptr;   // pinned
+  StatusDev* h_status = nullptr;   // pinned, [1 + kStatusSlots]: gbr_query_status's record, then the posted slots
+  hipEvent_t status_ev[kStatusSlots] = {};
+  bool status_posted[kStatusSlots] = {};
   // pass state
   bool capturing = false;
   bool have_pre = false, have_raster = false;
@@ -238,6 +242,8 @@ void free_all(gbr_ctx* c) {
   c->h_frames = nullptr; c->h_status = nullptr;
   for (int i = 0; i < kSlots; ++i)
     if (c->slot_ev[i]) (void)hipEventDestroy(c->slot_ev[i]);
+  for (int i = 0; i < kStatusSlots; ++i)
+    if (c->status_ev[i]) (void)hipEventDestroy(c->status_ev[i]);
   for (int k = 0; k < GBR_K_COUNT; ++k)
     for (int j = 0; j < 2; ++j)
       if (c->t_ev[k][j]) (void)hipEventDestroy(c->t_ev[k][j]);
@@ -488,10 +494,13 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(alloc_entries(c, cfg->max_entries));
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_frames), sizeof(FrameDev) * kSlots * c->cap_frames,
                     hipHostMallocDefault) != hipSuccess) TRY(GBR_ERR_OOM);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(StatusDev), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(StatusDev) * (1 + kStatusSlots),
+                    hipHostMallocDefault) != hipSuccess)
     TRY(GBR_ERR_OOM);
   for (int i = 0; i < kSlots; ++i)
     if (hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming) != hipSuccess) TRY(GBR_ERR_HIP);
+  for (int i = 0; i < kStatusSlots; ++i)
+    if (hipEventCreateWithFlags(&c->status_ev[i], hipEventDisableTiming) != hipSuccess) TRY(GBR_ERR_HIP);
   StatusDev zero;
   std::memset(&zero, 0, sizeof(zero));
   if (hipMemcpy(c->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) TRY(GBR_ERR_HIP);
@@ -750,18 +759,41 @@ int gbr_adam_step(gbr_ctx* c, int32_t group, float* params, const float* grads, 
   return GBR_OK;
 }
 
+static void fill_status(const gbr_ctx* c, const StatusDev& h, gbr_status* out) {
+  out->entries = (int64_t)h.entries;
+  out->entries_capacity = c->cap_entries;
+  out->overflow = (int32_t)h.overflow;
+  for (int i = 0; i < 4; ++i) out->adam_steps[i] = h.adam_step[i];
+  out->loss = h.loss;
+}
+
 int gbr_query_status(gbr_ctx* c, void* stream, gbr_status* out) {
   if (!c || !out) return GBR_ERR_INVALID_ARG;
   if (c->capturing) return GBR_ERR_STATE;
   hipStream_t s = (hipStream_t)stream;
   GBR_HIP(hipMemcpyAsync(c->h_status, c->d_status, sizeof(StatusDev), hipMemcpyDeviceToHost, s));
   GBR_HIP(hipStreamSynchronize(s));
-  const StatusDev& h = *c->h_status;
-  out->entries = (int64_t)h.entries;
-  out->entries_capacity = c->cap_entries;
-  out->overflow = (int32_t)h.overflow;
-  for (int i = 0; i < 4; ++i) out->adam_steps[i] = h.adam_step[i];
-  out->loss = h.loss;
+  fill_status(c, *c->h_status, out);
+  return GBR_OK;
+}
+
+int gbr_status_post(gbr_ctx* c, void* stream, int32_t slot) {
+  if (!c || slot < 0 || slot >= kStatusSlots) return GBR_ERR_INVALID_ARG;
+  if (c->capturing) return GBR_ERR_STATE;
+  hipStream_t s = (hipStream_t)stream;
+  // the slot's previous copy must have landed before it is overwritten
+  if (c->status_posted[slot]) GBR_HIP(hipEventSynchronize(c->status_ev[slot]));
+  GBR_HIP(hipMemcpyAsync(c->h_status + 1 + slot, c->d_status, sizeof(StatusDev), hipMemcpyDeviceToHost, s));
+  GBR_HIP(hipEventRecord(c->status_ev[slot], s));
+  c->status_posted[slot] = true;
+  return GBR_OK;
+}
+
+int gbr_status_wait(gbr_ctx* c, int32_t slot, gbr_status* out) {
+  if (!c || !out || slot < 0 || slot >= kStatusSlots) return GBR_ERR_INVALID_ARG;
+  if (!c->status_posted[slot]) return GBR_ERR_STATE;
+  GBR_HIP(hipEventSynchronize(c->status_ev[slot]));
+  fill_status(c, c->h_status[1 + slot], out);
   return GBR_OK;
 }
 

@@ -262,6 +262,43 @@ class Trainer:
             self._grow(st.entries)
         raise RuntimeError("tile-entry overflow persists after growing the capacity")
 
+    def run_steps(self, n: int, depth: int = 2) -> gbr.gbr_status:
+        """n steps on the current batch from the captured graph, each replay
+        enqueued before the host waits for the status of the step before it:
+        still one status read per step, but the GPU does not idle while the
+        host reads it and launches the next replay. A step that overflowed
+        updated nothing: the steps in flight are drained, the capacity grows,
+        the graph is captured again and the missing steps run. Returns the
+        last step's status."""
+        assert self.graph is not None, "capture the step first"
+        assert 1 <= depth <= 4
+        done, inflight, k, retries = 0, [], 0, 0
+        last = None
+        while done < n:
+            while len(inflight) < depth and done + len(inflight) < n:
+                gbr.gbr_graph_launch(self.graph, self.stream)
+                gbr.gbr_status_post(self.ctx, k % 4, self.stream)
+                inflight.append(k % 4)
+                k += 1
+                self.steps_launched += 1
+            st = gbr.gbr_status_wait(self.ctx, inflight.pop(0))
+            if not st.overflow:
+                done, last, retries = done + 1, st, 0
+                continue
+            need = st.entries
+            for slot in inflight:                 # drain the replays in flight
+                s2 = gbr.gbr_status_wait(self.ctx, slot)
+                if s2.overflow:
+                    need = max(need, s2.entries)
+                else:
+                    done, last = done + 1, s2
+            inflight = []
+            retries += 1
+            if retries > 3:
+                raise RuntimeError("tile-entry overflow persists after growing the capacity")
+            self._grow(need)
+        return last
+
     def _grow(self, entries: int) -> None:
         gbr.gbr_reserve(self.ctx, entries + entries // 4 + 4096)
         if self.graph is not None:      # buffers moved: capture again

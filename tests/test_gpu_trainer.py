@@ -235,3 +235,32 @@ def test_fused_blend_adam_equals_separate_steps(K, paper_mask):
     sa, sb = a.step(), b.step()
     assert sa.adam_steps[0] == sb.adam_steps[0] == 6
     a.close(); b.close()
+
+
+def test_pipelined_steps_equal_one_by_one_and_recover_from_overflow():
+    """run_steps enqueues each replay before reading the previous step's
+    status: the same updates as one step at a time; with a capacity too
+    small for the batch, the overflowed replays update nothing and are run
+    again after the capacity grows."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=7)
+    a = Trainer(cfg, bases, mlp, max_entries=2000)
+    b = Trainer(cfg, bases, mlp)
+    for tr in (a, b):
+        tr.set_batch(theta, targets, cams)
+    a.enqueue_step()                    # sizes the other buffers; the entries overflow, nothing updates
+    assert gbr.gbr_query_status(a.ctx, a.stream).overflow
+    a.capture()                         # captured at the small capacity: its replays overflow
+    st = a.run_steps(4)
+    assert not st.overflow and st.entries > 2000 and st.adam_steps[0] == 4
+    b.step()
+    b.capture()
+    lb = [b.step().loss for _ in range(3)]
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+    assert st.loss == lb[-1]
+    st2 = a.run_steps(3, depth=3)
+    lb += [b.step().loss for _ in range(3)]
+    assert st2.adam_steps[0] == 7 and st2.loss == lb[-1]
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+    a.close(); b.close()
