@@ -143,8 +143,8 @@ __global__ __launch_bounds__(kBlendThreads) void blend_adam_kernel(const float* 
                                                                     const float* __restrict__ weights, int B, int K,
                                                                     int64_t N, float* __restrict__ p,
                                                                     float* __restrict__ m, float* __restrict__ v,
-                                                                    const StatusDev* status, LrTable lr, float b1,
-                                                                    float b2, float eps) {
+                                                                    const StatusDev* status, int group, LrTable lr,
+                                                                    float b1, float b2, float eps) {
   __shared__ float wt[KM][kFrameGroup];
   if (status->overflow) return;
   const int64_t L = N * kNF;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlendThreads) void blend_adam_kernel(const float* 
   float acc[KM];
   dbases_element<KM>(draw, weights, B, K, L, i, live, wt, acc);
   if (!live) return;
-  const float rc1 = 1.0f / status->adam_bc[0], rsc2 = 1.0f / sqrtf(status->adam_bc[1]);
+  const float rc1 = 1.0f / status->adam_bc[group][0], rsc2 = 1.0f / sqrtf(status->adam_bc[group][1]);
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
     if (k <= K) {
@@ -175,10 +175,10 @@ void launch_blend_adam(const float* draw, const float* weights, int B, int K, in
   const dim3 g1(div_up(N * kNF, kBlendThreads));
   if (K + 1 <= 24)
     hipLaunchKernelGGL(blend_adam_kernel<24>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, p, m, v, status,
-                       lr, b1, b2, eps);
+                       group, lr, b1, b2, eps);
   else
     hipLaunchKernelGGL(blend_adam_kernel<64>, g1, dim3(kBlendThreads), 0, s, draw, weights, B, K, N, p, m, v, status,
-                       lr, b1, b2, eps);
+                       group, lr, b1, b2, eps);
 }
 
 // ---------------------------------------------------------------- adjoint: dweights

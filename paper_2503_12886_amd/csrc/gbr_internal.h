@@ -43,7 +43,7 @@ struct StatusDev {
   unsigned int pad0;
   int32_t adam_step[4];
   float loss;
-  float adam_bc[2];        // bias corrections 1 - beta^t of the last Adam step
+  float adam_bc[4][2];     // per group: bias corrections 1 - beta^t of its last Adam step
   float pad1;
 };
 

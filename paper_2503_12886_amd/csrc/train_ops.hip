@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void adam_kernel(const StatusDev* status, cons
 }
 
 void launch_adam_tick(StatusDev* status, int group, float b1, float b2, hipStream_t s) {
-  hipLaunchKernelGGL(adam_tick_kernel, dim3(1), dim3(1), 0, s, status, group, b1, b2, &status->adam_bc[0]);
+  hipLaunchKernelGGL(adam_tick_kernel, dim3(1), dim3(1), 0, s, status, group, b1, b2, &status->adam_bc[group][0]);
 }
 
 void launch_adam(StatusDev* status, int group, float* p, const float* g, float* m, float* v, int64_t n,
@@ -202,7 +202,7 @@ void launch_adam(StatusDev* status, int group, float* p, const float* g, float* 
   launch_adam_tick(status, group, b1, b2, s);
   if (n == 0) return;
   const unsigned nb = (unsigned)std::min<int64_t>(div_up(n, 256), 8192);
-  hipLaunchKernelGGL(adam_kernel, dim3(nb), dim3(256), 0, s, status, &status->adam_bc[0], p, g, m, v, n, split, lr,
+  hipLaunchKernelGGL(adam_kernel, dim3(nb), dim3(256), 0, s, status, &status->adam_bc[group][0], p, g, m, v, n, split, lr,
                      b1, b2, eps);
 }
 
