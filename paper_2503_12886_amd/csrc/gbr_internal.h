@@ -171,14 +171,27 @@ __device__ __forceinline__ int tile_of_rank(const uint32_t* cnt, const uint32_t*
   return -1;
 }
 
-// Sum over the 16 lanes of each row; each row's total lands in its lane 15
-// (lanes 15, 31, 47, 63).  Out-of-row sources read zero.
-__device__ __forceinline__ float row_sum_to15(float v) {
-  v += dpp_mov<0x111, 0xf, 0xf, true>(v);   // row_shr:1
-  v += dpp_mov<0x112, 0xf, 0xf, true>(v);   // row_shr:2
-  v += dpp_mov<0x114, 0xf, 0xf, true>(v);   // row_shr:4
-  v += dpp_mov<0x118, 0xf, 0xf, true>(v);   // row_shr:8
-  return v;
+// Sums over the 16 lanes of each row of 9 values; each row's totals land in
+// its lane 15 (lanes 15, 31, 47, 63).  Three shifts (out-of-row sources read
+// zero), then a rotation by 8: lane 15 reads lane 7, as a shift would.  The
+// last level is written as DPP adds in inline assembly (the compiler sinks
+// that level's adds into the lane-15 branch and would keep a separate DPP
+// move per value), after the two wait states that a DPP read of a VALU
+// result needs.
+__device__ __forceinline__ void row_sum9_to15(float* x) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    x[c] += dpp_mov<0x111, 0xf, 0xf, true>(x[c]);   // row_shr:1
+    x[c] += dpp_mov<0x112, 0xf, 0xf, true>(x[c]);   // row_shr:2
+    x[c] += dpp_mov<0x114, 0xf, 0xf, true>(x[c]);   // row_shr:4
+  }
+#define GBR_ROR8_ADD(i) "v_add_f32_dpp %" #i ", %" #i ", %" #i " row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
+  asm volatile("s_nop 1\n\t"
+               GBR_ROR8_ADD(0) GBR_ROR8_ADD(1) GBR_ROR8_ADD(2) GBR_ROR8_ADD(3) GBR_ROR8_ADD(4)
+               GBR_ROR8_ADD(5) GBR_ROR8_ADD(6) GBR_ROR8_ADD(7) GBR_ROR8_ADD(8)
+               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
+                 "+v"(x[8]));
+#undef GBR_ROR8_ADD
 }
 
 // Lane swaps of gfx950: after swap32(x, y), x holds (x lanes 0-31, y lanes

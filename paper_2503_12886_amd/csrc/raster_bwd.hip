@@ -10,6 +10,9 @@ template <int T> using TileShapeB = TileMap<T>;
 
 // Must stay bit-identical to the forward kernel's alpha: power = ca dx^2 +
 // cb dx dy + cc dy^2 + lo (lo = log2 opacity), alpha = 2^min(power, lo).
+// The clamp is one v_min_f32 (min(power, lo) for every non-NaN power);
+// written as such because fminf would first canonicalise lo, one more
+// instruction per (entry, pixel).
 __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, float py, float& dx, float& dy,
                                                float& pw_raw) {
 #pragma clang fp contract(off)
@@ -19,7 +22,9 @@ __device__ __forceinline__ float splat_alpha_b(float4 r0, float4 r1, float px, f
   pw = __builtin_fmaf(r0.w * dx, dy, pw);
   pw = __builtin_fmaf(r1.x * dy, dy, pw);
   pw_raw = pw;
-  return __builtin_amdgcn_exp2f(fminf(pw, r1.y));
+  float pc;
+  asm("v_min_f32 %0, %1, %2" : "=v"(pc) : "v"(pw), "v"(r1.y));
+  return __builtin_amdgcn_exp2f(pc);
 }
 
 // Per-entry partial, summed over the tile's pixels, in units of t = alpha *
@@ -84,7 +89,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   constexpr int U = 4;                      // entries folded per step (independent alphas)
   __shared__ float4 s0[CHUNK];
   __shared__ float4 s1[CHUNK];
-  __shared__ float s2[CHUNK];
+  __shared__ float4 s2[CHUNK];             // .x only: 16-byte slots share the LDS address of s0 and s1
   __shared__ float red[CHUNK][S::NW][9];
   __shared__ uint32_t wany[CHUNK];         // byte w: wave w wrote red[i][w]
   __shared__ uint32_t cm[CHUNK];          // byte w: quadrant w took the entry
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     for (int i = threadIdx.x; i < n; i += S::NT) {
       const uint32_t sp = a.sorted[start + cbeg + i];
       const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
-      s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = rec[2].x;
+      s0[i] = rec[0]; s1[i] = rec[1]; s2[i] = make_float4(rec[2].x, 0.0f, 0.0f, 0.0f);
       cm[i] = reinterpret_cast<const uint32_t*>(a.cmask)[start + cbeg + i];
       sid[i] = sp;
       wany[i] = 0u;
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
           // an absent entry is folded as an untaken one (zeros, state kept)
           const int i = e[u] < 0 ? e[0] : e[u];
           const uint32_t li = e[u] < 0 ? 0xffffffffu : (uint32_t)(cbeg + i);
-          entry_grad<S::PX>(s0[i], s1[i], s2[i], li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc[u], any[u]);
+          entry_grad<S::PX>(s0[i], s1[i], s2[i].x, li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc[u], any[u]);
           who[u] = __ballot(any[u]);
         }
         // Sums of the 4 x 9 partials over the wave's 64 lanes, in a fixed
@@ -173,8 +178,7 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
         fold32x9(acc[0], acc[1]);
         fold32x9(acc[2], acc[3]);
         fold16x9(acc[0], acc[2]);
-#pragma unroll
-        for (int c = 0; c < 9; ++c) acc[0][c] = row_sum_to15(acc[0][c]);
+        row_sum9_to15(acc[0]);
         if ((lane & 15) == 15) {
           const int r = lane >> 4, u = (r >> 1) | ((r & 1) << 1);
           const int eu = u == 0 ? e[0] : u == 1 ? e[1] : u == 2 ? e[2] : e[3];

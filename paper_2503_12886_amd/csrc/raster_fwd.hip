@@ -504,6 +504,9 @@ __device__ __forceinline__ bool strip_reach(float4 r0, float4 r1, float x0, floa
 // alpha of a splat at a pixel, bit-identical wherever it is evaluated:
 // power = ca dx^2 + cb dx dy + cc dy^2 (= -q/2 in log2 units) plus lo =
 // log2(opacity), clamped at lo (q >= 0), and alpha = 2^power = o 2^(-q/2 log2 e).
+// The clamp is one v_min_f32 (min(power, lo) for every non-NaN power);
+// written as such because fminf would first canonicalise lo, one more
+// instruction per (entry, pixel).
 __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, float py, float& dx, float& dy,
                                              float& pw_raw) {
 #pragma clang fp contract(off)
@@ -513,7 +516,9 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
   pw = __builtin_fmaf(r0.w * dx, dy, pw);
   pw = __builtin_fmaf(r1.x * dy, dy, pw);
   pw_raw = pw;
-  return __builtin_amdgcn_exp2f(fminf(pw, r1.y));
+  float pc;
+  asm("v_min_f32 %0, %1, %2" : "=v"(pc) : "v"(pw), "v"(r1.y));
+  return __builtin_amdgcn_exp2f(pc);
 }
 
 // A staged splat record: mean, log2-scaled conic, log2 opacity, colour.
