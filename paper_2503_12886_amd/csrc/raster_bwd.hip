@@ -49,25 +49,25 @@ template <int PX>
 __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, const float cbl, const uint32_t li,
                                            const float* pxf, const float* pyf, const uint32_t* nit, float* T_,
                                            float* SG, const float* G0, const float* G1, const float* G2,
-                                           float* acc, bool& any) {
+                                           float* acc) {
 #pragma unroll
   for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-  any = false;
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
     float dx, dy, pwr;
     const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr);
     const bool take = li < nit[p] && a0 >= kAlphaMin;
-    any = any || take;
-    const float al = fminf(a0, kAlphaMax);
+    // an untaken entry folds with alpha 0: 1/(1 - 0) = 1 exactly, so the
+    // transmittance passes through unchanged and the weight is 0
+    const float al = take ? fminf(a0, kAlphaMax) : 0.0f;
     const float inv = __builtin_amdgcn_rcpf(1.0f - al);
     const float Ti = T_[p] * inv;                     // transmittance in front of this entry
-    const float wgt = take ? al * Ti : 0.0f;
+    const float wgt = al * Ti;
     acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
     const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];   // <colour, dL/dout>
     const float dal = Ti * cg - SG[p] * inv;          // d out / d alpha
     SG[p] += wgt * cg;                                // <colour behind, dL/dout>
-    T_[p] = take ? Ti : T_[p];
+    T_[p] = Ti;
     // min(0.99, .) passes the gradient only below the clamp
     const float t = (take && a0 < kAlphaMax) ? a0 * dal : 0.0f;
     acc[5] += t;
@@ -85,6 +85,7 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
+  static_assert(CHUNK <= 256, "a group's chunk positions are packed one byte each");
   using S = TileShapeB<T>;
   constexpr int U = 4;                      // entries folded per step (independent alphas)
   __shared__ float4 s0[CHUNK];
@@ -142,7 +143,10 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     }
     __syncthreads();
     // Entries this wave's pixels took in the forward pass (its contribution
-    // mask bit), visited back to front in pairs.
+    // mask bit), visited back to front in groups of 4.  A pixel takes an
+    // entry here exactly when it took it in the forward pass (the same alpha
+    // bits, the same stop position), so every visited entry has a
+    // contributing pixel in the wave and its partial is written unchecked.
     for (int gb = (n - 1) & ~63; gb >= 0; gb -= 64) {
       const int idx = gb + lane;
       unsigned long long m = __ballot(idx < n && (uint32_t)(cbeg + idx) < Lw && ((cm[idx] >> (8 * w)) & 1u));
@@ -160,15 +164,12 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
           }
         }
         float acc[U][9];
-        bool any[U];
-        unsigned long long who[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           // an absent entry is folded as an untaken one (zeros, state kept)
           const int i = e[u] < 0 ? e[0] : e[u];
           const uint32_t li = e[u] < 0 ? 0xffffffffu : (uint32_t)(cbeg + i);
-          entry_grad<S::PX>(s0[i], s1[i], s2[i].x, li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc[u], any[u]);
-          who[u] = __ballot(any[u]);
+          entry_grad<S::PX>(s0[i], s1[i], s2[i].x, li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc[u]);
         }
         // Sums of the 4 x 9 partials over the wave's 64 lanes, in a fixed
         // order: fold lanes 32 apart (entries 0|1 and 2|3 into one register
@@ -179,11 +180,14 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
         fold32x9(acc[2], acc[3]);
         fold16x9(acc[0], acc[2]);
         row_sum9_to15(acc[0]);
+        // the group's chunk positions (< CHUNK <= 256), one byte each, so that
+        // a row's leader picks its entry with one shift
+        const uint32_t epack = (uint32_t)(e[0] & 0xff) | ((uint32_t)(e[1] & 0xff) << 8) |
+                               ((uint32_t)(e[2] & 0xff) << 16) | ((uint32_t)(e[3] & 0xff) << 24);
         if ((lane & 15) == 15) {
           const int r = lane >> 4, u = (r >> 1) | ((r & 1) << 1);
-          const int eu = u == 0 ? e[0] : u == 1 ? e[1] : u == 2 ? e[2] : e[3];
-          const unsigned long long wu = u == 0 ? who[0] : u == 1 ? who[1] : u == 2 ? who[2] : who[3];
-          if (u < cnt && wu != 0ull) {
+          const int eu = (int)((epack >> (8 * u)) & 0xffu);
+          if (u < cnt) {
 #pragma unroll
             for (int c = 0; c < 9; ++c) red[eu][w][c] = acc[0][c];
             wany8[eu * 4 + w] = 1;
