@@ -51,8 +51,6 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
                                            float* SG, const float* G0, const float* G1, const float* G2,
                                            float* acc) {
 #pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-#pragma unroll
   for (int p = 0; p < PX; ++p) {
     float dx, dy, pwr;
     const float a0 = splat_alpha_b(r0, r1, pxf[p], pyf[p], dx, dy, pwr);
@@ -63,22 +61,19 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
     const float inv = __builtin_amdgcn_rcpf(1.0f - al);
     const float Ti = T_[p] * inv;                     // transmittance in front of this entry
     const float wgt = al * Ti;
-    acc[6] += wgt * G0[p]; acc[7] += wgt * G1[p]; acc[8] += wgt * G2[p];
     const float cg = r1.z * G0[p] + r1.w * G1[p] + cbl * G2[p];   // <colour, dL/dout>
     const float dal = Ti * cg - SG[p] * inv;          // d out / d alpha
     SG[p] += wgt * cg;                                // <colour behind, dL/dout>
     T_[p] = Ti;
     // min(0.99, .) passes the gradient only below the clamp
     const float t = (take && a0 < kAlphaMax) ? a0 * dal : 0.0f;
-    acc[5] += t;
     // power clamped at log2 o (q < 0 by rounding): no gradient to the conic or mean
     const float tq = (pwr > r1.y) ? 0.0f : t;
     const float p1 = tq * dx, p2 = tq * dy;
-    acc[0] += p1;
-    acc[1] += p2;
-    acc[2] += p1 * dx;
-    acc[3] += p1 * dy;
-    acc[4] += p2 * dy;
+    const float v[9] = {p1, p2, p1 * dx, p1 * dy, p2 * dy, t, wgt * G0[p], wgt * G1[p], wgt * G2[p]};
+    // the first pixel assigns (adding it to 0 would cost an instruction per value)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = (p == 0) ? v[c] : acc[c] + v[c];
   }
 }
 
@@ -199,9 +194,9 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
     for (int i = threadIdx.x; i < n; i += S::NT) {
       const uint32_t wa = wany[i];
       if (wa == 0u) continue;
-      float v[9];
+      float v[9];   // -0 + x is x for every x, so the first wave's add folds away
 #pragma unroll
-      for (int c = 0; c < 9; ++c) v[c] = 0.0f;
+      for (int c = 0; c < 9; ++c) v[c] = -0.0f;
 #pragma unroll
       for (int ww = 0; ww < S::NW; ++ww) {
         if (!((wa >> (8 * ww)) & 0xffu)) continue;
