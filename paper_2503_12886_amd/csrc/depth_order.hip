@@ -87,11 +87,6 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs
   }
 }
 
-// bkt_start[i] = start of bucket i (frame-major) = the scanned matrix at block 0.
-__global__ void bucket_starts_kernel(PassArgs a, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i <= n) a.bkt_start[i] = a.bkt_moff[i * a.nblk];
-}
 
 __device__ __forceinline__ void emit_ranked(const PassArgs& a, unsigned long long key, uint32_t pos, uint32_t vbase) {
   const uint32_t s = (uint32_t)key;
@@ -219,8 +214,8 @@ void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* s
   const dim3 grid(a.nblk, a.B);
   const int64_t nb = (int64_t)a.B * a.nbk;
   hipLaunchKernelGGL(bucket_count_kernel, grid, dim3(kBucketThreads), 0, s, a);
-  launch_scan_u32(a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, a.status, -1, nullptr, s);
-  hipLaunchKernelGGL(bucket_starts_kernel, dim3(div_up(nb + 1, 256)), dim3(256), 0, s, a, nb);
+  // the scan also writes each bucket's start (its first workgroup's offset) to bkt_start
+  launch_scan_u32(a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, a.status, -1, nullptr, s, a.bkt_start, a.nblk);
   hipLaunchKernelGGL(bucket_scatter_kernel, grid, dim3(kBucketThreads), 0, s, a);
   hipLaunchKernelGGL(bucket_rank_kernel, dim3(div_up((int64_t)a.B * a.nbk, kRankBuckets)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_sort_big_kernel, dim3(std::min(a.B * a.nbk, 512)), dim3(kSortThreads), 0, s, a);

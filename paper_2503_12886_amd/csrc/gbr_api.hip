@@ -41,11 +41,13 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-// Clears the per-pass counters: tile counts/cursors, depth-bucket
-// counts/cursors, per-frame depth ranges, the large-bucket list, the status.
+// Clears the per-pass counters: per-frame depth ranges, the large-bucket
+// list, the status, and the tile-class counts of both schedules (66 words;
+// the grid has at least 256 threads).
 __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.B) { a.minmax[i * kMinmaxStride] = 0xffffffffu; a.minmax[i * kMinmaxStride + 1] = 0u; }
+  if (i < 66) a.cls_cnt[i] = 0u;
   if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
 }
 
@@ -107,6 +109,7 @@ struct gbr_ctx {
   // pass state
   bool capturing = false;
   bool have_pre = false, have_raster = false;
+  bool cls_clean = false;          // tile-class counts cleared by the last enqueued pass start, not yet used
   int B = 0;
   int64_t n_splats = 0, n_pixels = 0, max_frame_splats = 0;
   int n_tiles = 0;
@@ -207,6 +210,9 @@ int alloc_entries(gbr_ctx* c, int64_t cap) {
   int rc = GBR_OK;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
   if ((rc = dalloc(&c->part_flag, cap + 64))) return rc;   // gather reads 64-entry flag windows
+  // every pass leaves the flags zero (the gather resets what it reads), so
+  // they are cleared once here
+  if (hipMemset(c->part_flag, 0, (size_t)cap + 64) != hipSuccess) return GBR_ERR_HIP;
   if ((rc = dalloc(&c->cmask, 4 * cap))) return rc;   // a byte per quadrant
   if ((rc = dalloc(&c->part, cap * kPartF))) return rc;
   c->cap_entries = cap;
@@ -315,6 +321,7 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
   const int n_bkt = c->B * c->nbk;
   hipLaunchKernelGGL(begin_pass_kernel, dim3(div_up(std::max(std::max(c->n_tiles, n_bkt), c->B), 256)), dim3(256), 0,
                      s, a, n_bkt);
+  c->cls_clean = true;
   {
     KTimer t(c, GBR_K_PREPROCESS, s);
     launch_preprocess(a, raw, c->max_frame_splats, s);
@@ -345,7 +352,10 @@ int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
   PassArgs a = make_args(c);
   {
     KTimer t(c, GBR_K_TILE_SORT, s);
-    launch_fill_u32(c->cls_cnt, 0u, 66, s);   // both schedules of this pass start empty
+    // both schedules of this pass start empty: cleared at the pass start,
+    // or here when the pass is rasterised again
+    if (!c->cls_clean) launch_fill_u32(c->cls_cnt, 0u, 66, s);
+    c->cls_clean = false;
     launch_classify_tiles(a, false, s);
   }
   {
@@ -594,7 +604,6 @@ int gbr_render_backward(gbr_ctx* c, const float* dimages, float* draw, void* str
   PassArgs a = make_args(c);
   {
     KTimer t(c, GBR_K_COMPOSITE_BWD, s);
-    launch_clear_flags(a, s);
     launch_composite_bwd(a, dimages, nullptr, c->chunk, s);
   }
   {

@@ -100,7 +100,8 @@ struct PassArgs {
   uint32_t* n_contrib;      // [pixels] number of contributors (computed on request)
   float* t_final;           // [pixels]
   float* part;              // [E][kPartF] per-entry gradient partials (9 used), by emission slot
-  uint8_t* part_flag;       // [E] 1 where the entry's partial is non-zero and written
+  uint8_t* part_flag;       // [E] 1 where the entry's partial is written; zeroed at allocation, set by the
+                            // backward compositing, and reset to 0 by the gather that reads it
   uint8_t* cmask;           // [E][4] byte w = 1: some pixel of quadrant w of the tile took this entry (forward)
 };
 
@@ -257,8 +258,11 @@ void launch_blend_bwd(const float* draw, const float* bases, const float* weight
                       float* dbases, float* dweights, float* partials, int64_t n_partials, int accumulate,
                       hipStream_t s);
 int64_t blend_bwd_partials(int B, int K, int64_t N);
+// Exclusive scan of in[0, n) into out[0, n] (out[n] = total).  With strided
+// non-null, also strided[j] = out[j * stride] for every j * stride <= n.
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums, StatusDev* status,
-                     int64_t cap_check, unsigned long long* total_out, hipStream_t s);
+                     int64_t cap_check, unsigned long long* total_out, hipStream_t s, uint32_t* strided = nullptr,
+                     int stride = 1);
 int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
 // Words per bitmap row segment for frames of up to max_frame_tiles tiles
@@ -284,7 +288,6 @@ void launch_tangent_bwd(const float* draw_d, const int32_t* tri, const float* fr
                         float* draw_t, hipStream_t s);
 void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, int64_t N, float delta, float* bases,
                              uint8_t* done, hipStream_t s);
-void launch_clear_flags(const PassArgs& a, hipStream_t s);
 void launch_loss(const PassArgs& a, const float* images, const float* targets, int kind, float* dimages,
                  float* partials, int64_t n_partials, hipStream_t s);
 int64_t loss_partials(int64_t n_floats);

@@ -216,20 +216,6 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
   }
 }
 
-// Zero the entry flags of the pass (the entry count lives on the device).
-__global__ void clear_flags_kernel(uint8_t* __restrict__ f, const StatusDev* status) {
-  if (status->overflow) return;
-  const uint64_t n = status->entries;
-  const uint64_t n16 = (n + 15) / 16;
-  uint4* f4 = reinterpret_cast<uint4*>(f);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
-    f4[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
-void launch_clear_flags(const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(clear_flags_kernel, dim3(1024), dim3(256), 0, s, a.part_flag, a.status);
-}
-
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s) {
   (void)images;
   if (a.n_tiles == 0) return;
@@ -308,6 +294,9 @@ __global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __re
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           if (!v[u]) continue;
+          // the flag goes back to 0 for the next pass (only this splat's
+          // flags are written; neighbours mask this entry out of their windows)
+          a.part_flag[e[u]] = 0;
           acc[0] += q[u][0].x; acc[1] += q[u][0].y; acc[2] += q[u][0].z; acc[3] += q[u][0].w;
           acc[4] += q[u][1].x; acc[5] += q[u][1].y; acc[6] += q[u][1].z; acc[7] += q[u][1].w;
           acc[8] += q[u][2].x;

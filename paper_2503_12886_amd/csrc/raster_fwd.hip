@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
                                                                    const uint32_t* __restrict__ block_sums,
                                                                    uint32_t* __restrict__ out, StatusDev* status,
                                                                    int64_t cap_check,
-                                                                   unsigned long long* total_out) {
+                                                                   unsigned long long* total_out,
+                                                                   uint32_t* __restrict__ strided, int stride) {
   __shared__ uint32_t tile[kScanBlock];
   __shared__ uint32_t lw[kScanThreads / 64];
   __shared__ unsigned long long wsum[kScanThreads / 64];
@@ -99,12 +100,17 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
   for (int i = 0; i < kScanItems; ++i) {
     const int idx = i * kScanThreads + threadIdx.x;
     const int64_t k = base + idx;
-    if (k < n) out[k] = (uint32_t)(off + tile[idx]);
+    if (k < n) {
+      const uint32_t val = (uint32_t)(off + tile[idx]);
+      out[k] = val;
+      if (strided && (uint32_t)k % (uint32_t)stride == 0u) strided[(uint32_t)k / (uint32_t)stride] = val;
+    }
   }
   // out[n] = grand total, written by the block that holds position n
   if (threadIdx.x == kScanThreads - 1 && base <= n && n < base + kScanBlock) {
     const unsigned long long total = off + ex;   // ex of the last thread: the block's running total
     out[n] = (uint32_t)total;
+    if (strided && (uint32_t)n % (uint32_t)stride == 0u) strided[(uint32_t)n / (uint32_t)stride] = (uint32_t)total;
     publish_total(total, status, cap_check, total_out);
   }
 }
@@ -112,11 +118,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
 int64_t scan_scratch_words(int64_t n) { return div_up(n + 1, kScanBlock) + 1; }
 
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums, StatusDev* status,
-                     int64_t cap_check, unsigned long long* total_out, hipStream_t s) {
+                     int64_t cap_check, unsigned long long* total_out, hipStream_t s, uint32_t* strided,
+                     int stride) {
   const int nb = div_up(n + 1, kScanBlock);
   hipLaunchKernelGGL(scan_totals_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums);
   hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums, out, status,
-                     cap_check, total_out);
+                     cap_check, total_out, strided, stride < 1 ? 1 : stride);
 }
 
 // ---------------------------------------------------------------- preprocess
