@@ -195,6 +195,20 @@ __device__ __forceinline__ void row_sum9_to15(float* x) {
 #undef GBR_ROR8_ADD
 }
 
+// After row_sum9_to15: lanes 31 and 63 add the totals of the row before
+// them (lanes 15 and 47), so each half-wave's total lands in its last lane.
+// DPP row_bcast:15 with row mask 0b1010 (rows 1 and 3 written), after the
+// two wait states a DPP read of a VALU result needs.
+__device__ __forceinline__ void row_pair_add9(float* x) {
+#define GBR_BCAST15_ADD(i) "v_add_f32_dpp %" #i ", %" #i ", %" #i " row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+  asm volatile("s_nop 1\n\t"
+               GBR_BCAST15_ADD(0) GBR_BCAST15_ADD(1) GBR_BCAST15_ADD(2) GBR_BCAST15_ADD(3) GBR_BCAST15_ADD(4)
+               GBR_BCAST15_ADD(5) GBR_BCAST15_ADD(6) GBR_BCAST15_ADD(7) GBR_BCAST15_ADD(8)
+               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
+                 "+v"(x[8]));
+#undef GBR_BCAST15_ADD
+}
+
 // Lane swaps of gfx950: after swap32(x, y), x holds (x lanes 0-31, y lanes
 // 0-31) and y holds (x lanes 32-63, y lanes 32-63); after swap16(x, y), by
 // rows of 16 lanes, x holds (x0, y0, x2, y2) and y holds (x1, y1, x3, y3).

@@ -78,7 +78,7 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
 }
 
 template <int T, int CHUNK>
-__global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassArgs a,
+__global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
   static_assert(CHUNK <= 256, "a group's chunk positions are packed one byte each");
   using S = TileShapeB<T>;
@@ -157,6 +157,31 @@ __global__ __launch_bounds__(TileShapeB<T>::NT) void composite_bwd_kernel(PassAr
             e[u] = gb + hb;
             ++cnt;
           }
+        }
+        if (cnt <= 2) {
+          // a short group (the tail of a chunk): two entries, one lane-swap
+          // fold, the row sums, then each row pair added (lanes 31 and 63
+          // end with entries 0 and 1)
+          float acc2[2][9];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int i = e[u] < 0 ? e[0] : e[u];
+            const uint32_t li = e[u] < 0 ? 0xffffffffu : (uint32_t)(cbeg + i);
+            entry_grad<S::PX>(s0[i], s1[i], s2[i].x, li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc2[u]);
+          }
+          fold32x9(acc2[0], acc2[1]);
+          row_sum9_to15(acc2[0]);
+          row_pair_add9(acc2[0]);
+          if ((lane & 31) == 31) {
+            const int u = lane >> 5;
+            const int eu = u == 0 ? e[0] : e[1];
+            if (u < cnt) {
+#pragma unroll
+              for (int c = 0; c < 9; ++c) red[eu][w][c] = acc2[0][c];
+              wany8[eu * 4 + w] = 1;
+            }
+          }
+          continue;
         }
         float acc[U][9];
 #pragma unroll
