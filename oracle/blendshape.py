@@ -8,8 +8,8 @@ Each function is the plain definition from the paper:
 * blend adjoint: dG_0 = sum_b draw_b, dG_k = sum_b psi[b,k] draw_b,
   dpsi[b,k] = <dG_k, draw_b>;
 * MLP psi = F(theta) (Eq. 2): three linear layers, ReLU between them, linear
-  output (the paper names a three-layer MLP, Sec. A.3; the activation choice
-  is this build's reading);
+  output (the paper names a three-layer MLP, Sec. A.3, and leaves the
+  activation open: ReLU is a reading of it);
 * L1 colour loss (Sec. 3.2, "Loss Function") and an L2 variant, both as
   means over every channel of every pixel of every frame;
 * Adam (Sec. A.3) with bias correction, one learning rate per parameter.

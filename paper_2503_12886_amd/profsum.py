@@ -16,7 +16,7 @@ Two reports, both from rocprofv3's CSV output (``--output-format csv``):
   ``--window FIRST:COUNT`` only those launches of the kernel are averaged.
 
 Usage:
-  python -m paper_2503_12886_amd.profsum stats gpurun_out/stats
+  python -m paper_2503_12886_amd.profsum stats out/stats --window composite_bwd:24:100
   python -m paper_2503_12886_amd.profsum traffic --fetch D1 --write D2 \
       --kernel composite_bwd --copy-bytes 268435456 --json profiles/x.json
 """
