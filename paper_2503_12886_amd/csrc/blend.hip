@@ -187,7 +187,8 @@ void launch_blend_adam(const float* draw, const float* weights, int B, int K, in
 // elements (q-th quarter) of frame x's draw and of slice x's (and 16 + x's)
 // base; each of the 4 components feeds one 16x16x4 product (frames x slices,
 // contracted over the 4 quarters).  The pad features (14, 15) are skipped.
-// Writes a [B][K] partial per wave.
+// Writes a [B][K] partial per wave, or per workgroup for small tiles (B <= 16,
+// K <= 32: the four waves are added in LDS first, a quarter of the partials).
 constexpr int kDwSpan = 256;
 
 template <int MAXBT, int MAXKT>
@@ -237,19 +238,40 @@ __global__ __launch_bounds__(256) void blend_dweights_kernel(const float* __rest
         for (int j = 0; j < MAXKT; ++j)
           if (i < nbt && j < nkt) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][c], bb[j][c], acc[i][j], 0, 0, 0);
   }
-  float* out = partials + gw * (int64_t)B * K;
   // D layout of the f32 16x16x4 op: lane l, item r holds row 4(l/16) + r, column l%16.
+  if constexpr (MAXBT * MAXKT <= 2) {
+    // small tiles: the block's four waves are added in LDS (wave order) and
+    // the block writes one [B][K] partial
+    constexpr int TB = 16 * MAXBT, TK = 16 * MAXKT;
+    __shared__ float ws[4][TB * TK];
+    const int w = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < MAXBT; ++i)
+    for (int i = 0; i < MAXBT; ++i)
 #pragma unroll
-    for (int j = 0; j < MAXKT; ++j)
-      if (i < nbt && j < nkt)
+      for (int j = 0; j < MAXKT; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int b = 16 * i + 4 * q + r;
-          const int k = 16 * j + x;
-          if (b < B && k < K) out[(int64_t)b * K + k] = acc[i][j][r];
-        }
+        for (int r = 0; r < 4; ++r) ws[w][(16 * i + 4 * q + r) * TK + 16 * j + x] = acc[i][j][r];
+    __syncthreads();
+    float* out = partials + (int64_t)blockIdx.x * B * K;
+    for (int t = threadIdx.x; t < B * K; t += 256) {
+      const int b = t / K, k = t % K;
+      const int o = b * TK + k;
+      out[t] = ((ws[0][o] + ws[1][o]) + ws[2][o]) + ws[3][o];
+    }
+  } else {
+    float* out = partials + gw * (int64_t)B * K;
+#pragma unroll
+    for (int i = 0; i < MAXBT; ++i)
+#pragma unroll
+      for (int j = 0; j < MAXKT; ++j)
+        if (i < nbt && j < nkt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int b = 16 * i + 4 * q + r;
+            const int k = 16 * j + x;
+            if (b < B && k < K) out[(int64_t)b * K + k] = acc[i][j][r];
+          }
+  }
 }
 
 // One block per output: each thread sums a fixed stride of the partials,
@@ -287,11 +309,12 @@ void launch_blend_bwd(const float* draw, const float* bases, const float* weight
                        accumulate);
   if (K == 0) return;
   const dim3 g2(div_up(N * kNF, 4 * kDwSpan));
-  if (B <= 16 && K <= 32)
+  const bool small = B <= 16 && K <= 32;
+  if (small)
     hipLaunchKernelGGL((blend_dweights_kernel<1, 2>), g2, dim3(256), 0, s, draw, bases, B, K, N, partials);
   else
     hipLaunchKernelGGL((blend_dweights_kernel<4, 4>), g2, dim3(256), 0, s, draw, bases, B, K, N, partials);
-  const int64_t n_part = (int64_t)g2.x * 4;
+  const int64_t n_part = (int64_t)g2.x * (small ? 1 : 4);   // a partial per block (small tiles) or per wave
   (void)n_partials;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(B * K), dim3(256), 0, s, partials, n_part, B * K, dweights,
                      accumulate);
