@@ -261,9 +261,11 @@ void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* 
 // ---------------------------------------------------------------- gather + projection adjoint
 // Two passes.  gather_sum: one thread per splat sums its entries' partials in
 // row-major tile order (unflagged entries -- no contributing pixel, or past
-// the tile's last used position -- are zero): the flags of 8 entries are
-// read together, then the flagged partials, all loads in flight before any
-// is used; the 9 sums go to the splat's draw row as scratch.  proj_adjoint:
+// the tile's last used position -- are zero): the flags of a 64-entry window
+// are read as four 16-byte loads, then the flagged partials 4 at a time, all
+// loads in flight before any is used, and each consumed flag is reset to 0
+// for the next pass; the 9 sums go to the splat's draw row as scratch.
+// proj_adjoint:
 // one thread per splat chains those sums back through the conic, the EWA
 // projection and the activations in float64 and overwrites the row.  Kept
 // apart so the summing pass runs at full occupancy.
