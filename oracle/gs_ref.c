@@ -190,15 +190,55 @@ static int cmp_depth(const void* a, const void* b, void* ctx) {
 /* Per-pixel contributor record kept by the forward walk for the adjoint. */
 typedef struct { int64_t g; double a, G, alpha, T, dx, dy; } contrib_t;
 
+/* ---- ambiguity margins ---------------------------------------------------------
+   A binary32 implementation of the compositing can take a different discrete
+   decision from this double-precision walk only where a decision's value is
+   within that implementation's error of its threshold.  The margins below are
+   first-order bounds on those errors, for an implementation whose inputs are
+   the projected quantities (mean, conic, opacity) each rounded to binary32 and
+   whose arithmetic is binary32 throughout (u = 2^-24 per operation):
+
+   alpha = o exp(-q/2) with q = A dx^2 + 2 B dx dy + C dy^2, dx = px - mx,
+   dy = py - my.  With S = (|A| dx^2 + 2 |B dx dy| + |C| dy^2) / 2 (the
+   exponent's terms) and ln o:
+     - the rounded mean moves dx by u |mx| and the subtraction rounds by
+       u |dx|: d(q/2)/dmx = -(A dx + B dy), so the exponent moves by at most
+       u (|mx| + |dx|) |A dx + B dy| (likewise in y);
+     - the rounded conic coefficients: u S; two products per term: 2 u S; the
+       three additions (partial sums bounded by S + |ln o|): 3 u (S + |ln o|);
+       a change of base to exp2: u (S + |ln o|); the rounded opacity: u |ln o|;
+     - the exponential itself: 2 ulp, 4 u relative.
+   The relative error of alpha is at most the exponent's absolute error plus
+   4 u.  A product (1 - alpha_i) over the taken entries then carries, per
+   factor, alpha/(1 - alpha) times alpha's relative error (u for the clamped
+   0.99, whose binary32 value is within u of it), one rounding for 1 - alpha
+   and one for the product: the transmittance's relative error is at most the
+   sum over the factors so far.  The thresholds 1/255, 0.99 and 1e-4 are
+   themselves within u of their binary32 values. */
+#define U32 (1.0 / 16777216.0)
+
+static double alpha_rel_bound(const proj_t* p, double dx, double dy) {
+  double gx = fabs(p->Q[0] * dx + p->Q[1] * dy), gy = fabs(p->Q[1] * dx + p->Q[3] * dy);
+  double S = 0.5 * (fabs(p->Q[0]) * dx * dx + 2.0 * fabs(p->Q[1] * dx * dy) + fabs(p->Q[3]) * dy * dy);
+  double lo = fabs(log(p->o));
+  double e = (fabs(p->mx) + fabs(dx)) * gx + (fabs(p->my) + fabs(dy)) * gy + 7.0 * S + 5.0 * lo;
+  return U32 * (e + 4.0);
+}
+
 /* Walk one pixel's candidates (already in depth order), compositing front to
    back.  Writes the pixel colour, the final transmittance, and the
    contributor list; returns the number of contributors.  `flags` collects the
-   decisions that sit within a relative margin of their threshold:
-   1 = alpha vs 1/255, 2 = transmittance stop, 4 = alpha vs the 0.99 clamp. */
+   decisions that sit within a margin of their threshold: 1 = alpha vs 1/255,
+   2 = transmittance stop, 4 = alpha vs the 0.99 clamp.  With eps_a < 0 the
+   margins are the binary32 error bounds above (per entry and per pixel);
+   otherwise eps_a and eps_t are fixed relative margins for alpha and for the
+   transmittance. */
 static int64_t composite_pixel(const proj_t* P, const int64_t* cand, int64_t ncand, double px, double py,
                                const double bg[3], double eps_a, double eps_t, double out[3], double* Tend,
                                contrib_t* rec, unsigned* flags) {
+  const int derived = eps_a < 0.0;
   double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+  double rho = 0.0;                  /* bound on T's relative error so far (derived margins) */
   int64_t n = 0;
   for (int64_t k = 0; k < ncand; ++k) {
     const proj_t* p = &P[cand[k]];
@@ -207,12 +247,15 @@ static int64_t composite_pixel(const proj_t* P, const int64_t* cand, int64_t nca
     if (q < 0.0) q = 0.0;
     double G = exp(-0.5 * q);
     double a = p->o * G;
-    if (fabs(a - ALPHA_MIN) <= eps_a * ALPHA_MIN) *flags |= 1u;
+    double ea = derived ? alpha_rel_bound(p, dx, dy) + U32 : eps_a;
+    if (fabs(a - ALPHA_MIN) <= ea * a) *flags |= 1u;
     if (a < ALPHA_MIN) continue;
-    if (fabs(a - ALPHA_MAX) <= eps_a * ALPHA_MAX) *flags |= 4u;
+    if (fabs(a - ALPHA_MAX) <= ea * a) *flags |= 4u;
     double alpha = a < ALPHA_MAX ? a : ALPHA_MAX;
     double Tn = T * (1.0 - alpha);
-    if (fabs(Tn - T_MIN) <= eps_t * T_MIN) *flags |= 2u;
+    double ef = (alpha / (1.0 - alpha)) * (a < ALPHA_MAX ? ea : U32) + 2.0 * U32;
+    double et = derived ? rho + ef + U32 : eps_t;
+    if (fabs(Tn - T_MIN) <= et * Tn) *flags |= 2u;
     if (Tn < T_MIN) break;
     for (int c = 0; c < 3; ++c) C[c] += alpha * T * p->col[c];
     if (rec) {
@@ -221,10 +264,28 @@ static int64_t composite_pixel(const proj_t* P, const int64_t* cand, int64_t nca
     }
     ++n;
     T = Tn;
+    rho += ef;
   }
   for (int c = 0; c < 3; ++c) out[c] = C[c] + T * bg[c];
   *Tend = T;
   return n;
+}
+
+/* For checks of the margins: the unclamped alpha of Gaussian gidx[m] at the
+   point (px[m], py[m]) and the bound on its relative error used above. */
+int oracle_alpha_bounds(int64_t N, const double* raw, const double* camd, int W, int H, int64_t M,
+                        const int64_t* gidx, const double* px, const double* py, double* alpha, double* bound) {
+  cam_t cam; cam_load(camd, &cam);
+  for (int64_t m = 0; m < M; ++m) {
+    if (gidx[m] < 0 || gidx[m] >= N) return -1;
+    proj_t p; project_one(raw + NF * gidx[m], &cam, W, H, &p);
+    double dx = px[m] - p.mx, dy = py[m] - p.my;
+    double q = p.Q[0] * dx * dx + 2.0 * p.Q[1] * dx * dy + p.Q[3] * dy * dy;
+    if (q < 0.0) q = 0.0;
+    alpha[m] = p.o * exp(-0.5 * q);
+    bound[m] = alpha_rel_bound(&p, dx, dy);
+  }
+  return 0;
 }
 
 /* Candidate lists per 16x16 block of pixels: every valid Gaussian whose pixel

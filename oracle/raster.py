@@ -49,6 +49,8 @@ def _lib():
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8),
                                       ctypes.c_double, ctypes.c_double]
         lib.oracle_render_grad.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, d, d, d]
+        lib.oracle_alpha_bounds.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, i64,
+                                            ctypes.POINTER(ctypes.c_int64), d, d, d, d]
         lib.oracle_contributors.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
         _LIB = lib
@@ -83,17 +85,20 @@ def project(raw, cam) -> dict:
     return {k: out[:, i] for i, k in enumerate(PROJ_FIELDS)}
 
 
-# Relative margins within which a threshold decision of the float32 GPU path
-# may legitimately differ from this float64 reference: alpha vs 1/255 and
-# 0.99 (alpha's float32 error is a few 1e-6 relative), and the transmittance
-# stop (float32 products over a few hundred contributors).
-EPS_ALPHA = 3e-5
-EPS_T = 1e-3
+# Ambiguity margins.  By default (None) each decision's margin is the
+# first-order bound on a binary32 implementation's error for that very
+# decision, per entry for alpha and accumulated per pixel for the
+# transmittance (derivation in gs_ref.c, "ambiguity margins").  Fixed relative
+# margins can be given instead (e.g. 1e-5 for both).
 
 
-def render(raw, cam, eps_a: float = EPS_ALPHA, eps_t: float = EPS_T):
+def render(raw, cam, eps_a: float | None = None, eps_t: float | None = None):
     """-> image [3, H, W], T_end [H, W], n_contrib [H, W], flags [H, W] (uint8 bits:
     1 alpha near 1/255, 2 transmittance stop near 1e-4, 4 alpha near 0.99)."""
+    if (eps_a is None) != (eps_t is None):
+        raise ValueError("give both fixed margins or neither")
+    if eps_a is None:
+        eps_a, eps_t = -1.0, -1.0
     r = _raw64(raw)
     H, W = cam.height, cam.width
     img = np.zeros((3, H, W))
@@ -123,6 +128,25 @@ def render_grad(raw, cam, dimage):
     if rc != 0:
         raise MemoryError("oracle_render_grad failed")
     return draw[:N], dproj[:N]
+
+
+def alpha_bounds(raw, cam, gidx, px, py):
+    """Unclamped alpha of Gaussian gidx[m] at (px[m], py[m]) and the bound on
+    the relative error of a binary32 evaluation of it that the ambiguity
+    margins use -> (alpha [M], rel_bound [M])."""
+    r = _raw64(raw)
+    g = np.ascontiguousarray(np.asarray(gidx, dtype=np.int64))
+    x = np.ascontiguousarray(np.asarray(px, dtype=np.float64))
+    y = np.ascontiguousarray(np.asarray(py, dtype=np.float64))
+    M = g.shape[0]
+    a = np.zeros(max(M, 1))
+    e = np.zeros(max(M, 1))
+    c = cam_record(cam)
+    rc = _lib().oracle_alpha_bounds(r.shape[0], _ptr(r), _ptr(c), cam.width, cam.height, M,
+                                    _ptr(g, ctypes.c_int64), _ptr(x), _ptr(y), _ptr(a), _ptr(e))
+    if rc != 0:
+        raise IndexError("Gaussian index out of range")
+    return a[:M], e[:M]
 
 
 def contributors(raw, cam, cap: int = 4096):
