@@ -465,17 +465,26 @@ static void project_adjoint(const proj_t* p, const cam_t* cam, const dproj_t* d,
 /* dimage: [3][H][W] = dL/d(output image).  draw: [N][16] = dL/d(blended raw),
    overwritten.  Optional dproj_out: [N][9] gradients w.r.t. (mx, my, Q00, Q01,
    Q11, o, r, g, b) for stage checks. */
+/* The adjoint of the rendering: dimage -> draw [N][16] (and the projected-
+   quantity gradients dproj_out [N][9] if not NULL: d mean x, y, d conic
+   A, 2B, C, d opacity, d colour).  If dproj_mag is not NULL it receives, per
+   Gaussian and projected quantity, the sum over pixels of the magnitudes of
+   the per-pixel terms that the gradient is the sum of, each term's magnitude
+   formed from the magnitudes of its factors (the alpha gradient's colour
+   and background-behind parts taken separately), for error bounds of an
+   implementation that forms and sums them in binary32. */
 int oracle_render_grad(int64_t N, const double* raw, const double* camd, int W, int H, const double* dimage,
-                       double* draw, double* dproj_out) {
+                       double* draw, double* dproj_out, double* dproj_mag) {
   cam_t cam; cam_load(camd, &cam);
   scene_t s; memset(&s, 0, sizeof(s));
   if (scene_build(N, raw, &cam, W, H, &s)) { scene_free(&s); return -1; }
   dproj_t* dp = (dproj_t*)calloc((size_t)(N > 0 ? N : 1), sizeof(dproj_t));
+  dproj_t* dm = (dproj_t*)calloc((size_t)(N > 0 ? N : 1), sizeof(dproj_t));   /* magnitudes */
   int64_t maxc = 1;
   for (int b = 0; b < s.nbx * s.nby; ++b) if (s.blocks[b].n > maxc) maxc = s.blocks[b].n;
   contrib_t* rec = (contrib_t*)malloc(sizeof(contrib_t) * maxc);
   double* suffix = (double*)malloc(sizeof(double) * 3 * (maxc + 1));
-  if (!dp || !rec || !suffix) { free(dp); free(rec); free(suffix); scene_free(&s); return -1; }
+  if (!dp || !dm || !rec || !suffix) { free(dp); free(dm); free(rec); free(suffix); scene_free(&s); return -1; }
 
   for (int i = 0; i < H; ++i)
     for (int j = 0; j < W; ++j) {
@@ -494,11 +503,14 @@ int oracle_render_grad(int64_t N, const double* raw, const double* camd, int W, 
         const contrib_t* r = &rec[k];
         const proj_t* p = &s.P[r->g];
         dproj_t* d = &dp[r->g];
+        dproj_t* m = &dm[r->g];
         /* out = sum_m alpha_m T_m col_m + T_end bg, T_{m} = prod_{l<m} (1 - alpha_l) */
-        double dalpha = 0.0;
+        double dalpha = 0.0, dalpha_mag = 0.0;
         for (int c = 0; c < 3; ++c) {
           d->dcol[c] += r->alpha * r->T * g[c];
+          m->dcol[c] += fabs(r->alpha * r->T * g[c]);
           dalpha += g[c] * (r->T * p->col[c] - suffix[3 * (k + 1) + c] / (1.0 - r->alpha));
+          dalpha_mag += fabs(g[c]) * (r->T * fabs(p->col[c]) + fabs(suffix[3 * (k + 1) + c]) / (1.0 - r->alpha));
         }
         double da = (r->a < ALPHA_MAX) ? dalpha : 0.0;       /* min(0.99, a) */
         d->dop += r->G * da;
@@ -511,6 +523,17 @@ int oracle_render_grad(int64_t N, const double* raw, const double* camd, int W, 
         double ddy = dq * (2.0 * p->Q[1] * r->dx + 2.0 * p->Q[3] * r->dy);
         d->dmx -= ddx;                                        /* dx = px - mx */
         d->dmy -= ddy;
+        /* magnitudes: each factor by the magnitudes it is formed from (the
+           alpha gradient's two colour terms taken apart) */
+        if (r->a < ALPHA_MAX) {
+          double dq_mag = 0.5 * r->G * p->o * dalpha_mag;
+          m->dop += r->G * dalpha_mag;
+          m->dQ00 += dq_mag * r->dx * r->dx;
+          m->dQ01 += dq_mag * 2.0 * fabs(r->dx * r->dy);
+          m->dQ11 += dq_mag * r->dy * r->dy;
+          m->dmx += dq_mag * (2.0 * fabs(p->Q[0] * r->dx) + 2.0 * fabs(p->Q[1] * r->dy));
+          m->dmy += dq_mag * (2.0 * fabs(p->Q[1] * r->dx) + 2.0 * fabs(p->Q[3] * r->dy));
+        }
       }
     }
 
@@ -523,8 +546,13 @@ int oracle_render_grad(int64_t N, const double* raw, const double* camd, int W, 
       o[0] = dp[n].dmx; o[1] = dp[n].dmy; o[2] = dp[n].dQ00; o[3] = dp[n].dQ01; o[4] = dp[n].dQ11;
       o[5] = dp[n].dop; o[6] = dp[n].dcol[0]; o[7] = dp[n].dcol[1]; o[8] = dp[n].dcol[2];
     }
+    if (dproj_mag) {
+      double* o = dproj_mag + 9 * n;
+      o[0] = dm[n].dmx; o[1] = dm[n].dmy; o[2] = dm[n].dQ00; o[3] = dm[n].dQ01; o[4] = dm[n].dQ11;
+      o[5] = dm[n].dop; o[6] = dm[n].dcol[0]; o[7] = dm[n].dcol[1]; o[8] = dm[n].dcol[2];
+    }
   }
-  free(dp); free(rec); free(suffix);
+  free(dp); free(dm); free(rec); free(suffix);
   scene_free(&s);
   return 0;
 }
@@ -532,6 +560,26 @@ int oracle_render_grad(int64_t N, const double* raw, const double* camd, int W, 
 /* Per-pixel contributor lists as Gaussian indices (for structure checks):
    writes up to `cap` indices per pixel into lists[(i*W+j)*cap ...], counts
    into n_contrib.  Returns 0, or 1 if any pixel had more than `cap`. */
+/* The projection's adjoint alone: projected-quantity gradients dproj [N][9]
+   (as oracle_render_grad writes them) -> draw [N][16]. */
+int oracle_project_adjoint(int64_t N, const double* raw, const double* camd, int W, int H, const double* dproj,
+                           double* draw) {
+  cam_t cam; cam_load(camd, &cam);
+  for (int64_t n = 0; n < N; ++n) {
+    proj_t p; project_one(raw + NF * n, &cam, W, H, &p);
+    double* dr = draw + NF * n;
+    for (int k = 0; k < NF; ++k) dr[k] = 0.0;
+    if (!p.valid) continue;
+    const double* i = dproj + 9 * n;
+    dproj_t d;
+    memset(&d, 0, sizeof(d));
+    d.dmx = i[0]; d.dmy = i[1]; d.dQ00 = i[2]; d.dQ01 = i[3]; d.dQ11 = i[4];
+    d.dop = i[5]; d.dcol[0] = i[6]; d.dcol[1] = i[7]; d.dcol[2] = i[8];
+    project_adjoint(&p, &cam, &d, dr);
+  }
+  return 0;
+}
+
 int oracle_contributors(int64_t N, const double* raw, const double* camd, int W, int H, int32_t cap,
                         int64_t* lists, int32_t* n_contrib) {
   cam_t cam; cam_load(camd, &cam);

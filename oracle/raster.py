@@ -48,7 +48,8 @@ def _lib():
         lib.oracle_render.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, d, d,
                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint8),
                                       ctypes.c_double, ctypes.c_double]
-        lib.oracle_render_grad.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, d, d, d]
+        lib.oracle_render_grad.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, d, d, d, d]
+        lib.oracle_project_adjoint.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, d, d]
         lib.oracle_alpha_bounds.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, i64,
                                             ctypes.POINTER(ctypes.c_int64), d, d, d, d]
         lib.oracle_contributors.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int32,
@@ -124,10 +125,48 @@ def render_grad(raw, cam, dimage):
     draw = np.zeros((max(N, 1), 16))
     dproj = np.zeros((max(N, 1), 9))
     c = cam_record(cam)
-    rc = _lib().oracle_render_grad(N, _ptr(r), _ptr(c), cam.width, cam.height, _ptr(g), _ptr(draw), _ptr(dproj))
+    rc = _lib().oracle_render_grad(N, _ptr(r), _ptr(c), cam.width, cam.height, _ptr(g), _ptr(draw), _ptr(dproj),
+                                   None)
     if rc != 0:
         raise MemoryError("oracle_render_grad failed")
     return draw[:N], dproj[:N]
+
+
+def project_adjoint(raw, cam, dproj):
+    """The projection's adjoint alone: dproj [N, 9] (columns as render_grad
+    returns them) -> draw [N, 16]."""
+    r = _raw64(raw)
+    N = r.shape[0]
+    dp = np.ascontiguousarray(np.asarray(dproj, dtype=np.float64).reshape(N, 9))
+    draw = np.zeros((max(N, 1), 16))
+    c = cam_record(cam)
+    _lib().oracle_project_adjoint(N, _ptr(r), _ptr(c), cam.width, cam.height, _ptr(dp), _ptr(draw))
+    return draw[:N]
+
+
+def adjoint_magnitude(raw, cam, dimage):
+    """Per Gaussian and blended feature, the magnitude that its gradient is
+    summed from: the sum over pixels of the magnitudes of the per-pixel terms
+    of each projected-quantity gradient, carried to the blended features
+    through the magnitudes of the projection adjoint's coefficients,
+    sum_c |d raw_f / d proj_c| * sum_p |term_{p,c}|  -> [N, 16]."""
+    r = _raw64(raw)
+    N = r.shape[0]
+    g = np.ascontiguousarray(np.asarray(dimage, dtype=np.float64))
+    draw = np.zeros((max(N, 1), 16))
+    dproj = np.zeros((max(N, 1), 9))
+    mag = np.zeros((max(N, 1), 9))
+    c = cam_record(cam)
+    rc = _lib().oracle_render_grad(N, _ptr(r), _ptr(c), cam.width, cam.height, _ptr(g), _ptr(draw), _ptr(dproj),
+                                   _ptr(mag))
+    if rc != 0:
+        raise MemoryError("oracle_render_grad failed")
+    out = np.zeros((N, 16))
+    for k in range(9):
+        e = np.zeros((N, 9))
+        e[:, k] = 1.0
+        out += np.abs(project_adjoint(r, cam, e)) * mag[:N, k:k + 1]
+    return out
 
 
 def alpha_bounds(raw, cam, gidx, px, py):
