@@ -105,7 +105,8 @@ const char* gbr_strerror(int code);
 int gbr_create(const gbr_config* cfg, gbr_ctx** out);
 int gbr_destroy(gbr_ctx* ctx);
 /* Grow the entry capacity to at least max_entries (synchronises the device;
-   not allowed during graph capture).  Invalidates graphs captured before. */
+   not allowed during graph capture).  When the capacity grows, graphs
+   captured before refuse to launch (GBR_ERR_STATE). */
 int gbr_reserve(gbr_ctx* ctx, int64_t max_entries);
 /* Switch tile size / LDS chunk depth (validated as in gbr_config). */
 int gbr_set_tiling(gbr_ctx* ctx, int32_t tile, int32_t chunk);
@@ -261,7 +262,13 @@ int gbr_status_wait(gbr_ctx* ctx, int32_t slot, gbr_status* out);
 int gbr_stage_frames(gbr_ctx* ctx, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B);
 
 /* Graph capture of the work enqueued on `stream` between begin and end
-   (one captured training step replayed with a single launch). */
+   (one captured training step replayed with a single launch).  A graph
+   keeps the device addresses of the context's buffers at capture: when a
+   later call reallocates one of them (gbr_reserve, gbr_entry_count growing
+   the entry capacity, a render needing larger per-pass buffers),
+   gbr_graph_launch returns GBR_ERR_STATE without enqueueing anything, and
+   the caller captures again.  A graph must be destroyed before its
+   context. */
 int gbr_graph_begin(gbr_ctx* ctx, void* stream);
 int gbr_graph_end(gbr_ctx* ctx, void* stream, gbr_graph** out);
 int gbr_graph_launch(gbr_graph* g, void* stream);

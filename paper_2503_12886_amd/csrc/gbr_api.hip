@@ -103,6 +103,9 @@ struct gbr_ctx {
   hipEvent_t slot_ev[kSlots] = {};
   bool slot_used[kSlots] = {};
   int next_slot = 0;
+  // bumped whenever a buffer that captured work may reference is freed and
+  // allocated again; a graph records it and refuses to launch once it moved
+  uint64_t alloc_gen = 0;
   StatusDev* h_status = nullptr;   // pinned, [1 + kStatusSlots]: gbr_query_status's record, then the posted slots
   hipEvent_t status_ev[kStatusSlots] = {};
   bool status_posted[kStatusSlots] = {};
@@ -129,6 +132,8 @@ struct gbr_ctx {
 struct gbr_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  const gbr_ctx* ctx = nullptr;   // the context whose buffers the captured work uses
+  uint64_t alloc_gen = 0;         // its allocation generation at capture
 };
 
 namespace {
@@ -206,6 +211,7 @@ int check_tiling(int tile, int chunk) {
 }
 
 int alloc_entries(gbr_ctx* c, int64_t cap) {
+  ++c->alloc_gen;
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   int rc = GBR_OK;
   if ((rc = dalloc(&c->sorted, cap))) return rc;
@@ -220,6 +226,7 @@ int alloc_entries(gbr_ctx* c, int64_t cap) {
 }
 
 int alloc_buckets(gbr_ctx* c, int64_t n, int64_t cells) {
+  ++c->alloc_gen;
   dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
   c->cap_bkt = 0; c->cap_bkt_cells = 0;
   int rc = GBR_OK;
@@ -388,6 +395,7 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   if (scan_words > c->cap_scan_words) {   // the bucket-count matrix is the longest scan of a pass
     if (c->capturing) return GBR_ERR_STATE;
     GBR_HIP(hipDeviceSynchronize());
+    ++c->alloc_gen;
     dfree(c->scan_scratch);
     c->cap_scan_words = 0;
     rc = dalloc(&c->scan_scratch, scan_words);
@@ -402,6 +410,7 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   if (need_bits > c->cap_tbits) {
     if (c->capturing) return GBR_ERR_STATE;
     GBR_HIP(hipDeviceSynchronize());
+    ++c->alloc_gen;
     dfree(c->tbits);
     c->cap_tbits = 0;
     rc = dalloc(&c->tbits, need_bits);
@@ -412,6 +421,7 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   if (need_seg > c->cap_seg) {
     if (c->capturing) return GBR_ERR_STATE;
     GBR_HIP(hipDeviceSynchronize());
+    ++c->alloc_gen;
     dfree(c->seg_cnt);
     c->cap_seg = 0;
     rc = dalloc(&c->seg_cnt, need_seg);
@@ -840,12 +850,15 @@ int gbr_graph_end(gbr_ctx* c, void* stream, gbr_graph** out) {
     delete g;
     return GBR_ERR_HIP;
   }
+  g->ctx = c;
+  g->alloc_gen = c->alloc_gen;
   *out = g;
   return GBR_OK;
 }
 
 int gbr_graph_launch(gbr_graph* g, void* stream) {
   if (!g) return GBR_ERR_INVALID_ARG;
+  if (g->ctx->alloc_gen != g->alloc_gen) return GBR_ERR_STATE;   // a buffer it uses was reallocated
   GBR_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   return GBR_OK;
 }

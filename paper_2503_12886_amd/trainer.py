@@ -178,7 +178,7 @@ class Trainer:
             gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.targets)
             st = gbr.gbr_query_status(c, self.stream)
         if st.overflow:
-            gbr.gbr_reserve(c, st.entries + st.entries // 4 + 4096)
+            self._grow(st.entries)
             self.render_targets()
 
     def _mask_deltas(self) -> None:
@@ -252,7 +252,7 @@ class Trainer:
         On entry overflow the step did not update anything: grow and replay."""
         for _ in range(3):
             if self.graph is not None:
-                gbr.gbr_graph_launch(self.graph, self.stream)
+                self._replay()
             else:
                 self.enqueue_step()
             self.steps_launched += 1
@@ -276,7 +276,7 @@ class Trainer:
         last = None
         while done < n:
             while len(inflight) < depth and done + len(inflight) < n:
-                gbr.gbr_graph_launch(self.graph, self.stream)
+                self._replay()
                 gbr.gbr_status_post(self.ctx, k % 4, self.stream)
                 inflight.append(k % 4)
                 k += 1
@@ -302,9 +302,25 @@ class Trainer:
     def _grow(self, entries: int) -> None:
         gbr.gbr_reserve(self.ctx, entries + entries // 4 + 4096)
         if self.graph is not None:      # buffers moved: capture again
-            gbr.gbr_graph_destroy(self.graph)
-            self.graph = None
-            self.capture()
+            self._recapture()
+
+    def _recapture(self) -> None:
+        gbr.gbr_graph_destroy(self.graph)
+        self.graph = None
+        self.capture()
+
+    def _replay(self) -> None:
+        """Launch the captured step; if the context reallocated a buffer the
+        graph uses since it was captured (e.g. an entry count of the
+        per-frame scheme grew the capacity), the library refuses the launch
+        and the step is captured again."""
+        try:
+            gbr.gbr_graph_launch(self.graph, self.stream)
+        except gbr.GbrError as e:
+            if e.code != -5:
+                raise
+            self._recapture()
+            gbr.gbr_graph_launch(self.graph, self.stream)
 
     def capture(self) -> None:
         """Capture one step as a graph (after a warm-up step sized the buffers)."""

@@ -264,3 +264,25 @@ def test_pipelined_steps_equal_one_by_one_and_recover_from_overflow():
     for x, y in zip(state(a), state(b)):
         assert np.array_equal(x, y)
     a.close(); b.close()
+
+
+def test_graph_refuses_to_launch_after_its_buffers_moved():
+    """A graph keeps the buffer addresses of its capture: after the entry
+    capacity grows, launching it returns GBR_ERR_STATE with nothing enqueued,
+    and the trainer captures its step again and goes on."""
+    import torch
+    cfg, bases, mlp, theta, cams, targets = small(seed=4)
+    tr = Trainer(cfg, bases, mlp)
+    tr.set_batch(theta, targets, cams)
+    tr.step()
+    tr.capture()
+    tr.step()
+    st = gbr.gbr_query_status(tr.ctx)
+    gbr.gbr_reserve(tr.ctx, st.entries_capacity * 2)
+    with pytest.raises(gbr.GbrError) as e:
+        gbr.gbr_graph_launch(tr.graph, tr.stream)
+    assert e.value.code == -5
+    st2 = tr.step()                       # the trainer captures again
+    assert tr.graph is not None and not st2.overflow
+    torch.cuda.synchronize()
+    tr.close()
