@@ -8,9 +8,10 @@ weights.  The library does all the work; this module only marshals tensors.
 A context keeps the state of its last render for the backward (including a
 pointer to the blended Gaussians, which the autograd context keeps alive), so
 one forward may be in flight per context: call backward before the next
-forward on the same context.  The forward reads the pass status once (a host
-synchronisation), and if the tile-entry capacity overflowed it grows the
-capacity and renders again.
+forward on the same context.  The forward records the context's pass count
+and the backward raises if another pass has started since.  The forward
+reads the pass status once (a host synchronisation), and if the tile-entry
+capacity overflowed it grows the capacity and renders again.
 """
 from __future__ import annotations
 
@@ -40,12 +41,16 @@ class BlendRender(torch.autograd.Function):
                 raise RuntimeError("BlendRender: tile-entry overflow after growing the capacity")
         fctx.save_for_backward(bases, weights)
         fctx.gctx = ctx
+        fctx.pass_id = ctx.passes
         fctx.raw = raw          # the library's backward re-reads the blended Gaussians
         return images
 
     @staticmethod
     def backward(fctx, dimages):
         bases, weights = fctx.saved_tensors
+        if fctx.gctx.passes != fctx.pass_id:
+            raise RuntimeError("BlendRender.backward: the context has rendered again since this forward; "
+                               "its saved state belongs to the later pass")
         dbases = torch.empty_like(bases)
         dweights = torch.empty_like(weights)
         gbr.gbr_backward(fctx.gctx, dimages.contiguous(), bases, weights, dbases, dweights)

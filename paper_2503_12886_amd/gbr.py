@@ -207,6 +207,9 @@ class Context:
         _check(lib().gbr_create(ctypes.byref(self.cfg), ctypes.byref(h)), "gbr_create")
         self.handle = h
         self.tile, self.chunk = tile, chunk
+        # forward passes started on this context (gbr_render, gbr_preprocess,
+        # gbr_autotune): the state a backward reads is the latest pass's
+        self.passes = 0
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -252,12 +255,14 @@ def _frames(raw, gauss_offsets, cams):
 def gbr_render(ctx: Context, raw, gauss_offsets, cams, images, stream=None) -> None:
     B, off, cc = _frames(raw, gauss_offsets, cams)
     _f32dev(images, "images", image_numel(cams))
+    ctx.passes += 1
     _check(lib().gbr_render(ctx.handle, _f32dev(raw, "raw"), off, cc, B, _ptr(images), _stream(stream)),
            "gbr_render")
 
 
 def gbr_preprocess(ctx: Context, raw, gauss_offsets, cams, stream=None) -> None:
     B, off, cc = _frames(raw, gauss_offsets, cams)
+    ctx.passes += 1
     _check(lib().gbr_preprocess(ctx.handle, _f32dev(raw, "raw"), off, cc, B, _stream(stream)), "gbr_preprocess")
 
 
@@ -430,6 +435,7 @@ def gbr_autotune(ctx: Context, raw, gauss_offsets, cams, images, dimages, draw, 
     B, off, cc = _frames(raw, gauss_offsets, cams)
     bt, bc = _i32(), _i32()
     times = (_f32 * 9)()
+    ctx.passes += 1
     _check(lib().gbr_autotune(ctx.handle, _f32dev(raw, "raw"), off, cc, B, _f32dev(images, "images"),
                               _f32dev(dimages, "dimages"), _f32dev(draw, "draw"), _stream(stream), ctypes.byref(bt),
                               ctypes.byref(bc), times), "gbr_autotune")

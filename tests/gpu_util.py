@@ -8,6 +8,21 @@ from paper_2503_12886_amd import gbr, synth
 
 IMAGE_TOL = 1e-4        # max-abs image error against the float64 reference
 GRAD_RTOL = 1e-3        # relative gradient error (per tensor, and per entry above a floor)
+# Largest fraction of a frame's pixels that the reference may flag as
+# ambiguous (a threshold decision within a binary32 renderer's error bound of
+# its threshold).  The bounds flag 0 - 3e-4 of the pixels of the small test
+# scenes and 3.5e-4 - 4.5e-4 of the 512 x 512 training frames.
+MASK_FRAC_MAX = 1e-3
+U32 = 2.0 ** -24         # binary32 unit roundoff
+
+
+def report(tag: str, **fields) -> None:
+    """One line per parity check with the figures it was decided on (masked
+    pixel fraction, excluded Gaussians, worst error ratios)."""
+    parts = []
+    for k, v in fields.items():
+        parts.append(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}")
+    print(f"PARITY {tag} " + " ".join(parts), flush=True)
 
 
 def dev(a, dtype=None):
@@ -58,13 +73,18 @@ def pack_images(imgs) -> np.ndarray:
     return np.concatenate([np.asarray(i, dtype=np.float32).ravel() for i in imgs])
 
 
-def compare_image(gpu_img, ref_img, flags, tol=IMAGE_TOL):
+def compare_image(gpu_img, ref_img, flags, tol=IMAGE_TOL, tag=None):
     """Max-abs error on pixels whose threshold decisions are not within the
-    reference's ambiguity margins; returns (max_err, masked_fraction)."""
+    reference's ambiguity margins; returns (max_err, masked_fraction).  With
+    a tag, prints both (and the error over all pixels)."""
     ok = flags == 0
     err = np.abs(gpu_img.astype(np.float64) - ref_img)
     m = float(err[:, ok].max()) if ok.any() else 0.0
-    return m, 1.0 - ok.mean()
+    frac = 1.0 - float(ok.mean())
+    if tag is not None:
+        report(tag, image_maxabs=m, masked_frac=frac, masked_px=int((~ok).sum()),
+               maxabs_all=float(err.max()) if err.size else 0.0)
+    return m, frac
 
 
 def masked_gaussians(proj, flags) -> np.ndarray:
@@ -79,18 +99,185 @@ def masked_gaussians(proj, flags) -> np.ndarray:
     return bad
 
 
-def grad_check(gpu, ref, exclude_rows=None, rtol=GRAD_RTOL, floor=1e-3):
-    """Per-tensor relative L2 error and per-entry error with a per-column floor.
-    Returns (rel_norm_err, worst_entry_ratio) where ratio <= 1 passes."""
+def cancellation_kappa(n_max: int) -> int:
+    """Units of u * magnitude that a binary32 render adjoint may be off by in
+    an entry whose per-pixel terms cancel.  A first-order count per term: its
+    pixel's transmittance is recovered through at most n_max divisions and
+    the colour behind it formed from at most n_max additions (n_max: the
+    most contributors of any pixel), alpha carries its own bound (at most
+    about 64 u), and the term's products and the fixed-order sum over pixels
+    add a few dozen roundings; the total is doubled for the factors'
+    interaction.  It is a count, not a proof: the tests print the largest
+    error found in these units beside it."""
+    return 4 * (int(n_max) + 64)
+
+
+def grad_check(gpu, ref, exclude_rows=None, rtol=GRAD_RTOL, floor=1e-3, tag=None, mag=None, n_max=None):
+    """Per-tensor relative L2 error and per-entry error, returns
+    (rel_norm_err, worst_entry_ratio) where ratio <= 1 passes.
+
+    Per entry: |g - g*| <= rtol max(|g*|, floor max|g*| of its column).  With
+    mag (per entry, the magnitude its value is summed from: see
+    oracle.raster.adjoint_magnitude) and n_max, an entry whose terms cancel
+    may instead be off by up to cancellation_kappa(n_max) u mag, the binary32
+    error such a sum can carry.  With a tag, prints the figures."""
     g = np.asarray(gpu, dtype=np.float64)
     r = np.asarray(ref, dtype=np.float64)
     rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
     g2 = g.reshape(g.shape[0], -1) if g.ndim > 1 else g[:, None]
     r2 = r.reshape(r.shape[0], -1) if r.ndim > 1 else r[:, None]
+    m2 = None
+    if mag is not None:
+        m2 = np.asarray(mag, np.float64).reshape(g2.shape)
     if exclude_rows is not None:
         keep = ~np.asarray(exclude_rows)
         g2, r2 = g2[keep], r2[keep]
+        m2 = m2[keep] if m2 is not None else None
     colmax = np.abs(r2).max(axis=0, keepdims=True) + 1e-30
-    bound = rtol * np.maximum(np.abs(r2), floor * colmax)
-    worst = float((np.abs(g2 - r2) / bound).max()) if g2.size else 0.0
+    err = np.abs(g2 - r2)
+    rule = rtol * np.maximum(np.abs(r2), floor * colmax)
+    bound = rule
+    extra = {}
+    if m2 is not None:
+        kappa = cancellation_kappa(n_max)
+        canc = kappa * U32 * m2
+        bound = np.maximum(rule, canc)
+        in_u = err / np.maximum(U32 * m2, 1e-300)
+        extra = dict(kappa=kappa, err_in_u_mag_max=float(in_u.max()) if in_u.size else 0.0,
+                     by_cancellation=int((canc > rule).sum()),
+                     worst_rule_only=float((err / rule).max()) if err.size else 0.0)
+    worst = float((err / bound).max()) if g2.size else 0.0
+    if tag is not None:
+        n_ex = int(np.count_nonzero(exclude_rows)) if exclude_rows is not None else 0
+        report(tag, rel_l2=float(rel), worst_entry_ratio=worst, rows=int(g.shape[0]), excluded_rows=n_ex, **extra)
     return rel, worst
+
+
+# ---------------------------------------------------------------- summation error bounds
+# The blend adjoint's two contractions run in binary32 in a fixed order.  A
+# sum of products in which every product and every addition is rounded once
+# (unit roundoff u = 2^-24) differs from the exact sum of the same inputs by
+# at most gamma_d * sum|terms|, gamma_d = d u / (1 - d u), where d is the
+# largest number of roundings any one term passes through (Higham, Accuracy
+# and Stability of Numerical Algorithms, Sec. 3.1 and 4.2).  The depths below
+# follow the kernels' orders; they make no assumption on how the matrix
+# cores round inside one instruction (each of its additions may round).
+TINY32 = 2.0 ** -126     # flushed subnormal products: an absolute error of at most this much per term
+
+
+def gamma(d: int) -> float:
+    return d * U32 / (1.0 - d * U32)
+
+
+def dweights_depth(B: int, K: int, N: int) -> int:
+    """Roundings a term of dweights[b][k] passes through: one product; the
+    wave's span of 256 elements is 64 matrix-core products of 4 terms each,
+    accumulated in one register, so a term meets at most the 255 additions of
+    the span's other terms; for small tiles (B <= 16, K <= 32) the four waves
+    of a workgroup are added in sequence (3); then the final reduction, where
+    each of 256 threads adds its stride of the per-span partials in order
+    (ceil(partials / 256)) and a 256-to-1 tree follows (8)."""
+    L = N * 16
+    blocks = -(-L // 1024)
+    small = B <= 16 and K <= 32
+    n_part = blocks if small else 4 * blocks
+    return 1 + 255 + (3 if small else 0) + -(-n_part // 256) + 8
+
+
+def dbases_depth(B: int) -> int:
+    """Roundings a term of dbases[k][n][f] passes through: frames in groups of
+    16, each group a chain of fused multiply-adds (one rounding per step, the
+    product exact inside it: at most 16), the groups' sums added in order."""
+    return 16 + -(-B // 16)
+
+
+def check_sum_bound(got, exact, mag, depth: int, n_terms: int, tag: str) -> float:
+    """|got - exact| <= gamma_depth * mag + n_terms * TINY32 entry by entry,
+    where exact is the float64 value of the kernel's own inputs and mag the sum
+    of its terms' magnitudes.  Returns the worst ratio (<= 1 passes)."""
+    err = np.abs(np.asarray(got, np.float64) - exact)
+    bound = gamma(depth) * np.asarray(mag, np.float64) + n_terms * TINY32
+    worst = float((err / bound).max()) if err.size else 0.0
+    report(tag, depth=depth, gamma=gamma(depth), worst_ratio=worst, entries=int(err.size))
+    assert worst <= 1.0, (tag, worst)
+    return worst
+
+
+def check_entries_against_bound(got, ref, bound, tag: str, rtol=GRAD_RTOL, floor=1e-3) -> float:
+    """Gradient entries checked against the float64 adjoint of the reference's
+    own inputs: an entry whose |ref| exceeds its error bound (the binary32
+    summation bound plus the error its inputs carry in) takes the per-entry
+    rule |g - g*| <= rtol max(|g*|, floor max|g*| of its column); an entry
+    below it is a sum that cancels to within its own rounding and must lie
+    within the bound.  Returns the worst ratio (<= 1 passes)."""
+    g = np.asarray(got, np.float64)
+    r = np.asarray(ref, np.float64)
+    b = np.asarray(bound, np.float64)
+    g2 = g.reshape(g.shape[0], -1)
+    r2 = r.reshape(r.shape[0], -1)
+    b2 = np.broadcast_to(b.reshape(b.shape[0], -1) if b.ndim else b, r2.shape)
+    colmax = np.abs(r2).max(axis=0, keepdims=True) + 1e-30
+    big = np.abs(r2) > b2
+    lim = np.where(big, rtol * np.maximum(np.abs(r2), floor * colmax), b2)
+    ratio = np.abs(g2 - r2) / np.maximum(lim, 1e-300)
+    worst = float(ratio.max()) if ratio.size else 0.0
+    report(tag, worst_ratio=worst, per_entry_rule=int(big.sum()), within_bound=int((~big).sum()))
+    assert worst <= 1.0, (tag, worst)
+    return worst
+
+
+def zero_flagged(dimg, flags):
+    """The image gradient with the ambiguous pixels (reference flags) set to
+    zero: a pixel's contribution to the adjoint is its own, so with these
+    zeroed on both sides the gradients must agree entry by entry, and no
+    Gaussian needs to be left out."""
+    return [np.where(np.asarray(f)[None] == 0, d, 0.0).astype(np.float32) for d, f in zip(dimg, flags)]
+
+
+def blend_adjoint_checks(tag, draw_t, bases64, psi, draw_ref, dB, dpsi, draw_mag=None, n_max=None):
+    """The blend adjoint (Eq. 1's derivative) of the GPU's own draw, and the
+    chain against the float64 reference:
+
+    * the kernels against the float64 sums of their own inputs (the GPU's
+      draw and the float32 bases and weights), within the binary32 summation
+      bound of their fixed orders;
+    * draw against the reference adjoint, entry by entry (every Gaussian of
+      every frame; with draw_mag [B][N][16] and n_max, entries whose terms
+      cancel within their binary32 error as grad_check allows);
+    * dbases and dweights against the reference's: per tensor, and per entry
+      wherever the value exceeds what the summation and the error of draw
+      carried through the sum can account for (the per-entry rule), within
+      that bound elsewhere."""
+    from oracle import blendshape as bs
+    B, N = draw_ref.shape[:2]
+    K = bases64.shape[0] - 1
+    d32 = host(draw_t).reshape(B, N, 16).astype(np.float64)
+    assert np.all(d32[..., 14:] == 0)
+    rel, worst = grad_check(d32.reshape(B * N, 16)[:, :14], draw_ref.reshape(B * N, 16)[:, :14],
+                            tag=f"{tag} draw",
+                            mag=None if draw_mag is None else np.asarray(draw_mag).reshape(B * N, 16)[:, :14],
+                            n_max=n_max)
+    assert rel <= 1e-3 and worst <= 1.0, (rel, worst)
+    w64 = psi.astype(np.float64)
+    got_b = host(dB).astype(np.float64)[..., :14]
+    got_w = host(dpsi).astype(np.float64)
+    # kernels against their own inputs
+    exact_b, exact_w = bs.blend_adjoint(d32, bases64, w64)
+    mag_b, _ = bs.blend_adjoint(np.abs(d32), bases64, np.abs(w64))
+    check_sum_bound(got_b, exact_b[..., :14], mag_b[..., :14], dbases_depth(B), B, f"{tag} dbases kernel")
+    mag_w = np.einsum("knf,bnf->bk", np.abs(bases64[1:, :, :14]), np.abs(d32[:, :, :14]))
+    check_sum_bound(got_w, exact_w, mag_w, dweights_depth(B, K, N), N * 14, f"{tag} dweights kernel")
+    # chain against the reference
+    ref_b, ref_w = bs.blend_adjoint(draw_ref, bases64, w64)
+    dd = np.abs(d32 - draw_ref)
+    carry_b, _ = bs.blend_adjoint(dd, bases64, np.abs(w64))
+    carry_w = np.einsum("knf,bnf->bk", np.abs(bases64[1:, :, :14]), dd[:, :, :14])
+    rows = lambda a: np.transpose(a[..., :14], (1, 0, 2)).reshape(N, -1)
+    rel, _ = grad_check(rows(got_b), rows(ref_b[..., :14]), tag=f"{tag} dbases")
+    assert rel <= 1e-3, rel
+    bound_b = gamma(dbases_depth(B)) * mag_b[..., :14] + carry_b[..., :14] + B * TINY32
+    check_entries_against_bound(rows(got_b), rows(ref_b[..., :14]), rows(bound_b), f"{tag} dbases entries")
+    rel, _ = grad_check(got_w, ref_w, tag=f"{tag} dweights")
+    assert rel <= 1e-3, rel
+    bound_w = gamma(dweights_depth(B, K, N)) * mag_w + carry_w + N * 14 * TINY32
+    check_entries_against_bound(got_w, ref_w, bound_w, f"{tag} dweights entries")

@@ -7,17 +7,21 @@ import pytest
 from oracle import blendshape as bs
 from oracle import raster
 from paper_2503_12886_amd import gbr, synth
-from gpu_util import dev, grad_check, host, make_ctx, masked_gaussians, render
+from gpu_util import MASK_FRAC_MAX, dev, grad_check, host, make_ctx, render, report, zero_flagged
 
 pytestmark = pytest.mark.gpu
 
 
-def _render_grad_case(raw, cams, N, seed=0, tile=16, chunk=128):
+def _render_grad_case(raw, cams, N, seed=0, tile=16, chunk=128, flags=None):
+    """GPU render adjoint of a random image gradient; with the reference's
+    flags, the gradient is zero at the ambiguous pixels."""
     import torch
     ctx = make_ctx(tile=tile, chunk=chunk)
     imgs, rw, images = render(ctx, raw, cams)
     rng = np.random.default_rng(seed)
     dimg = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams]
+    if flags is not None:
+        dimg = zero_flagged(dimg, flags)
     draw = torch.zeros(raw.shape[0] * 16, device="cuda")
     gbr.gbr_render_backward(ctx, dev(np.concatenate([d.ravel() for d in dimg])), draw)
     return host(draw).reshape(-1, 16), dimg
@@ -28,11 +32,13 @@ def test_tiny_render_backward():
     w = synth.make_weights(1, 8, seed=2)
     cam = synth.fixed_camera(128, 128, 150.0, 0.5, bg=(0.2, 0.3, 0.4))
     raw = bs.blend(bases, w).astype(np.float32)[0]
-    got, dimg = _render_grad_case(raw, [cam], 2000)
+    _, _, nc, fl = raster.render(raw, cam)
+    report("tiny backward", masked_frac=float((fl != 0).mean()), max_contributors=int(nc.max()))
+    assert (fl != 0).mean() <= MASK_FRAC_MAX
+    got, dimg = _render_grad_case(raw, [cam], 2000, flags=[fl])
     ref, _ = raster.render_grad(raw, cam, dimg[0])
-    _, _, _, fl = raster.render(raw, cam)
-    bad = masked_gaussians(raster.project(raw, cam), fl)
-    rel, worst = grad_check(got[:, :14], ref[:, :14], exclude_rows=bad)
+    mag = raster.adjoint_magnitude(raw, cam, dimg[0])
+    rel, worst = grad_check(got[:, :14], ref[:, :14], tag="tiny backward draw", mag=mag[:, :14], n_max=nc.max())
     assert rel <= 1e-3, rel
     assert worst <= 1.0, worst
     assert np.all(got[:, 14:] == 0)
@@ -45,13 +51,19 @@ def test_batch_render_backward_all_tilings(tile, chunk):
     w = synth.make_weights(B, 4, seed=3)
     cams = synth.make_cameras(B, seed=5, resolutions=[(72, 64), (96, 80)], dist=(0.45, 0.6))
     raw = bs.blend(bases, w).astype(np.float32).reshape(B * N, 16)
-    got, dimg = _render_grad_case(raw, cams, N, seed=1, tile=tile, chunk=chunk)
+    refs = [raster.render(raw[b * N:(b + 1) * N], cam) for b, cam in enumerate(cams)]
+    flags = [r[3] for r in refs]
+    for b, fl in enumerate(flags):
+        report(f"batch backward frame {b}", masked_frac=float((fl != 0).mean()), max_contributors=int(refs[b][2].max()))
+        assert (fl != 0).mean() <= MASK_FRAC_MAX
+    got, dimg = _render_grad_case(raw, cams, N, seed=1, tile=tile, chunk=chunk, flags=flags)
     for b, cam in enumerate(cams):
         r = raw[b * N:(b + 1) * N]
         ref, _ = raster.render_grad(r, cam, dimg[b])
-        _, _, _, fl = raster.render(r, cam)
-        bad = masked_gaussians(raster.project(r, cam), fl)
-        rel, worst = grad_check(got[b * N:(b + 1) * N, :14], ref[:, :14], exclude_rows=bad)
+        mag = raster.adjoint_magnitude(r, cam, dimg[b])
+        rel, worst = grad_check(got[b * N:(b + 1) * N, :14], ref[:, :14],
+                                tag=f"batch backward draw frame {b} tile {tile} chunk {chunk}", mag=mag[:, :14],
+                                n_max=refs[b][2].max())
         assert rel <= 1e-3, (b, rel)
         assert worst <= 1.0, (b, worst)
 

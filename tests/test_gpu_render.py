@@ -8,7 +8,7 @@ import pytest
 from oracle import blendshape as bs
 from oracle import raster
 from paper_2503_12886_amd import gbr, synth
-from gpu_util import IMAGE_TOL, compare_image, dev, host, make_ctx, render
+from gpu_util import IMAGE_TOL, MASK_FRAC_MAX, compare_image, dev, host, make_ctx, render
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +35,9 @@ def test_tiny_image_parity():
     ctx = make_ctx()
     imgs, _, _ = render(ctx, raw, [cam])
     ref, Te, nc, fl = raster.render(raw, cam)
-    err, masked = compare_image(imgs[0], ref, fl)
+    err, masked = compare_image(imgs[0], ref, fl, tag="tiny image")
     assert err <= IMAGE_TOL, err
-    assert masked < 0.02, masked
+    assert masked <= MASK_FRAC_MAX, masked
     tfin = gbr.gbr_inspect(ctx, "t_final", 128 * 128).reshape(128, 128)
     assert np.abs(tfin - Te)[fl == 0].max() <= 1e-4
 
@@ -97,9 +97,9 @@ def test_batch_images_with_uneven_sizes_and_gaussian_sets():
     imgs, _, _ = render(ctx, raw, cams, offs)
     for b, cam in enumerate(cams):
         ref, _, _, fl = raster.render(raw[offs[b]:offs[b + 1]], cam)
-        err, masked = compare_image(imgs[b], ref, fl)
+        err, masked = compare_image(imgs[b], ref, fl, tag=f"uneven-sets frame {b}")
         assert err <= IMAGE_TOL, (b, err)
-        assert masked < 0.02
+        assert masked <= MASK_FRAC_MAX, (b, masked)
 
 
 def test_tile_size_and_chunk_invariance_bit_exact():
@@ -301,8 +301,10 @@ def test_large_frame_orders_tiles_in_a_separate_pass():
     ctx = make_ctx(max_splats=N, max_entries=1 << 24)
     imgs, _, _ = render(ctx, raw, [cam])
     ref, _, _, fl = raster.render(raw, cam)
-    err, masked = compare_image(imgs[0], ref, fl)
-    assert err <= IMAGE_TOL and masked < 0.05, (err, masked)
+    err, masked = compare_image(imgs[0], ref, fl, tag="300k-Gaussian frame")
+    # 300,000 Gaussians over 64 x 64 pixels: thousands of contributors per
+    # pixel, 5 of the 4096 pixels flagged
+    assert err <= IMAGE_TOL and masked <= 2 * MASK_FRAC_MAX, (err, masked)
     proj = raster.project(raw, cam)
     ranges, sf, sg, _ = raster.bin_and_sort([proj], [cam], 16)
     srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
@@ -322,8 +324,8 @@ def test_frames_with_many_tiles_build_rows_in_memory():
     ctx = make_ctx(tile=8)
     imgs, _, _ = render(ctx, raw, [cam])
     ref, _, _, fl = raster.render(raw, cam)
-    err, masked = compare_image(imgs[0], ref, fl)
-    assert err <= IMAGE_TOL and masked < 0.02, (err, masked)
+    err, masked = compare_image(imgs[0], ref, fl, tag="2250-tile frame")
+    assert err <= IMAGE_TOL and masked <= MASK_FRAC_MAX, (err, masked)
     proj = raster.project(raw, cam)
     ranges, sf, sg, _ = raster.bin_and_sort([proj], [cam], 8)
     assert len(ranges) > 2048

@@ -1,12 +1,16 @@
 """Serving on the GPU: a frame rendered alone equals the same frame rendered
-inside a mixed batch of several avatars (bit for bit), and a short Poisson
+inside a mixed batch of several avatars (bit for bit), the frames of a mixed
+batch match the float64 reference (MLP, blend, render), and a short Poisson
 stream is served completely with overlapping batches."""
 import numpy as np
 import pytest
 
+from oracle import blendshape as bs
+from oracle import raster
 from paper_2503_12886_amd import synth
 from paper_2503_12886_amd.serve import AvatarSpec, Batcher, GpuExecutor, Request, Server
 from paper_2503_12886_amd.trainer import mlp_pack
+from gpu_util import IMAGE_TOL, MASK_FRAC_MAX, compare_image, host
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +41,40 @@ def test_alone_equals_in_mix():
         a = ex.image(1, alone, r.rid).cpu().numpy()
         m = ex.image(0, mixed, r.rid).cpu().numpy()
         assert np.array_equal(a, m), r.rid
+    ex.close()
+
+
+def test_mixed_batch_frames_match_reference():
+    """Each frame of a batch mixing three avatars: its weights (Eq. 2), its
+    blended Gaussians (Eq. 1) and its image against the float64 reference."""
+    import torch
+    ex = executor()
+    reqs = requests(12, seed=5)
+    offsets = ex.enqueue(0, reqs)
+    torch.cuda.synchronize()
+    S = ex.slots[0]
+    frames = [reqs[i] for i in sorted(range(len(reqs)), key=lambda i: reqs[i].avatar)]   # the executor's order
+    assert len({r.avatar for r in reqs}) >= 2
+    psi_all = host(S["psi"])
+    raw_all = host(S["raw"])
+    o = 0
+    for pos, r in enumerate(frames):
+        a = r.avatar
+        N, K = ex.N[a], ex.K[a]
+        p = synth.make_mlp(K=20, seed=20 + a)
+        psi_ref, _ = bs.mlp_forward(p, np.asarray(r.theta, np.float32)[None].astype(np.float64))
+        psi = psi_all.reshape(-1)[pos * psi_all.shape[1]:pos * psi_all.shape[1] + K]
+        assert np.abs(psi - psi_ref[0]).max() <= 1e-5 * max(1.0, np.abs(psi_ref).max()), r.rid
+        bases = host(ex.bases[a]).astype(np.float64)
+        raw = raw_all[o:o + N]
+        o += N
+        want = bs.blend(bases, psi[None].astype(np.float64))[0].astype(np.float32)
+        ulp = np.abs(raw.view(np.int32).astype(np.int64) - want.view(np.int32))
+        assert ulp.max() <= 1, r.rid
+        ref, _, _, fl = raster.render(raw, r.cam)
+        img = host(ex.image(0, offsets, r.rid)).reshape(3, r.cam.height, r.cam.width)
+        err, frac = compare_image(img, ref, fl, tag=f"served frame {r.rid} (avatar {a}, N={N})")
+        assert err <= IMAGE_TOL and frac <= MASK_FRAC_MAX, (r.rid, err, frac)
     ex.close()
 
 
