@@ -153,6 +153,23 @@ int gbr_render_backward(gbr_ctx* ctx, const float* dimages, float* draw, void* s
 int gbr_blend_backward(gbr_ctx* ctx, const float* draw, const float* bases, const float* weights, int32_t B,
                        int32_t K, int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream);
 
+/* gbr_blend_backward for callers that cannot allocate device memory (code
+   under graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): no context, and nothing is allocated or freed.  The dweights
+   partials go to a fixed 4 MiB device array of the library (one per device,
+   its address looked up on the first call on that device and kept until the
+   process ends), so a shape whose partials exceed 2^20 floats --
+   ceil(N * 16 / 1024) * B * K, times 4 when B > 16 or K > 32 -- returns
+   GBR_ERR_CAPACITY (N = 50,000, B = 16, K = 20 needs 250,240).  Arguments,
+   layouts, limits (1 <= B <= 64, 0 <= K <= 63) and results as
+   gbr_blend_backward, bit for bit.  Call it with the stream's device
+   current.  Every call on a device shares that device's array: calls that
+   overlap on one device (different streams, or host threads) race and give
+   wrong results; calls ordered on one stream are safe (the array needs no
+   clearing: each call writes every partial it reads). */
+int gbr_blend_backward_noalloc(const float* draw, const float* bases, const float* weights, int32_t B, int32_t K,
+                               int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream);
+
 /* The Adam step of gbr_adam_step (Sec. A.3) on the bases [(K+1)][N][16],
    with their gradient -- the dbases of gbr_blend_backward (Eq. 1's adjoint,
    accumulate = 0) for the same draw and weights -- formed inside the update

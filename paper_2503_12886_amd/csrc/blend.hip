@@ -296,6 +296,13 @@ int64_t blend_bwd_partials(int B, int K, int64_t N) {
   return waves * (int64_t)B * K;
 }
 
+int64_t blend_bwd_partials_used(int B, int K, int64_t N) {
+  if (K == 0) return 0;
+  const int64_t blocks = (int64_t)div_up(N * kNF, 4 * kDwSpan);
+  const bool small = B <= 16 && K <= 32;     // as launch_blend_bwd: a partial per block, else per wave
+  return (small ? blocks : 4 * blocks) * (int64_t)B * K;
+}
+
 void launch_blend_bwd(const float* draw, const float* bases, const float* weights, int B, int K, int64_t N,
                       float* dbases, float* dweights, float* partials, int64_t n_partials, int accumulate,
                       hipStream_t s) {

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gbr.h"
@@ -54,6 +55,30 @@ __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
 __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u; }
 
 }  // namespace
+
+// ---- scratch of the allocation-free entry point (gbr_blend_backward_noalloc)
+// The dweights partials live in this fixed device array instead of a
+// context's workspace.  In host code `scratch` only names the symbol: its
+// device address is taken once per device with hipGetSymbolAddress (that
+// device current) and only that address is passed to kernels.
+constexpr int64_t kNoAllocScratchFloats = int64_t(1) << 20;   // 4 MiB per device
+static __device__ __align__(256) float scratch[kNoAllocScratchFloats];
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_addr[kNoAllocMaxDevices] = {};
+
+static int scratch_of_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return GBR_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GBR_ERR_HIP;
+    g_scratch_addr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return GBR_OK;
+}
 
 constexpr int kStatusSlots = 4;   // status records in flight (gbr_status_post / gbr_status_wait)
 
@@ -635,6 +660,21 @@ int gbr_blend_backward(gbr_ctx* c, const float* draw, const float* bases, const 
     launch_blend_bwd(draw, bases, weights, B, K, N, dbases, dweights, c->blend_part, c->blend_part_n, accumulate,
                      (hipStream_t)stream);
   }
+  GBR_HIP(hipGetLastError());
+  return GBR_OK;
+}
+
+int gbr_blend_backward_noalloc(const float* draw, const float* bases, const float* weights, int32_t B, int32_t K,
+                               int64_t N, float* dbases, float* dweights, int32_t accumulate, void* stream) {
+  if (!draw || !bases || B < 1 || B > 64 || K < 0 || K > kMaxK || N < 1) return GBR_ERR_INVALID_ARG;
+  if (K > 0 && (!weights || !dweights)) return GBR_ERR_INVALID_ARG;
+  if (N > (int64_t)INT32_MAX / kNF) return GBR_ERR_INVALID_ARG;
+  if (blend_bwd_partials_used(B, K, N) > kNoAllocScratchFloats) return GBR_ERR_CAPACITY;
+  float* part = nullptr;
+  const int rc = scratch_of_current_device(&part);
+  if (rc) return rc;
+  launch_blend_bwd(draw, bases, weights, B, K, N, dbases, dweights, part, kNoAllocScratchFloats, accumulate,
+                   (hipStream_t)stream);
   GBR_HIP(hipGetLastError());
   return GBR_OK;
 }

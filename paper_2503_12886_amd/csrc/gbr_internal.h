@@ -272,6 +272,8 @@ void launch_blend_bwd(const float* draw, const float* bases, const float* weight
                       float* dbases, float* dweights, float* partials, int64_t n_partials, int accumulate,
                       hipStream_t s);
 int64_t blend_bwd_partials(int B, int K, int64_t N);
+// floats of partials launch_blend_bwd actually writes and reads for this shape
+int64_t blend_bwd_partials_used(int B, int K, int64_t N);
 // Exclusive scan of in[0, n) into out[0, n] (out[n] = total).  With strided
 // non-null, also strided[j] = out[j * stride] for every j * stride <= n.
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums, StatusDev* status,

@@ -67,6 +67,7 @@ _SIGS = {
     "gbr_rasterize": ([_vp, _vp, _vp], ctypes.c_int),
     "gbr_render_backward": ([_vp, _vp, _vp, _vp], ctypes.c_int),
     "gbr_blend_backward": ([_vp, _vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _i32, _vp], ctypes.c_int),
+    "gbr_blend_backward_noalloc": ([_vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _i32, _vp], ctypes.c_int),
     "gbr_backward": ([_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp], ctypes.c_int),
     "gbr_color_init": ([_vp, _vp, _vp, ctypes.c_float, _vp, _vp], ctypes.c_int),
     "gbr_tangent_frames": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
@@ -292,6 +293,20 @@ def gbr_blend_backward(ctx: Context, draw, bases, weights, dbases, dweights, acc
                                     _f32dev(dbases, "dbases") if dbases is not None else None,
                                     _f32dev(dweights, "dweights") if K > 0 else None,
                                     int(bool(accumulate)), _stream(stream)), "gbr_blend_backward")
+
+
+def gbr_blend_backward_noalloc(draw, bases, weights, dbases, dweights, accumulate: bool = False,
+                               stream=None) -> None:
+    """gbr_blend_backward without a context and without allocating (see
+    include/gbr.h); dbases may be None."""
+    K1, N, _ = bases.shape
+    K = K1 - 1
+    B = draw.shape[0]
+    _check(lib().gbr_blend_backward_noalloc(_f32dev(draw, "draw"), _f32dev(bases, "bases"),
+                                            _f32dev(weights, "weights") if K > 0 else None, B, K, N,
+                                            _f32dev(dbases, "dbases") if dbases is not None else None,
+                                            _f32dev(dweights, "dweights") if K > 0 else None,
+                                            int(bool(accumulate)), _stream(stream)), "gbr_blend_backward_noalloc")
 
 
 def gbr_blend_adam_step(ctx: Context, group: int, draw, weights, bases, m, v, lr_table: Sequence[float],
