@@ -528,17 +528,26 @@ __device__ __forceinline__ float splat_alpha(float4 r0, float4 r1, float px, flo
   return __builtin_amdgcn_exp2f(pc);
 }
 
-// A staged splat record: mean, log2-scaled conic, log2 opacity, colour.
+// A staged candidate: mean, log2-scaled conic, log2 opacity, colour, and the
+// position after it in the tile's list.
 struct __align__(16) StagedRec {
   float4 r0;    // mx my ca cb
   float4 r1;    // cc lo r g (lo = log2 opacity)
   float cb;     // b
-  float pad[3];
+  uint32_t next;  // list position after this entry
+  float pad[2];
 };
 
 // One wave per (tile, quadrant): each wave composites its quadrant's pixels
 // on its own, with no barrier shared with the other quadrants of the tile,
-// and stops as soon as its own pixels have stopped.  The tile's list is read
+// and stops as soon as its own pixels have stopped.  While a chunk's records
+// are staged, the entries whose alpha >= 1/255 region may reach the wave's
+// pixels are compacted into LDS in list order (a lane tests an entry); the
+// compositing then walks that dense array 4 at a time with a uniform counter.
+// Per (entry, pixel) the front-to-back step is written on the pixel's signed
+// transmittance Te (its transmittance while it runs; once it has stopped,
+// minus the transmittance at the stop), so every decision is a vector
+// compare and select: no per-entry mask logic on the scalar unit.  The tile's list is read
 // in depth order from its bitmap row, a chunk at a time, as the compositing
 // consumes it: a cursor walks the row's segments 64 at a time (their bit
 // counts, prefix-summed across the wave, place each segment in the tile's
@@ -575,9 +584,13 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
   const uint32_t start = a.tile_start[g], end = a.tile_start[g + 1];
   const int vt = q * 64 + lane;         // this lane's thread index in the tile's pixel map
   const int lx0 = S::lx0(vt), ly0 = S::ly0(vt);
-  float T_[S::PX], C0[S::PX], C1[S::PX], C2[S::PX], pxf[S::PX], pyf[S::PX];
-  uint32_t last[S::PX];
-  bool done[S::PX], inside[S::PX];
+  // Te: transmittance while the pixel runs; once it has stopped, minus the
+  // transmittance at the stop (-0 outside the frame).  last: list position
+  // after the last entry taken; lastk: candidate slot + 1 of the last entry
+  // taken in the current chunk (0: none)
+  float Te[S::PX], C0[S::PX], C1[S::PX], C2[S::PX], pxf[S::PX], pyf[S::PX];
+  uint32_t last[S::PX], lastk[S::PX];
+  bool inside[S::PX];
   bool mine = false;
 #pragma unroll
   for (int p = 0; p < S::PX; ++p) {
@@ -585,9 +598,9 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
     pxf[p] = (float)px + 0.5f;
     pyf[p] = (float)py + 0.5f;
     inside[p] = px < F.W && py < F.H;
-    T_[p] = 1.0f; C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0;
-    done[p] = !inside[p];
-    mine |= !done[p];
+    Te[p] = inside[p] ? 1.0f : 0.0f;
+    C0[p] = C1[p] = C2[p] = 0.0f; last[p] = 0; lastk[p] = 0;
+    mine |= inside[p];
   }
   const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
   const uint16_t* segc = a.seg_cnt + (int64_t)g * a.seg_stride;
@@ -662,82 +675,97 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
       wseg += 64u;
       wpos += wtot;
     }
-    // ---- the chunk's records ----
-    for (int i = lane; i < n; i += 64) {
-      const uint32_t sp = a.depth_sorted[vbase + min(list[i], nv - 1u)];   // (every rank is written)
-      a.sorted[cb + i] = sp;
-      const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
-      sr[i].r0 = rec[0]; sr[i].r1 = rec[1]; sr[i].cb = rec[2].x;
+    // ---- the chunk's records; the candidates compacted in list order ----
+    constexpr int NB = (CHUNK + 63) / 64;
+    int kslot[NB];                        // this lane's entry of block j: its candidate slot, or -1
+    int ncand = 0;                        // (uniform)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int i = j * 64 + lane;
+      kslot[j] = -1;
+      if (j * 64 >= n) continue;
+      float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0;
+      float qb = 0.f;
+      bool c = false;
+      if (i < n) {
+        const uint32_t sp = a.depth_sorted[vbase + min(list[i], nv - 1u)];   // (every rank is written)
+        a.sorted[cb + i] = sp;
+        const float4* rec = reinterpret_cast<const float4*>(a.rec + (int64_t)sp * kRecF);
+        q0 = rec[0]; q1 = rec[1]; qb = rec[2].x;
+        c = live && strip_reach(q0, q1, sx0, sx1, sy0, sy1);
+      }
+      const unsigned long long m = __ballot(c);
+      if (c) {
+        const int k = ncand + (int)lanes_below(m);
+        kslot[j] = k;
+        sr[k].r0 = q0; sr[k].r1 = q1; sr[k].cb = qb; sr[k].next = c0 + (uint32_t)i + 1u;
+      }
+      ncand += __popcll(m);
     }
-    if (lane < U) {                       // padding entries: opacity 0 (log2 -1e30), never taken
-      sr[n + lane].r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      sr[n + lane].r1 = make_float4(0.f, -1e30f, 0.f, 0.f);
-      sr[n + lane].cb = 0.f;
+    if (lane < U) {                       // padding entries: opacity 0 (log2 -1e30), never taken; their
+      sr[ncand + lane].r1 = make_float4(0.f, -1e30f, 0.f, 0.f);   // colour 0 (its mean and conic may be
+      sr[ncand + lane].cb = 0.f;                                   // anything: min(power, -1e30) = -1e30)
     }
     __syncthreads();
-    // ---- compositing: entries whose alpha >= 1/255 region may reach the
-    // wave's rectangle (a lane tests an entry), in list order, U at a time ----
-    for (int gb = 0; gb < n; gb += 64) {
-      unsigned long long cand = 0ull;
-      if (live) {
-        const int idx = gb + lane;
-        cand = __ballot(idx < n && strip_reach(sr[idx].r0, sr[idx].r1, sx0, sx1, sy0, sy1));
-      }
-      unsigned long long tookm = 0ull;
-      while (cand) {
-        int e[U];
+    // ---- compositing: the candidates in list order, U at a time ----
+    uint32_t took4 = 0u;                  // lane g: bit u = some pixel took candidate 4 g + u
+    for (int k = 0; live && k < ncand; k += U) {
+      float4 r0[U], r1[U];
+      float cb2[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) { r0[u] = sr[k + u].r0; r1[u] = sr[k + u].r1; cb2[u] = sr[k + u].cb; }
+      unsigned long long tm[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) tm[u] = 0ull;
+#pragma unroll
+      for (int p = 0; p < S::PX; ++p) {
+        float al[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int f = __ffsll((long long)cand) - 1;   // -1 once the candidates run out
-          cand &= cand - 1ull;
-          e[u] = f >= 0 ? gb + f : n + u;                // padding entry: opacity 0, never taken
-        }
-        float4 r0[U], r1[U];
-        float cb2[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) { r0[u] = sr[e[u]].r0; r1[u] = sr[e[u]].r1; cb2[u] = sr[e[u]].cb; }
-        unsigned long long tm[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) tm[u] = 0ull;
-#pragma unroll
-        for (int p = 0; p < S::PX; ++p) {
-          float al[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            float dx, dy, pwr;
-            al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr);
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            // branch-free front-to-back step; the arithmetic of a taken entry is
-            // exactly that of the plain loop, an untaken one changes nothing
-            const bool ok = !done[p] && al[u] >= kAlphaMin;
-            const float alc = fminf(al[u], kAlphaMax);
-            const float tn = T_[p] * (1.0f - alc);
-            const bool stop = ok && tn < kTMin;
-            const bool take = ok && !stop;
-            done[p] = done[p] || stop;
-            const float wgt = take ? alc * T_[p] : 0.0f;
-            C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
-            C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
-            C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
-            T_[p] = take ? tn : T_[p];
-            last[p] = take ? (c0 + (uint32_t)e[u] + 1u) : last[p];
-            tm[u] |= __builtin_amdgcn_ballot_w64(take);
-          }
+          float dx, dy, pwr;
+          al[u] = splat_alpha(r0[u], r1[u], pxf[p], pyf[p], dx, dy, pwr);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (tm[u]) tookm |= 1ull << (e[u] - gb);
-        bool mine_now = false;
-#pragma unroll
-        for (int p = 0; p < S::PX; ++p) mine_now |= !done[p];
-        if (__ballot(mine_now) == 0ull) {
-          live = false;
-          break;
+        for (int u = 0; u < U; ++u) {
+          // the front-to-back step: alpha below 1/255 is skipped (w = 0, Te
+          // passes unchanged), T (1 - alpha) < 1e-4 stops the pixel before
+          // this entry (Te -> -T); a stopped pixel has Te <= 0, so its tn <= 0
+          // stops it again (Te kept: min(Te, -Te)) and it takes nothing
+          const float w = (al[u] >= kAlphaMin) ? fminf(al[u], kAlphaMax) : 0.0f;
+          const float tn = Te[p] * (1.0f - w);
+          const bool stop = tn < kTMin;
+          const float wgt = stop ? 0.0f : w * Te[p];
+          C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
+          C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
+          C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
+          float te_neg;
+          asm("v_min_f32 %0, %1, -%1" : "=v"(te_neg) : "v"(Te[p]));
+          Te[p] = stop ? te_neg : tn;
+          const bool take = wgt > 0.0f;   // w >= 1/255 and Te >= 1e-4: never 0 when taken
+          lastk[p] = take ? (uint32_t)(k + u + 1) : lastk[p];
+          tm[u] |= __builtin_amdgcn_ballot_w64(take);
         }
       }
-      if (gb + lane < n) a.cmask[((int64_t)(cb + gb + lane) << 2) + q] = (uint8_t)((tookm >> lane) & 1ull);
+      const uint32_t m4 = (tm[0] ? 1u : 0u) | (tm[1] ? 2u : 0u) | (tm[2] ? 4u : 0u) | (tm[3] ? 8u : 0u);
+      took4 = (lane == k / U) ? m4 : took4;
+      bool mine_now = false;
+#pragma unroll
+      for (int p = 0; p < S::PX; ++p) mine_now |= Te[p] > 0.0f;
+      if (__ballot(mine_now) == 0ull) live = false;
+    }
+    // the list position after each pixel's last entry taken in this chunk
+#pragma unroll
+    for (int p = 0; p < S::PX; ++p) {
+      if (lastk[p]) last[p] = sr[lastk[p] - 1].next;
+      lastk[p] = 0;
+    }
+    // the quadrant's contribution byte of every entry of the chunk
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int i = j * 64 + lane;
+      const int ks = kslot[j];
+      const uint32_t t4 = (uint32_t)__shfl((int)took4, ks < 0 ? 0 : ks / U);
+      if (i < n) a.cmask[((int64_t)(cb + i) << 2) + q] = (ks >= 0) ? (uint8_t)((t4 >> (ks % U)) & 1u) : (uint8_t)0;
     }
     __syncthreads();
   }
@@ -749,11 +777,12 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
       const int64_t pix = (int64_t)py * F.W + px;
       const int64_t hw = (int64_t)F.W * F.H;
       float* img = images + F.pix_base * 3;
-      img[pix] = C0[p] + T_[p] * F.bg[0];
-      img[hw + pix] = C1[p] + T_[p] * F.bg[1];
-      img[2 * hw + pix] = C2[p] + T_[p] * F.bg[2];
+      const float Tfin = fabsf(Te[p]);
+      img[pix] = C0[p] + Tfin * F.bg[0];
+      img[hw + pix] = C1[p] + Tfin * F.bg[1];
+      img[2 * hw + pix] = C2[p] + Tfin * F.bg[2];
       a.n_iter[F.pix_base + pix] = last[p];
-      a.t_final[F.pix_base + pix] = T_[p];
+      a.t_final[F.pix_base + pix] = Tfin;
       my_last = max(my_last, last[p]);
     }
   }
