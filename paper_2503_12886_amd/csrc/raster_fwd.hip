@@ -612,9 +612,11 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
     nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
     nseg = ((nv + 31) / 32 + SW - 1) / SW;
   }
-  // the wave's pixel-centre rectangle, for culling entries that cannot reach it
-  const float sx0 = (float)(tx * T + S::qx(vt) * S::QW) + 0.5f, sx1 = sx0 + (float)(S::QW - 1);
-  const float sy0 = (float)(ty * T + S::qy(vt) * S::QW) + 0.5f, sy1 = sy0 + (float)(S::QW - 1);
+  // the wave's quadrant origin (pixel centre of its first lane's first pixel);
+  // entries are culled against the rectangle of its pixels still running
+  static_assert(S::LPR == 8, "the live-rectangle fold assumes 8 lanes per quadrant row");
+  const float qx0 = (float)(tx * T + S::qx(vt) * S::QW) + 0.5f;
+  const float qy0 = (float)(ty * T + S::qy(vt) * S::QW) + 0.5f;
   uint32_t wseg = 0, wpos = 0;          // cursor: a segment starting at or before the chunk, its first position
   bool live = __ballot(mine) != 0ull;
   for (uint32_t cb = start; live && cb < end; cb += CHUNK) {
@@ -674,6 +676,30 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
       }
       wseg += 64u;
       wpos += wtot;
+    }
+    // ---- the rectangle of the pixel centres still running: lanes are 8 per
+    // row, so a column runs if any of its 8 lanes does, a row if its byte of
+    // the wave mask is nonzero ----
+    float sx0, sx1, sy0, sy1;
+    {
+      bool run = false;
+#pragma unroll
+      for (int p = 0; p < S::PX; ++p) run |= Te[p] > 0.0f;
+      const unsigned long long M = __ballot(run);
+      unsigned long long cm8 = M | (M >> 32);
+      cm8 |= cm8 >> 16;
+      cm8 |= cm8 >> 8;
+      cm8 &= 0xffull;
+      unsigned long long rm = M | (M >> 4);
+      rm |= rm >> 2;
+      rm |= rm >> 1;
+      rm &= 0x0101010101010101ull;
+      const int c0l = __ffsll((long long)cm8) - 1, c1l = 63 - __clzll((long long)cm8);
+      const int r0l = (__ffsll((long long)rm) - 1) >> 3, r1l = (63 - __clzll((long long)rm)) >> 3;
+      sx0 = qx0 + (float)(c0l * S::PXW);
+      sx1 = qx0 + (float)(c1l * S::PXW + S::PXW - 1);
+      sy0 = qy0 + (float)(r0l * S::PXW);
+      sy1 = qy0 + (float)(r1l * S::PXW + S::PXW - 1);
     }
     // ---- the chunk's records; the candidates compacted in list order ----
     constexpr int NB = (CHUNK + 63) / 64;
