@@ -643,7 +643,7 @@ int gbr_render_backward(gbr_ctx* c, const float* dimages, float* draw, void* str
   }
   {
     KTimer t(c, GBR_K_GATHER_BWD, s);
-    launch_gather_bwd(a, c->last_raw, draw, s);
+    launch_gather_bwd(a, c->last_raw, draw, c->max_frame_splats, s);
   }
   GBR_HIP(hipGetLastError());
   return GBR_OK;

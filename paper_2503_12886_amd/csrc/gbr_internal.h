@@ -294,7 +294,7 @@ void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
-void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s);
+void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, int64_t max_frame_splats, hipStream_t s);
 void launch_tangent_frames(const float* verts, const int32_t* faces, const float* face_uv, int B, int V, int F,
                            float* frames, hipStream_t s);
 void launch_tangent_fwd(const float* raw_t, const int32_t* tri, const float* bary, const float* verts,

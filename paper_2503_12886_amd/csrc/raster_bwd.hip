@@ -336,10 +336,15 @@ __global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __re
   for (int k = 0; k < 9; ++k) out[k] = acc[k];
 }
 
+// A workgroup per (frame, 256 of its splats): the frame is the grid's y
+// index, so its camera is read at uniform addresses.
 __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const float* __restrict__ raw,
                                                            float* __restrict__ draw) {
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s >= a.n_splats) return;
+  const int b = blockIdx.y;
+  const FrameDev& F = a.frames[b];
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= F.gauss_count) return;
+  const int64_t s = F.gauss_base + n;
   float4* out = reinterpret_cast<float4*>(draw + s * kNF);
   const uint32_t c = a.cnt[s];
   if (a.status->overflow || c == 0) {
@@ -347,8 +352,6 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
     out[0] = z; out[1] = z; out[2] = z; out[3] = z;
     return;
   }
-  const int b = frame_of_splat(a.frames, a.B, s);
-  const FrameDev& F = a.frames[b];
   float acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = draw[s * kNF + k];
@@ -492,10 +495,10 @@ void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, in
                      bases, done);
 }
 
-void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, hipStream_t s) {
-  if (a.n_splats == 0) return;
+void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, int64_t max_frame_splats, hipStream_t s) {
+  if (a.n_splats == 0 || max_frame_splats == 0) return;
   hipLaunchKernelGGL(gather_sum_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, draw);
-  hipLaunchKernelGGL(proj_adjoint_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, raw, draw);
+  hipLaunchKernelGGL(proj_adjoint_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a, raw, draw);
 }
 
 // ---------------------------------------------------------------- loss
