@@ -19,6 +19,7 @@ every step of the computation runs in the library's kernels.
 """
 from __future__ import annotations
 
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -262,14 +263,15 @@ class Trainer:
             self._grow(st.entries)
         raise RuntimeError("tile-entry overflow persists after growing the capacity")
 
-    def run_steps(self, n: int, depth: int = 2) -> gbr.gbr_status:
+    def run_steps(self, n: int, depth: int = 2, record: list | None = None) -> gbr.gbr_status:
         """n steps on the current batch from the captured graph, each replay
         enqueued before the host waits for the status of the step before it:
         still one status read per step, but the GPU does not idle while the
         host reads it and launches the next replay. A step that overflowed
         updated nothing: the steps in flight are drained, the capacity grows,
         the graph is captured again and the missing steps run. Returns the
-        last step's status."""
+        last step's status.  With record, appends (host time when the
+        step's status arrived, its tile entries) for every completed step."""
         assert self.graph is not None, "capture the step first"
         assert 1 <= depth <= 4
         done, inflight, k, retries = 0, [], 0, 0
@@ -284,6 +286,8 @@ class Trainer:
             st = gbr.gbr_status_wait(self.ctx, inflight.pop(0))
             if not st.overflow:
                 done, last, retries = done + 1, st, 0
+                if record is not None:
+                    record.append((time.perf_counter(), int(st.entries)))
                 continue
             need = st.entries
             for slot in inflight:                 # drain the replays in flight
@@ -292,6 +296,8 @@ class Trainer:
                     need = max(need, s2.entries)
                 else:
                     done, last = done + 1, s2
+                    if record is not None:
+                        record.append((time.perf_counter(), int(s2.entries)))
             inflight = []
             retries += 1
             if retries > 3:
