@@ -378,27 +378,43 @@ def eager_breakdown(tr) -> dict:
 def serve_leg(seconds: float) -> dict:
     """Animation serving: 8 resident avatars (N above, K=20), Poisson requests at
     2000/s with a tracking vector and a 512x512 camera each, batches formed every
-    <= 2 ms, admission by a 2 GiB in-flight memory budget, 3 overlapping slots."""
+    <= 2 ms, 3 overlapping slots, a 2 GiB device-memory budget: the slots'
+    contexts are sized to hold a third of it each (the library's accounting),
+    and a request joins a batch only while it fits its slot and the footprint
+    of the work in flight fits the budget."""
     from paper_2503_12886_amd import synth
-    from paper_2503_12886_amd.serve import AvatarSpec, Batcher, GpuExecutor, Request, Server
+    from paper_2503_12886_amd.serve import (AvatarSpec, Batcher, GpuExecutor, Request, Server, frame_footprint,
+                                            slot_spec_for_budget)
     from paper_2503_12886_amd.trainer import mlp_pack
-    rate = 2000.0
+    rate, budget, n_slots, max_batch = 2000.0, 2 << 30, 3, 8
+    spec = slot_spec_for_budget(budget, n_slots, SERVE_NS, 512, 512, max_batch)
     bases = [synth.make_scene(n, 20, seed=100 + i) for i, n in enumerate(SERVE_NS)]
     mlps = [mlp_pack(synth.make_mlp(K=20, seed=200 + i)) for i in range(len(SERVE_NS))]
-    ex = GpuExecutor(bases, mlps, n_slots=3, max_batch=16, width=512, height=512)
+    ex = GpuExecutor(bases, mlps, n_slots=n_slots, max_batch=max_batch, width=512, height=512, slot=spec)
     n = int(rate * seconds)
     t, av, th, yaw = synth.make_request_stream(n, rate, len(SERVE_NS), seed=4)
     cams = synth.make_cameras(n, 512, 512, seed=5)
+    avatars = [AvatarSpec(N=x, K=20) for x in SERVE_NS]
     warm = [Request(rid=-1 - i, avatar=i, theta=th[0], cam=cams[0], t_arrival=0.0) for i in range(len(SERVE_NS))]
-    b = Batcher([AvatarSpec(N=x, K=20) for x in SERVE_NS], budget_bytes=2 << 30, max_batch=16, window_s=0.002)
+    b = Batcher(avatars, budget_bytes=budget, max_batch=max_batch, window_s=0.002, slot=spec)
     Server(b, ex).run(warm)                                  # warm-up (code objects, first launches)
     reqs = [Request(rid=i, avatar=int(av[i]), theta=th[i], cam=cams[i], t_arrival=float(t[i])) for i in range(n)]
-    b = Batcher([AvatarSpec(N=x, K=20) for x in SERVE_NS], budget_bytes=2 << 30, max_batch=16, window_s=0.002)
+    b = Batcher(avatars, budget_bytes=budget, max_batch=max_batch, window_s=0.002, slot=spec)
     stats = Server(b, ex).run(reqs)
+    held = ex.memory()
+    ov = ex.overflows
     ex.close()
     stats.update({"offered_req_per_s": rate, "avatars": list(SERVE_NS), "resolution": [512, 512],
-                  "window_ms": 2.0, "budget_bytes": 2 << 30, "slots": 3,
-                  "latency": "arrival to render complete on the GPU"})
+                  "window_ms": 2.0, "budget_bytes": budget, "slots": n_slots, "max_batch": max_batch,
+                  "slot_capacity_splats": spec.max_splats, "slot_planned_bytes": spec.bytes,
+                  "slots_held_bytes": held, "entry_overflows": ov,
+                  "frame_footprint_bytes": {str(x): frame_footprint(x, 512, 512, max(SERVE_NS))
+                                            for x in sorted(set(SERVE_NS))},
+                  "latency": "arrival to render complete on the GPU",
+                  "admission": "a frame's footprint is the library's planned workspace for it (per-splat, "
+                               "per-pixel, per-tile, tile bitmap rows at the largest avatar's length, 32 tile "
+                               "entries per Gaussian); deferred counts the times the head of the queue waited for "
+                               "budget or slot capacity"})
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in stats.items()}
 
 

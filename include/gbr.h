@@ -108,6 +108,20 @@ int gbr_destroy(gbr_ctx* ctx);
    not allowed during graph capture).  When the capacity grows, graphs
    captured before refuse to launch (GBR_ERR_STATE). */
 int gbr_reserve(gbr_ctx* ctx, int64_t max_entries);
+/* Device memory of a context's workspace, in bytes, for callers that budget
+   it (the serving executor admits work by the bytes its contexts hold):
+   gbr_memory gives what the context holds now (its capacities at creation,
+   grown by gbr_reserve and by the per-pass buffers -- depth buckets, scan
+   scratch, tile bitmap rows -- of the largest pass so far); gbr_plan_bytes
+   gives what a context created with cfg would hold after one pass of B
+   frames (per-frame Gaussian counts from gauss_offsets, host [B + 1];
+   frame sizes widths, heights, host [B]) with at least `entries` tile
+   entries reserved.  Both count the allocations as requested (the device
+   allocator rounds each up).  Host-only; GBR_ERR_INVALID_ARG /
+   GBR_ERR_CAPACITY as gbr_create and gbr_render would return. */
+int gbr_memory(gbr_ctx* ctx, int64_t* device_bytes);
+int gbr_plan_bytes(const gbr_config* cfg, int32_t B, const int64_t* gauss_offsets, const int32_t* widths,
+                   const int32_t* heights, int64_t entries, int64_t* device_bytes);
 /* Switch tile size / LDS chunk depth (validated as in gbr_config). */
 int gbr_set_tiling(gbr_ctx* ctx, int32_t tile, int32_t chunk);
 

@@ -462,6 +462,70 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   return GBR_OK;
 }
 
+// Device bytes of a context's workspace from its capacities: the sizes
+// gbr_create allocates, grown by a pass (depth buckets, scan scratch, tile
+// bitmap rows and their segment counts) and by gbr_reserve (entries).  One
+// formula serves gbr_memory (a context's current bytes) and gbr_plan_bytes
+// (what a context sized for a batch would hold).
+struct WorkspaceCaps {
+  int64_t frames, splats, pixels, tiles, entries, bkt, bkt_cells, scan_words, tbits, seg, ci_pixels, ci_splats;
+  bool timing;
+};
+
+int64_t workspace_bytes(const WorkspaceCaps& k) {
+  auto n = [](int64_t c) { return c < 1 ? (int64_t)1 : c; };   // dalloc allocates at least one element
+  int64_t b = 0;
+  b += n(k.frames) * (int64_t)sizeof(FrameDev) + (int64_t)sizeof(StatusDev);
+  b += n(k.splats * kRecF) * 4 + n(k.splats) * 16 + n(k.splats) * 4 + n(k.splats + 1) * 4 + n(k.splats) * 4;
+  b += (n(k.tiles) + n(k.tiles + 1) + n(k.tiles) + n(4 * k.tiles) + 2 * n(33 * k.tiles)) * 4 + 66 * 4;
+  b += n((int64_t)kMinmaxStride * k.frames) * 4 + 4;
+  b += (n(k.splats) * 2) * 8 + n(k.splats) * 4 * 2;                       // bucket keys, order, rank
+  b += (n(k.bkt_cells) + n(k.bkt_cells + 1) + n(k.bkt + 1) + n(k.bkt)) * 4;  // depth buckets
+  b += 3 * n(k.pixels) * 4;                                                  // n_iter, n_contrib, t_final
+  b += n(k.scan_words) * 4 + n(k.splats * kNF) * 4;
+  b += n(2 * loss_partials(3 * k.pixels) + 2) * 4;
+  b += n(4 * k.splats + 4096LL * k.frames + 64LL * 64 * 8) * 4;
+  b += (int64_t)kBlendMaxFrames * kBlendW64Stride * 8 + 4 * n(k.frames * 1024) * 4;
+  b += n(k.entries) * 4 + n(k.entries + 64) + n(4 * k.entries) + n(k.entries * kPartF) * 4;   // sorted, flags, cmask, part
+  b += n(k.tbits) * 4 + n(k.seg) * 2;
+  if (k.ci_pixels) b += n(3 * k.ci_pixels) * 4 + n(k.ci_splats * kNF) * 4;
+  if (k.timing) b += 4 * GBR_K_COUNT * 8;
+  return b;
+}
+
+// The pass-dependent capacities for frames of up to mfs splats (bucket
+// count and blocks as set_pass chooses them) over n_tiles tiles, the largest
+// frame having max_frame_tiles.
+void pass_caps(int B, int64_t mfs, int64_t n_tiles, int max_frame_tiles, int64_t* bkt, int64_t* cells,
+               int64_t* scan_words, int64_t* tbits, int64_t* seg) {
+  int nbk = 64;
+  while (nbk < 8192 && (int64_t)nbk * 8 < mfs) nbk *= 2;
+  const int64_t nblk = std::max<int64_t>(1, (mfs + 4095) / 4096);
+  *bkt = (int64_t)B * nbk;
+  *cells = (int64_t)B * nbk * nblk;
+  *scan_words = scan_scratch_words(*cells);
+  const int64_t row_words = ((mfs + 31) / 32 + 31) / 32 * 32;
+  const int sw = bitmap_seg_words(max_frame_tiles, row_words);
+  *tbits = std::max<int64_t>(1, n_tiles * row_words);
+  *seg = std::max<int64_t>(1, n_tiles * (row_words / sw));
+}
+
+WorkspaceCaps caps_at_create(const gbr_config* cfg) {
+  WorkspaceCaps k{};
+  k.frames = cfg->max_frames;
+  k.splats = cfg->max_splats;
+  k.pixels = cfg->max_pixels;
+  const int64_t edge = 2 * (int64_t)std::ceil(std::sqrt((double)cfg->max_pixels)) / 8 + 1;
+  k.tiles = cfg->max_pixels / 64 + (int64_t)cfg->max_frames * (2 * edge + 1);
+  k.entries = cfg->max_entries;
+  k.bkt = 64LL * cfg->max_frames;
+  k.bkt_cells = 64LL * cfg->max_frames;
+  k.scan_words = scan_scratch_words(std::max<int64_t>(std::max<int64_t>(k.splats, k.tiles), 8192LL * k.frames));
+  k.tbits = 0;
+  k.seg = 0;
+  return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -496,8 +560,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   c->cap_splats = cfg->max_splats;
   c->cap_pixels = cfg->max_pixels;
   // tiles at the smallest tile size, plus partial edge tiles of every frame
-  const int64_t edge = 2 * (int64_t)std::ceil(std::sqrt((double)cfg->max_pixels)) / 8 + 1;
-  c->cap_tiles = cfg->max_pixels / 64 + (int64_t)cfg->max_frames * (2 * edge + 1);
+  c->cap_tiles = caps_at_create(cfg).tiles;
   int rc = GBR_OK;
 #define TRY(x) do { if ((rc = (x))) { free_all(c); delete c; return rc; } } while (0)
   TRY(dalloc(&c->d_frames, c->cap_frames));
@@ -560,6 +623,49 @@ int gbr_destroy(gbr_ctx* c) {
   (void)hipDeviceSynchronize();
   free_all(c);
   delete c;
+  return GBR_OK;
+}
+
+int gbr_memory(gbr_ctx* c, int64_t* device_bytes) {
+  if (!c || !device_bytes) return GBR_ERR_INVALID_ARG;
+  WorkspaceCaps k{};
+  k.frames = c->cap_frames; k.splats = c->cap_splats; k.pixels = c->cap_pixels; k.tiles = c->cap_tiles;
+  k.entries = c->cap_entries; k.bkt = c->cap_bkt; k.bkt_cells = c->cap_bkt_cells; k.scan_words = c->cap_scan_words;
+  k.tbits = c->cap_tbits; k.seg = c->cap_seg;
+  k.ci_pixels = c->ci_ones ? c->cap_pixels : 0;
+  k.ci_splats = c->ci_ones ? c->cap_splats : 0;
+  k.timing = c->t_stamp != nullptr;
+  *device_bytes = workspace_bytes(k);
+  return GBR_OK;
+}
+
+int gbr_plan_bytes(const gbr_config* cfg, int32_t B, const int64_t* gauss_offsets, const int32_t* widths,
+                   const int32_t* heights, int64_t entries, int64_t* device_bytes) {
+  if (!cfg || !gauss_offsets || !widths || !heights || !device_bytes || B < 1 || B > cfg->max_frames ||
+      entries < 0 || check_tiling(cfg->tile, cfg->chunk))
+    return GBR_ERR_INVALID_ARG;
+  WorkspaceCaps k = caps_at_create(cfg);
+  int64_t mfs = 0, n_tiles = 0, pix = 0;
+  int mft = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t nb = gauss_offsets[b + 1] - gauss_offsets[b];
+    if (nb < 0 || widths[b] < 1 || heights[b] < 1) return GBR_ERR_INVALID_ARG;
+    mfs = std::max(mfs, nb);
+    const int t = ((widths[b] + cfg->tile - 1) / cfg->tile) * ((heights[b] + cfg->tile - 1) / cfg->tile);
+    n_tiles += t;
+    mft = std::max(mft, t);
+    pix += (int64_t)widths[b] * heights[b];
+  }
+  if (gauss_offsets[B] > cfg->max_splats || pix > cfg->max_pixels || n_tiles > k.tiles) return GBR_ERR_CAPACITY;
+  int64_t bkt, cells, scan_words, tbits, seg;
+  pass_caps(B, mfs, n_tiles, mft, &bkt, &cells, &scan_words, &tbits, &seg);
+  // a pass grows a buffer only beyond its current capacity
+  if (bkt > k.bkt || cells > k.bkt_cells) { k.bkt = bkt; k.bkt_cells = cells; }
+  k.scan_words = std::max(k.scan_words, scan_words);
+  k.tbits = tbits;
+  k.seg = seg;
+  k.entries = std::max(k.entries, entries);
+  *device_bytes = workspace_bytes(k);
   return GBR_OK;
 }
 

@@ -60,6 +60,9 @@ _SIGS = {
     "gbr_destroy": ([_vp], ctypes.c_int),
     "gbr_reserve": ([_vp, _i64], ctypes.c_int),
     "gbr_set_tiling": ([_vp, _i32, _i32], ctypes.c_int),
+    "gbr_memory": ([_vp, ctypes.POINTER(_i64)], ctypes.c_int),
+    "gbr_plan_bytes": ([ctypes.POINTER(gbr_config), _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                        ctypes.POINTER(_i32), _i64, ctypes.POINTER(_i64)], ctypes.c_int),
     "gbr_blend": ([_vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp], ctypes.c_int),
     "gbr_render": ([_vp, _vp, ctypes.POINTER(_i64), ctypes.POINTER(gbr_camera), _i32, _vp, _vp], ctypes.c_int),
     "gbr_preprocess": ([_vp, _vp, ctypes.POINTER(_i64), ctypes.POINTER(gbr_camera), _i32, _vp], ctypes.c_int),
@@ -227,6 +230,27 @@ class Context:
 # ---------------------------------------------------------------- entry points (same names as the C ABI)
 def gbr_reserve(ctx: Context, max_entries: int) -> None:
     _check(lib().gbr_reserve(ctx.handle, int(max_entries)), "gbr_reserve")
+
+
+def gbr_memory(ctx: Context) -> int:
+    """Device bytes the context's workspace holds now."""
+    n = _i64()
+    _check(lib().gbr_memory(ctx.handle, ctypes.byref(n)), "gbr_memory")
+    return int(n.value)
+
+
+def gbr_plan_bytes(tile: int, chunk: int, max_frames: int, max_splats: int, max_pixels: int, max_entries: int,
+                   gauss_offsets, widths, heights, entries: int = 0) -> int:
+    """Device bytes a context of this configuration would hold after one pass
+    over frames of these Gaussian counts and sizes (host only, no GPU)."""
+    cfg = gbr_config(tile, chunk, 0, max_frames, max_splats, max_pixels, max_entries)
+    B = len(widths)
+    w = (_i32 * B)(*[int(x) for x in widths])
+    h = (_i32 * B)(*[int(x) for x in heights])
+    n = _i64()
+    _check(lib().gbr_plan_bytes(ctypes.byref(cfg), B, offsets_c(gauss_offsets), w, h, int(entries), ctypes.byref(n)),
+           "gbr_plan_bytes")
+    return int(n.value)
 
 
 def gbr_set_tiling(ctx: Context, tile: int, chunk: int) -> None:

@@ -9,9 +9,13 @@ through the avatar's weight MLP (Eq. 2), blends its Gaussian blendshapes
 * requests arrive continuously; a batch is formed at least every `window_s`
   seconds (or as soon as `max_batch` requests wait) from the queue in arrival
   order, for any free execution slot;
-* admission is by HBM footprint: a request joins a batch only while the
-  estimated device memory of all work in flight plus the batch stays within
-  `budget_bytes`;
+* admission is by HBM footprint: the executor holds `budget_bytes` of device
+  workspace, split over its slots (each slot's library context is sized so
+  that the bytes it holds, by the library's own accounting, fit its share);
+  a request joins a batch only while the batch fits its slot's capacity
+  (frames, Gaussians, pixels, tile entries) and the footprint of all work in
+  flight stays within the budget; requests held back by either limit are
+  counted as deferred;
 * each slot has its own stream and library context, so batches launched
   while others are still on the GPU overlap with them;
 * a batch holds frames of different avatars: per avatar, one MLP call and
@@ -49,15 +53,75 @@ class AvatarSpec:
     K: int
 
 
-def frame_footprint(N: int, width: int, height: int, entries_per_splat: int = 24) -> int:
-    """Estimated device bytes one frame needs while in flight: blended and
-    projected Gaussians plus per-splat bookkeeping, its tile entries (keys,
-    order, maps, gradient slots are not needed for rendering), the image and
-    the per-pixel state."""
-    per_splat = 64 + 48 + 16 + 4 * 6
-    per_entry = 4 * 3 + 1
-    per_pixel = 12 + 4 * 3
-    return N * per_splat + N * entries_per_splat * per_entry + width * height * per_pixel
+ENTRIES_PER_SPLAT = 32   # tile entries a frame's Gaussian is planned for (measured 18 at 512 x 512, distance 0.5)
+
+
+def _plan(ns, width, height, tile=16, entries_per_splat=ENTRIES_PER_SPLAT) -> int:
+    """Device bytes of a library context sized exactly for one pass over
+    frames of these Gaussian counts (the library's own accounting)."""
+    from . import gbr
+    B = len(ns)
+    offs = [0]
+    for n in ns:
+        offs.append(offs[-1] + int(n))
+    total = max(offs[-1], 1)
+    return gbr.gbr_plan_bytes(tile, 64, B, total, B * width * height, max(1, total * entries_per_splat), offs,
+                              [width] * B, [height] * B, total * entries_per_splat)
+
+
+def frame_footprint(N: int, width: int, height: int, n_max: int | None = None, tile: int = 16,
+                    entries_per_splat: int = ENTRIES_PER_SPLAT) -> int:
+    """Device bytes one frame of an avatar of N Gaussians adds to a pass: the
+    library's per-splat, per-pixel, per-tile and per-entry workspace, the tile
+    bitmap rows sized by the largest avatar in a batch (n_max), as the
+    difference of two planned contexts."""
+    n_max = max(N, n_max or N)
+    return (_plan([n_max, N], width, height, tile, entries_per_splat)
+            - _plan([n_max], width, height, tile, entries_per_splat))
+
+
+@dataclass
+class SlotSpec:
+    """Capacities of one execution slot's library context."""
+    max_frames: int
+    max_splats: int
+    max_pixels: int
+    max_entries: int
+    tile: int = 16
+    bytes: int = 0          # device bytes a context of these capacities holds after a full pass
+
+
+def slot_spec_for_budget(budget_bytes: int, n_slots: int, avatars_n, width: int, height: int, max_batch: int,
+                         tile: int = 16, entries_per_splat: int = ENTRIES_PER_SPLAT) -> SlotSpec:
+    """The largest Gaussian capacity S per slot whose context fits
+    budget / n_slots after its most demanding pass: max_batch frames (the
+    most tiles) holding S Gaussians, one of them of the largest avatar (the
+    longest tile bitmap rows)."""
+    from . import gbr
+    share = budget_bytes // n_slots
+    n_max = max(avatars_n)
+    W, H, mb = width, height, max_batch
+
+    def plan(S):
+        rest = S - n_max
+        k = mb - 1
+        ns = [n_max] + [max(1, rest // k + (1 if i < rest % k else 0)) for i in range(k)] if k else [n_max]
+        offs = [0]
+        for n in ns:
+            offs.append(offs[-1] + n)
+        return gbr.gbr_plan_bytes(tile, 64, mb, offs[-1], mb * W * H, offs[-1] * entries_per_splat, offs,
+                                  [W] * len(ns), [H] * len(ns), offs[-1] * entries_per_splat)
+
+    lo, hi = n_max, mb * n_max
+    if plan(lo) > share:
+        raise ValueError("the memory budget cannot hold a full batch with one frame of the largest avatar per slot")
+    while lo < hi:                               # the largest S with plan(S) <= share
+        mid = (lo + hi + 1) // 2
+        if plan(mid) <= share:
+            lo = mid
+        else:
+            hi = mid - 1
+    return SlotSpec(mb, lo, mb * W * H, lo * entries_per_splat, tile, plan(lo))
 
 
 @dataclass
@@ -67,14 +131,23 @@ class Batcher:
     budget_bytes: int
     max_batch: int = 16
     window_s: float = 0.002
+    slot: Optional[SlotSpec] = None          # capacity of a slot's context (None: the budget alone)
     queue: collections.deque = field(default_factory=collections.deque)
     inflight_bytes: int = 0
+    deferred: int = 0                        # times the head request waited for budget or slot capacity
+    _fp: dict = field(default_factory=dict)
 
     def footprint(self, r: Request) -> int:
-        return frame_footprint(self.avatars[r.avatar].N, r.cam.width, r.cam.height)
+        key = (r.avatar, r.cam.width, r.cam.height)
+        if key not in self._fp:
+            n_max = max(a.N for a in self.avatars)
+            self._fp[key] = frame_footprint(self.avatars[r.avatar].N, r.cam.width, r.cam.height, n_max)
+        return self._fp[key]
 
     def add(self, r: Request) -> None:
-        if self.footprint(r) > self.budget_bytes:
+        if self.footprint(r) > self.budget_bytes or (self.slot is not None and (
+                self.avatars[r.avatar].N > self.slot.max_splats or
+                r.cam.width * r.cam.height > self.slot.max_pixels)):
             raise ValueError("request larger than the whole memory budget")
         self.queue.append(r)
 
@@ -83,14 +156,24 @@ class Batcher:
         return bool(self.queue) and (len(self.queue) >= self.max_batch or now - self.queue[0].t_arrival >= self.window_s)
 
     def take(self) -> List[Request]:
-        """Requests for one batch, in arrival order, within the free budget."""
-        batch, used = [], 0
+        """Requests for one batch, in arrival order, within the free budget and
+        the slot's capacity."""
+        batch, used, splats, pixels = [], 0, 0, 0
         while self.queue and len(batch) < self.max_batch:
-            f = self.footprint(self.queue[0])
-            if self.inflight_bytes + used + f > self.budget_bytes:
+            r = self.queue[0]
+            f = self.footprint(r)
+            n = self.avatars[r.avatar].N
+            px = r.cam.width * r.cam.height
+            over = self.inflight_bytes + used + f > self.budget_bytes
+            if self.slot is not None:
+                over = over or splats + n > self.slot.max_splats or pixels + px > self.slot.max_pixels
+            if over:
+                self.deferred += 1
                 break
             batch.append(self.queue.popleft())
             used += f
+            splats += n
+            pixels += px
         self.inflight_bytes += used
         return batch
 
@@ -163,7 +246,8 @@ class Server:
         span = max(r.t_done for r in self.done) - min(r.t_arrival for r in self.done)
         return {"requests": len(self.done), "frames_per_s": len(self.done) / span if span > 0 else 0.0,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "mean_ms": float(lat.mean()), "max_inflight_bytes": int(self.max_inflight_bytes)}
+                "mean_ms": float(lat.mean()), "max_inflight_bytes": int(self.max_inflight_bytes),
+                "deferred": int(self.b.deferred)}
 
 
 class GpuExecutor:
@@ -171,7 +255,10 @@ class GpuExecutor:
 
     def __init__(self, avatars_bases, avatars_mlp, n_slots: int = 3, max_batch: int = 16, width: int = 512,
                  height: int = 512, d_in: int = 56, hidden: int = 256, tile: int = 16, chunk: int = 64,
-                 device: int = 0):
+                 device: int = 0, slot: Optional[SlotSpec] = None):
+        """With slot, every slot's context gets those capacities (a memory
+        budget's share, slot_spec_for_budget); without, room for max_batch
+        frames of the largest avatar."""
         import torch
 
         from . import gbr
@@ -185,11 +272,16 @@ class GpuExecutor:
         self.d_in, self.hidden = d_in, hidden
         self.n_slots = n_slots
         maxN = max(self.N)
-        max_splats = max_batch * maxN
+        if slot is None:
+            slot = SlotSpec(max_batch, max_batch * maxN, max_batch * width * height,
+                            max_batch * maxN * ENTRIES_PER_SPLAT, tile)
+        self.spec = slot
+        max_splats = slot.max_splats
+        self.overflows = 0
         self.slots = []
         for _ in range(n_slots):
-            ctx = gbr.Context(tile=tile, chunk=chunk, device=device, max_frames=max_batch, max_splats=max_splats,
-                              max_pixels=max_batch * width * height, max_entries=max_batch * maxN * 40)
+            ctx = gbr.Context(tile=slot.tile, chunk=chunk, device=device, max_frames=slot.max_frames,
+                              max_splats=max_splats, max_pixels=slot.max_pixels, max_entries=slot.max_entries)
             self.slots.append({
                 "ctx": ctx, "stream": torch.cuda.Stream(device=dev),
                 "theta_h": torch.zeros(max_batch, d_in, dtype=torch.float32).pin_memory(),
@@ -236,15 +328,27 @@ class GpuExecutor:
         return out
 
     def launch(self, slot: int, batch: List[Request]):
-        return (slot, self.enqueue(slot, batch))
+        return (slot, self.enqueue(slot, batch), batch)
 
     def is_done(self, handle) -> bool:
         return self.slots[handle[0]]["event"].query()
 
     def finish(self, handle) -> None:
-        st = self.gbr.gbr_query_status(self.slots[handle[0]]["ctx"], self.slots[handle[0]]["stream"])
+        """Reads the batch's status; a batch that overflowed the slot's tile
+        entries (more than planned) grows them and renders again."""
+        slot, _, batch = handle
+        S = self.slots[slot]
+        st = self.gbr.gbr_query_status(S["ctx"], S["stream"])
         if st.overflow:
-            raise RuntimeError("tile-entry overflow while serving: raise the slot capacity")
+            self.overflows += 1
+            self.gbr.gbr_reserve(S["ctx"], st.entries + st.entries // 4 + 4096)
+            self.enqueue(slot, batch)
+            if self.gbr.gbr_query_status(S["ctx"], S["stream"]).overflow:
+                raise RuntimeError("tile-entry overflow persists while serving")
+
+    def memory(self) -> int:
+        """Device bytes the slots' contexts hold (the library's accounting)."""
+        return sum(self.gbr.gbr_memory(S["ctx"]) for S in self.slots)
 
     def image(self, slot: int, offsets: dict, rid: int):
         o, n = offsets[rid]

@@ -86,3 +86,37 @@ def test_stream_is_served_with_overlap():
     assert stats["requests"] == 300
     assert stats["p99_ms"] < 1000.0
     ex.close()
+
+
+def test_workspace_accounting_matches_device_memory():
+    """The library's accounting of a context's workspace (what the serving
+    admission budgets) against the device memory it takes: gbr_memory after
+    a pass equals gbr_plan_bytes for that pass, and both match the drop of
+    free device memory up to the allocator's rounding."""
+    import torch
+    from paper_2503_12886_amd import gbr
+    from oracle import blendshape as bs
+    from gpu_util import dev, report
+    B, N, W = 4, 20_000, 256
+    bases = synth.make_scene(N, 4, seed=40)
+    raw = dev(bs.blend(bases, synth.make_weights(B, 4, seed=41)).astype(np.float32).reshape(B * N, 16))
+    cams = synth.make_cameras(B, W, W, seed=42)
+    images = torch.empty(gbr.image_numel(cams), device="cuda")
+    offs = [b * N for b in range(B + 1)]
+    cfg = dict(tile=16, chunk=64, max_frames=B, max_splats=B * N, max_pixels=B * W * W, max_entries=B * N * 32)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    ctx = gbr.Context(**cfg)
+    gbr.gbr_render(ctx, raw, offs, cams, images)
+    st = gbr.gbr_query_status(ctx)
+    assert not st.overflow
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    held = gbr.gbr_memory(ctx)
+    planned = gbr.gbr_plan_bytes(cfg["tile"], cfg["chunk"], B, B * N, B * W * W, B * N * 32, offs, [W] * B, [W] * B)
+    drop = free0 - free1
+    report("workspace accounting", held=held, planned=planned, device_drop=drop,
+           rel_diff=float(abs(drop - held) / held), entries=int(st.entries), entries_per_splat=float(st.entries / (B * N)))
+    assert held == planned
+    assert abs(drop - held) <= 0.05 * held + (32 << 20)
+    ctx.close()

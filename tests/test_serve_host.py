@@ -107,3 +107,34 @@ def test_admission_rejects_oversized_and_waits_for_budget():
     huge = Batcher(AV, budget_bytes=10, max_batch=8)
     with pytest.raises(ValueError):
         huge.add(Request(2, 0, np.zeros(56), cam, 0.0))
+
+
+def test_slot_capacity_from_the_memory_budget():
+    """A slot's Gaussian capacity is the largest whose planned workspace (the
+    library's accounting, its most demanding pass) fits the slot's share."""
+    from paper_2503_12886_amd import gbr
+    from paper_2503_12886_amd.serve import slot_spec_for_budget
+    ns = (20_000, 100_000, 50_000)
+    spec = slot_spec_for_budget(2 << 30, 3, ns, 512, 512, 8)
+    assert spec.bytes <= (2 << 30) // 3
+    assert 100_000 <= spec.max_splats < 8 * 100_000
+    with pytest.raises(ValueError):
+        slot_spec_for_budget(64 << 20, 3, ns, 512, 512, 8)
+    # the footprint of a frame grows with its Gaussians and includes the tile entries (57 B each)
+    assert frame_footprint(100_000, 512, 512) - frame_footprint(50_000, 512, 512, 100_000) > 50_000 * 32 * 57
+
+
+def test_batches_fit_the_slot_and_deferrals_are_counted():
+    from paper_2503_12886_amd.serve import SlotSpec
+    clock = FakeClock()
+    spec = SlotSpec(max_frames=8, max_splats=12_000, max_pixels=8 * 64 * 64, max_entries=12_000 * 32)
+    b = Batcher(AV, budget_bytes=1 << 40, max_batch=8, window_s=0.002, slot=spec)
+    ex = FakeExecutor(clock, n_slots=2, base=2e-3, per_frame=5e-4)
+    srv = Server(b, ex, clock=clock, sleep=clock.sleep)
+    stats = srv.run(make_requests(300, 4000.0, AV), t0=0.0)
+    assert stats["requests"] == 300
+    n_of = {i: a.N for i, a in enumerate(AV)}
+    done = {r.rid: r for r in srv.done}
+    for _, _, ids in ex.launched:
+        assert sum(n_of[done[i].avatar] for i in ids) <= spec.max_splats
+    assert stats["deferred"] > 0
