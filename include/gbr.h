@@ -230,6 +230,23 @@ int gbr_tangent_transform(gbr_ctx* ctx, const float* raw_t, const int32_t* tri, 
 int gbr_tangent_backward(gbr_ctx* ctx, const float* draw_d, const int32_t* tri, const float* frames, int32_t B,
                          int64_t N, int32_t F, float* draw_t, void* stream);
 
+/* gbr_render of tangent-space Gaussians with the transform applied inside
+   the pass (Sec. 3.1, Eq. 4): raw_t [B][N][16] as gbr_blend writes it (every
+   frame holds the same N Gaussians), bound to triangles tri [N] with
+   barycentric coordinates bary [N][3] of the mesh faces [F][3] (V vertices),
+   verts [B][V][3] one deformed mesh per frame, frames [B][F][16] the
+   per-(frame, triangle) records of gbr_tangent_frames.  Each Gaussian is
+   carried to its frame's mesh in the projection, with the same bits as
+   gbr_tangent_transform followed by gbr_render; the adjoint of this pass
+   (gbr_render_backward, gbr_backward) returns dL/draw_t in tangent space,
+   with the same bits as gbr_render_backward followed by
+   gbr_tangent_backward.  No deformed copy is stored.  The pointers must
+   stay valid until the pass's backward has run; indices out of
+   range are clamped.  Errors as gbr_render. */
+int gbr_render_tangent(gbr_ctx* ctx, const float* raw_t, const int32_t* tri, const float* bary, const float* verts,
+                       const int32_t* faces, const float* frames, int64_t N, int32_t V, int32_t F,
+                       const gbr_camera* cams, int32_t B, float* images, void* stream);
+
 /* Colour initialisation (Sec. 3.1, "Initialization", Eq. 3) after a render
    of a batch blended from one set of bases (every frame b holds Gaussians
    [b N, (b + 1) N) of the blend, as for gbr_backward).  For every Gaussian n

@@ -148,6 +148,8 @@ struct gbr_ctx {
   hipEvent_t t_ev[GBR_K_COUNT][2] = {};
   unsigned long long* t_stamp = nullptr;   // [GBR_K_COUNT][4]: start, sum of ticks, launches, unused
   int wall_khz = 0;                        // wall-clock rate of the device
+  // tangent-space binding of the last pass (gbr_render_tangent); off for gbr_render
+  TangentArgs tg{};
   // MLP state
   const float* mlp_theta = nullptr;
   int mlp_B = 0, mlp_din = 0, mlp_hidden = 0, mlp_K = 0;
@@ -189,6 +191,7 @@ PassArgs make_args(gbr_ctx* c) {
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
   a.big_list = c->big_list; a.big_count = c->big_count;
   a.n_iter = c->n_iter; a.n_contrib = c->n_contrib; a.t_final = c->t_final; a.part = c->part;
+  a.tg = c->tg;
   return a;
 }
 
@@ -699,12 +702,18 @@ int gbr_blend(gbr_ctx* c, const float* bases, const float* weights, int32_t B, i
   return GBR_OK;
 }
 
-int gbr_preprocess(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B,
-                   void* stream) {
-  if (!c) return GBR_ERR_INVALID_ARG;
+static int preprocess_impl(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B,
+                           void* stream) {
   int rc = set_pass(c, raw, goff, cams, B);
   if (rc) return rc;
   return enqueue_preprocess(c, raw, (hipStream_t)stream);
+}
+
+int gbr_preprocess(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B,
+                   void* stream) {
+  if (!c) return GBR_ERR_INVALID_ARG;
+  c->tg.on = 0;
+  return preprocess_impl(c, raw, goff, cams, B, stream);
 }
 
 int gbr_entry_count(gbr_ctx* c, void* stream, int64_t* entries) {
@@ -733,8 +742,26 @@ int gbr_rasterize(gbr_ctx* c, float* images, void* stream) {
 int gbr_render(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera* cams, int32_t B, float* images,
                void* stream) {
   if (!c || !images) return GBR_ERR_INVALID_ARG;
-  int rc = gbr_preprocess(c, raw, goff, cams, B, stream);
+  c->tg.on = 0;
+  int rc = preprocess_impl(c, raw, goff, cams, B, stream);
   if (rc) return rc;
+  return enqueue_rasterize(c, images, (hipStream_t)stream);
+}
+
+int gbr_render_tangent(gbr_ctx* c, const float* raw_t, const int32_t* tri, const float* bary, const float* verts,
+                       const int32_t* faces, const float* frames, int64_t N, int32_t V, int32_t F,
+                       const gbr_camera* cams, int32_t B, float* images, void* stream) {
+  if (!c || !raw_t || !tri || !bary || !verts || !faces || !frames || !images || N < 1 || V < 1 || F < 1 || B < 1)
+    return GBR_ERR_INVALID_ARG;
+  if ((int64_t)B * N > c->cap_splats) return GBR_ERR_CAPACITY;
+  std::vector<int64_t> goff(B + 1);
+  for (int b = 0; b <= B; ++b) goff[b] = (int64_t)b * N;
+  c->tg = TangentArgs{tri, bary, verts, faces, frames, N, V, F, 1, 0};
+  int rc = preprocess_impl(c, raw_t, goff.data(), cams, B, stream);
+  if (rc) {
+    c->tg.on = 0;
+    return rc;
+  }
   return enqueue_rasterize(c, images, (hipStream_t)stream);
 }
 

@@ -47,6 +47,24 @@ struct StatusDev {
   float pad1;
 };
 
+// Tangent-space binding of a pass (Sec. 3.1, Eq. 4): when `on`, the pass
+// reads tangent-space Gaussians (every frame holds the same N, bound to
+// triangle tri[n] at barycentric coordinates bary[n]), carries each to its
+// frame's deformed mesh inside the projection, and the adjoint returns the
+// gradient in tangent space.  frames: [B][F][16] per-(frame, triangle) TBN
+// matrix and frame quaternion (gbr_tangent_frames).
+struct TangentArgs {
+  const int32_t* tri;
+  const float* bary;
+  const float* verts;       // [B][V][3]
+  const int32_t* faces;     // [F][3]
+  const float* frames;      // [B][F][16]
+  int64_t N;
+  int32_t V, F;
+  int32_t on;
+  int32_t pad;
+};
+
 // Everything the pass kernels need, passed by value.
 constexpr int kMinmaxStride = 32;
 
@@ -103,6 +121,7 @@ struct PassArgs {
   uint8_t* part_flag;       // [E] 1 where the entry's partial is written; zeroed at allocation, set by the
                             // backward compositing, and reset to 0 by the gather that reads it
   uint8_t* cmask;           // [E][4] byte w = 1: some pixel of quadrant w of the tile took this entry (forward)
+  TangentArgs tg;           // tangent-space binding (tg.on = 0: the pass reads deformed-space Gaussians)
 };
 
 __device__ __forceinline__ int frame_of_tile(const FrameDev* frames, int B, int g) {

@@ -3,6 +3,7 @@
 // the tile's pixels without atomics, a fixed-order gather per splat, and the
 // adjoint of activation + EWA projection.  Also the photometric loss.
 #include "gbr_internal.h"
+#include "tangent_ops.h"
 
 namespace gbr {
 
@@ -357,7 +358,11 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   for (int k = 0; k < 9; ++k) acc[k] = draw[s * kNF + k];
 
   // ---- recompute the forward quantities (float64) ----
-  const float* gp = raw + s * kNF;
+  const float4* src = reinterpret_cast<const float4*>(raw + s * kNF);
+  float4 v0 = src[0], v1 = src[1];
+  const float4 v2 = src[2];
+  if (a.tg.on) tangent_deform(a.tg, b, n, v0, v1, v0, v1);   // as the forward pass did
+  const float gp[11] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z};
   const double mu0 = gp[0], mu1 = gp[1], mu2 = gp[2];
   double R[9], tcam[3];
   for (int i = 0; i < 9; ++i) R[i] = F.R[i];
@@ -457,8 +462,11 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   res[10] = (float)((double)acc[5] * (1.0 - o));
   res[11] = acc[6]; res[12] = acc[7]; res[13] = acc[8];
   res[14] = 0.0f; res[15] = 0.0f;
-  out[0] = make_float4(res[0], res[1], res[2], res[3]);
-  out[1] = make_float4(res[4], res[5], res[6], res[7]);
+  float4 o0 = make_float4(res[0], res[1], res[2], res[3]);
+  float4 o1 = make_float4(res[4], res[5], res[6], res[7]);
+  if (a.tg.on) tangent_adjoint(tangent_frame(a.tg, b, n), o0, o1, o0, o1);   // back to tangent space
+  out[0] = o0;
+  out[1] = o1;
   out[2] = make_float4(res[8], res[9], res[10], res[11]);
   out[3] = make_float4(res[12], res[13], res[14], res[15]);
 }

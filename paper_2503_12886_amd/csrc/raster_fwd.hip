@@ -2,6 +2,7 @@
 // every (frame, Gaussian), tile binning, per-tile depth order and front-to-back
 // compositing, for all frames of a batch with no host synchronisation.
 #include "gbr_device.h"
+#include "tangent_ops.h"
 
 namespace gbr {
 
@@ -139,11 +140,11 @@ struct Projected {
   int x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ void project_gaussian(const float* __restrict__ g, const FrameDev& F, Projected& p) {
+// v0, v1, v2: the first three float4 of a blended record (position,
+// quaternion, log-scales, opacity logit, red).
+__device__ __forceinline__ void project_gaussian(const float4 v0, const float4 v1, const float4 v2, const FrameDev& F,
+                                                 Projected& p) {
   p.valid = false;
-  const float4 v0 = reinterpret_cast<const float4*>(g)[0];
-  const float4 v1 = reinterpret_cast<const float4*>(g)[1];
-  const float4 v2 = reinterpret_cast<const float4*>(g)[2];
   const double mu0 = v0.x, mu1 = v0.y, mu2 = v0.z;
   const double tx = (double)F.R[0] * mu0 + (double)F.R[1] * mu1 + (double)F.R[2] * mu2 + (double)F.t[0];
   const double ty = (double)F.R[3] * mu0 + (double)F.R[4] * mu1 + (double)F.R[5] * mu2 + (double)F.t[1];
@@ -220,10 +221,13 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
   uint32_t dmin = 0xffffffffu, dmax = 0u;
   if (n < F.gauss_count) {
     const int64_t s = F.gauss_base + n;
-    const float4 col = reinterpret_cast<const float4*>(raw + s * kNF)[2];   // colour: .w, then the next row
-    const float4 col2 = reinterpret_cast<const float4*>(raw + s * kNF)[3];
+    const float4* src = reinterpret_cast<const float4*>(raw + s * kNF);
+    float4 v0 = src[0], v1 = src[1];
+    const float4 col = src[2];              // log-scales 1-2, opacity logit, red
+    const float4 col2 = src[3];             // green, blue
+    if (a.tg.on) tangent_deform(a.tg, b, n, v0, v1, v0, v1);   // tangent space -> frame b's mesh
     Projected p;
-    project_gaussian(raw + s * kNF, F, p);
+    project_gaussian(v0, v1, col, F, p);
     float* rec = a.rec + s * kRecF;
     int4 r = make_int4(0, 0, -1, -1);
     uint32_t count = 0, key = 0xffffffffu;

@@ -9,12 +9,11 @@
 // attributes pass through.  The adjoint is dx_T = R^T dx_D,
 // dq_T = conj(q_R) (x) dq_D.  Frame quantities are formed in float64 from
 // the float32 inputs and rounded once.
-#include "gbr_internal.h"
+#include "tangent_ops.h"
 
 namespace gbr {
 
 // frames: [B][F][kFrameF]: R row-major (R[i][j] = component i of column j), q_R (w, x, y, z)
-constexpr int kFrameF = 16;
 
 __device__ __forceinline__ void quat_of_frame(const double G[9], double q[4]) {
   const double tr = G[0] + G[4] + G[8];
@@ -88,73 +87,34 @@ __global__ __launch_bounds__(256) void tbn_kernel(const float* __restrict__ vert
   out[13] = out[14] = out[15] = 0.0f;
 }
 
-__device__ __forceinline__ void qmul(const double p[4], const double q[4], double o[4]) {
-  o[0] = p[0] * q[0] - p[1] * q[1] - p[2] * q[2] - p[3] * q[3];
-  o[1] = p[0] * q[1] + p[1] * q[0] + p[2] * q[3] - p[3] * q[2];
-  o[2] = p[0] * q[2] - p[1] * q[3] + p[2] * q[0] + p[3] * q[1];
-  o[3] = p[0] * q[3] + p[1] * q[2] - p[2] * q[1] + p[3] * q[0];
-}
-
-__global__ __launch_bounds__(256) void tangent_fwd_kernel(const float* __restrict__ raw_t,
-                                                          const int32_t* __restrict__ tri,
-                                                          const float* __restrict__ bary,
-                                                          const float* __restrict__ verts,
-                                                          const int32_t* __restrict__ faces,
-                                                          const float* __restrict__ frames, int B, int64_t N, int V,
-                                                          int F, float* __restrict__ raw_d) {
+__global__ __launch_bounds__(256) void tangent_fwd_kernel(const float* __restrict__ raw_t, TangentArgs tg, int B,
+                                                          float* __restrict__ raw_d) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)B * N) return;
-  const int b = (int)(i / N);
-  const int64_t n = i % N;
-  const int f = min(max(tri[n], 0), F - 1);
-  const float* fr = frames + ((int64_t)b * F + f) * kFrameF;
+  if (i >= (int64_t)B * tg.N) return;
+  const int b = (int)(i / tg.N);
+  const int64_t n = i % tg.N;
   const float4* src = reinterpret_cast<const float4*>(raw_t + i * kNF);
   float4* dst = reinterpret_cast<float4*>(raw_d + i * kNF);
-  const float4 a0 = src[0], a1 = src[1];
-  const float* vb = verts + (int64_t)b * V * 3;
-  double t[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < 3; ++k) {
-    const int v = min(max(faces[3 * f + k], 0), V - 1);
-    const double w = bary[n * 3 + k];
-    for (int c = 0; c < 3; ++c) t[c] += w * (double)vb[(int64_t)v * 3 + c];
-  }
-  const double x[3] = {a0.x, a0.y, a0.z};
-  double xd[3];
-  for (int r = 0; r < 3; ++r)
-    xd[r] = (double)fr[3 * r] * x[0] + (double)fr[3 * r + 1] * x[1] + (double)fr[3 * r + 2] * x[2] + t[r];
-  const double qr[4] = {fr[9], fr[10], fr[11], fr[12]};
-  const double qt[4] = {a0.w, a1.x, a1.y, a1.z};
-  double qd[4];
-  qmul(qr, qt, qd);
-  dst[0] = make_float4((float)xd[0], (float)xd[1], (float)xd[2], (float)qd[0]);
-  dst[1] = make_float4((float)qd[1], (float)qd[2], (float)qd[3], a1.w);
+  float4 d0, d1;
+  tangent_deform(tg, b, n, src[0], src[1], d0, d1);
+  dst[0] = d0;
+  dst[1] = d1;
   dst[2] = src[2];
   dst[3] = src[3];
 }
 
-__global__ __launch_bounds__(256) void tangent_bwd_kernel(const float* __restrict__ draw_d,
-                                                          const int32_t* __restrict__ tri,
-                                                          const float* __restrict__ frames, int B, int64_t N, int F,
+__global__ __launch_bounds__(256) void tangent_bwd_kernel(const float* __restrict__ draw_d, TangentArgs tg, int B,
                                                           float* __restrict__ draw_t) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)B * N) return;
-  const int b = (int)(i / N);
-  const int64_t n = i % N;
-  const int f = min(max(tri[n], 0), F - 1);
-  const float* fr = frames + ((int64_t)b * F + f) * kFrameF;
+  if (i >= (int64_t)B * tg.N) return;
+  const int b = (int)(i / tg.N);
+  const int64_t n = i % tg.N;
   const float4* src = reinterpret_cast<const float4*>(draw_d + i * kNF);
   float4* dst = reinterpret_cast<float4*>(draw_t + i * kNF);
-  const float4 g0 = src[0], g1 = src[1];
-  const double gx[3] = {g0.x, g0.y, g0.z};
-  double dx[3];
-  for (int c = 0; c < 3; ++c)
-    dx[c] = (double)fr[c] * gx[0] + (double)fr[3 + c] * gx[1] + (double)fr[6 + c] * gx[2];   // R^T gx
-  const double qc[4] = {fr[9], -(double)fr[10], -(double)fr[11], -(double)fr[12]};
-  const double gq[4] = {g0.w, g1.x, g1.y, g1.z};
-  double dq[4];
-  qmul(qc, gq, dq);
-  dst[0] = make_float4((float)dx[0], (float)dx[1], (float)dx[2], (float)dq[0]);
-  dst[1] = make_float4((float)dq[1], (float)dq[2], (float)dq[3], g1.w);
+  float4 o0, o1;
+  tangent_adjoint(tangent_frame(tg, b, n), src[0], src[1], o0, o1);
+  dst[0] = o0;
+  dst[1] = o1;
   dst[2] = src[2];
   dst[3] = src[3];
 }
@@ -171,16 +131,16 @@ void launch_tangent_fwd(const float* raw_t, const int32_t* tri, const float* bar
                         hipStream_t s) {
   const int64_t n = (int64_t)B * N;
   if (n == 0) return;
-  hipLaunchKernelGGL(tangent_fwd_kernel, dim3(div_up(n, 256)), dim3(256), 0, s, raw_t, tri, bary, verts, faces,
-                     frames, B, N, V, F, raw_d);
+  const TangentArgs tg{tri, bary, verts, faces, frames, N, V, F, 1, 0};
+  hipLaunchKernelGGL(tangent_fwd_kernel, dim3(div_up(n, 256)), dim3(256), 0, s, raw_t, tg, B, raw_d);
 }
 
 void launch_tangent_bwd(const float* draw_d, const int32_t* tri, const float* frames, int B, int64_t N, int F,
                         float* draw_t, hipStream_t s) {
   const int64_t n = (int64_t)B * N;
   if (n == 0) return;
-  hipLaunchKernelGGL(tangent_bwd_kernel, dim3(div_up(n, 256)), dim3(256), 0, s, draw_d, tri, frames, B, N, F,
-                     draw_t);
+  const TangentArgs tg{tri, nullptr, nullptr, nullptr, frames, N, 0, F, 1, 0};
+  hipLaunchKernelGGL(tangent_bwd_kernel, dim3(div_up(n, 256)), dim3(256), 0, s, draw_d, tg, B, draw_t);
 }
 
 }  // namespace gbr

@@ -76,6 +76,8 @@ _SIGS = {
     "gbr_tangent_frames": ([_vp, _vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
     "gbr_tangent_transform": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _i32, _i32, _vp, _vp], ctypes.c_int),
     "gbr_tangent_backward": ([_vp, _vp, _vp, _vp, _i32, _i64, _i32, _vp, _vp], ctypes.c_int),
+    "gbr_render_tangent": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i32, _i32, ctypes.POINTER(gbr_camera), _i32,
+                            _vp, _vp], ctypes.c_int),
     "gbr_loss": ([_vp, _vp, _vp, _i32, _vp, _vp], ctypes.c_int),
     "gbr_mlp_forward": ([_vp, _vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
     "gbr_mlp_backward": ([_vp, _vp, _vp, _vp, _vp], ctypes.c_int),
@@ -390,6 +392,22 @@ def gbr_tangent_backward(ctx: Context, draw_d, tri, frames, draw_t, stream=None)
     _check(lib().gbr_tangent_backward(ctx.handle, _f32dev(draw_d, "draw_d"), _i32dev(tri, "tri"),
                                       _f32dev(frames, "frames"), B, N, F, _f32dev(draw_t, "draw_t", B * N * 16),
                                       _stream(stream)), "gbr_tangent_backward")
+
+
+def gbr_render_tangent(ctx: Context, raw_t, tri, bary, verts, faces, frames, cams, images, stream=None) -> None:
+    """gbr_render of tangent-space Gaussians raw_t [B][N][16], carried to
+    each frame's mesh (verts [B][V][3]) inside the pass; the backward then
+    returns tangent-space gradients."""
+    B, N, _ = raw_t.shape
+    if len(cams) != B or verts.shape[0] != B or frames.shape[0] != B:
+        raise ValueError("gbr_render_tangent: one camera, mesh and frame table per frame")
+    V, F = verts.shape[1], faces.shape[0]
+    _f32dev(images, "images", image_numel(cams))
+    ctx.passes += 1
+    _check(lib().gbr_render_tangent(ctx.handle, _f32dev(raw_t, "raw_t"), _i32dev(tri, "tri"), _f32dev(bary, "bary"),
+                                    _f32dev(verts, "verts"), _i32dev(faces, "faces"),
+                                    _f32dev(frames, "frames", B * F * 16), N, V, F, cameras_c(cams), B, _ptr(images),
+                                    _stream(stream)), "gbr_render_tangent")
 
 
 def gbr_color_init(ctx: Context, targets, bases, done, delta: float = 0.1, stream=None) -> None:

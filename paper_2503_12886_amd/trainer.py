@@ -134,9 +134,6 @@ class Trainer:
         F = self.faces.shape[0]
         self.verts = torch.zeros(cfg.B, n_verts, 3, device=dev, dtype=torch.float32)
         self.frames = torch.zeros(cfg.B, F, 16, device=dev, dtype=torch.float32)
-        self.raw_d = torch.zeros_like(self.raw)
-        self.draw_d = torch.zeros_like(self.raw)
-        self.draw_t = torch.zeros_like(self.raw)
 
     def set_batch(self, theta: np.ndarray, targets: np.ndarray, cams: list, verts=None) -> None:
         """Copy one batch of (tracking vector, target image, camera[, deformed mesh])
@@ -176,7 +173,7 @@ class Trainer:
         with self.torch.cuda.stream(self.stream):
             gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
             gbr.gbr_blend(c, self.bases, self.psi, self.raw)
-            gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.targets)
+            self._render(self.targets)
             st = gbr.gbr_query_status(c, self.stream)
         if st.overflow:
             self._grow(st.entries)
@@ -206,15 +203,19 @@ class Trainer:
         with self.torch.cuda.stream(self.stream):
             self._enqueue_grads()
 
-    def _to_deformed(self):
-        """The blended Gaussians as rendered: carried to the frames' meshes when
-        a mesh is bound (enqueued on the current stream)."""
-        if getattr(self, "verts", None) is None:
-            return self.raw
+    def _render(self, images) -> None:
+        """The batch's render of the blended Gaussians (enqueued on the
+        current stream).  With a bound mesh they live in tangent space: the
+        per-(frame, triangle) frames are formed, and the pass carries every
+        Gaussian to its frame's mesh inside the projection; its backward then
+        returns tangent-space gradients."""
         c = self.ctx
+        if getattr(self, "verts", None) is None:
+            gbr.gbr_render(c, self.raw, self.offsets, self.cams, images)
+            return
         gbr.gbr_tangent_frames(c, self.verts, self.faces, self.face_uv, self.frames)
-        gbr.gbr_tangent_transform(c, self.raw, self.tri, self.bary, self.verts, self.faces, self.frames, self.raw_d)
-        return self.raw_d
+        gbr.gbr_render_tangent(c, self.raw, self.tri, self.bary, self.verts, self.faces, self.frames, self.cams,
+                               images)
 
     def _enqueue_grads(self, fused: bool = False):
         """Forward, loss and backward. With fused, dbases is left to the
@@ -222,19 +223,13 @@ class Trainer:
         c, cfg = self.ctx, self.cfg
         gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
         gbr.gbr_blend(c, self.bases, self.psi, self.raw)
-        gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.images)
+        self._render(self.images)
         gbr.gbr_loss(c, self.images, self.targets, cfg.loss, self.dimages)
         dbases = None if fused else self.dbases
-        if getattr(self, "verts", None) is None:
-            gbr.gbr_render_backward(c, self.dimages, self.draw)
-            draw = self.draw
-        else:
-            gbr.gbr_render_backward(c, self.dimages, self.draw_d)
-            gbr.gbr_tangent_backward(c, self.draw_d, self.tri, self.frames, self.draw_t)
-            draw = self.draw_t
-        gbr.gbr_blend_backward(c, draw, self.bases, self.psi, dbases, self.dpsi)
+        gbr.gbr_render_backward(c, self.dimages, self.draw)     # tangent space when a mesh is bound
+        gbr.gbr_blend_backward(c, self.draw, self.bases, self.psi, dbases, self.dpsi)
         gbr.gbr_mlp_backward(c, self.mlp, self.dpsi, self.dmlp)
-        return draw
+        return self.draw
 
     def _enqueue_step(self) -> None:
         c, cfg = self.ctx, self.cfg
@@ -387,7 +382,7 @@ class Trainer:
             with self.torch.cuda.stream(self.stream):
                 gbr.gbr_mlp_forward(c, self.mlp, self.theta, cfg.d_in, cfg.hidden, cfg.K, self.psi)
                 gbr.gbr_blend(c, self.bases, self.psi, self.raw)
-                gbr.gbr_render(c, self._to_deformed(), self.offsets, self.cams, self.images)
+                self._render(self.images)
                 st = gbr.gbr_query_status(c, self.stream)
                 if not st.overflow:
                     gbr.gbr_color_init(c, self.targets, self.bases, self.ci_done, delta)

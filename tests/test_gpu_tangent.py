@@ -130,3 +130,43 @@ def test_trainer_in_tangent_space():
     assert runs[0][0] == runs[1][0]
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][2], runs[1][2])
     assert runs[0][0][-1] < runs[0][0][0]
+
+
+def test_transform_inside_the_pass_equals_separate_kernels():
+    """gbr_render_tangent (the transform applied in the projection, its
+    adjoint in the projection adjoint) gives the same bits as the stand-alone
+    transform, render, render adjoint and tangent adjoint."""
+    import torch
+    vb, faces, uv, tri, bary, raw_t = _mesh_case(B=3, N=3000, seed=4)
+    B, N = raw_t.shape[:2]
+    cams = synth.make_cameras(B, 96, 80, seed=8)
+    rng = np.random.default_rng(9)
+    dimg = dev(np.concatenate([rng.normal(size=(3, c.height, c.width)).ravel() for c in cams]).astype(np.float32))
+    # separate kernels
+    ctx = make_ctx()
+    frames, raw_d, Tr = _gpu_transform(ctx, vb, faces, uv, tri, bary, raw_t)
+    img_sep = torch.empty(gbr.image_numel(cams), device="cuda")
+    gbr.gbr_render(ctx, raw_d, [b * N for b in range(B + 1)], cams, img_sep)
+    assert not gbr.gbr_query_status(ctx).overflow
+    draw_d = torch.zeros(B, N, 16, device="cuda")
+    gbr.gbr_render_backward(ctx, dimg, draw_d)
+    draw_sep = torch.zeros_like(draw_d)
+    gbr.gbr_tangent_backward(ctx, draw_d, Tr, frames, draw_sep)
+    # inside the pass
+    ctx2 = make_ctx()
+    V, Fd, Ba, Rt = dev(vb), dev(faces), dev(bary), dev(raw_t)   # the backward re-reads them: keep them alive
+    img_in = torch.empty_like(img_sep)
+    gbr.gbr_render_tangent(ctx2, Rt, Tr, Ba, V, Fd, frames, cams, img_in)
+    assert not gbr.gbr_query_status(ctx2).overflow
+    draw_in = torch.zeros_like(draw_d)
+    gbr.gbr_render_backward(ctx2, dimg, draw_in)
+    torch.cuda.synchronize()
+    assert torch.equal(img_in, img_sep)
+    assert torch.equal(draw_in, draw_sep)
+    # a plain render afterwards is not transformed
+    img_plain = torch.empty_like(img_sep)
+    gbr.gbr_render(ctx2, raw_d, [b * N for b in range(B + 1)], cams, img_plain)
+    torch.cuda.synchronize()
+    assert torch.equal(img_plain, img_sep)
+    ctx.close()
+    ctx2.close()
