@@ -9,7 +9,7 @@
  *             binning + depth order, front-to-back alpha compositing; a
  *             whole batch of frames, each with its own Gaussian set and
  *             camera, in one pass with no host synchronisation (Sec. 3.2,
- *             "Batch-parallel Gaussian Rasterization", Fig. 4c)
+ *             "Batch-parallel Gaussian Rasterization", Fig. 5c)
  *   backward  dL/dimages -> dL/d(blended Gaussians) -> dL/dbases, dL/dweights
  *             (the bases and weights are what training optimises, Sec. 3.2
  *             and Sec. A.3)
@@ -143,7 +143,7 @@ int gbr_blend(gbr_ctx* ctx, const float* bases, const float* weights, int32_t B,
 int gbr_render(gbr_ctx* ctx, const float* raw, const int64_t* gauss_offsets, const gbr_camera* cams, int32_t B,
                float* images, void* stream);
 /* The two halves of gbr_render, for callers that want the paper's per-frame
-   scheme (Fig. 4a/4b): gbr_preprocess (activation, projection, per-frame
+   scheme (Fig. 5a/5b): gbr_preprocess (activation, projection, per-frame
    depth order, per-tile rank bitmaps and entry counts), then gbr_entry_count
    (a host synchronisation that returns the number of tile entries, and
    grows the capacity if needed), then gbr_rasterize (compositing). */

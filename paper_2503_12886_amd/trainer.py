@@ -1,15 +1,15 @@
 """Training-step driver: the sequence of library calls that makes one
 optimisation step of the reduced-Gaussian-blendshape avatar, in two schemes.
 
-* batched (Sec. 3.2, Fig. 4c): B frames per step -- weights MLP (Eq. 2),
+* batched (Sec. 3.2, Fig. 5c): B frames per step -- weights MLP (Eq. 2),
   blend (Eq. 1), one batch-parallel render, L1 loss with random backgrounds
   (Sec. 3.2), backward to bases and MLP, Adam with per-attribute learning
   rates (Sec. A.3); one host synchronisation (the status read) per step.
   The whole step can be captured once as a graph and replayed.
-* per-frame (Fig. 4a, "w/o batch parallel"): one frame per optimisation
+* per-frame (Fig. 5a, "w/o batch parallel"): one frame per optimisation
   step, preprocess -> host synchronisation to size the tile lists ->
   rasterize, and an Adam step per frame.
-* naive batch-parallel (Fig. 4b, Table 4 middle row): one optimisation step
+* naive batch-parallel (Fig. 5b, Table 4 middle row): one optimisation step
   per batch (batched MLP, blend, blend adjoint, MLP adjoint, Adam), but the
   frames are rasterised one after another, each with its own host
   synchronisation between preprocess and rasterize.
@@ -394,7 +394,7 @@ class Trainer:
     # ---------------------------------------------------------------- naive batch-parallel scheme
     def naive_batch_grads(self) -> None:
         """Gradients of one batch, rasterising frame by frame with a host
-        synchronisation per frame (Fig. 4b).  Each frame's loss is normalised
+        synchronisation per frame (Fig. 5b).  Each frame's loss is normalised
         over that frame alone: the gradients are B times the batched step's
         (a constant factor that Adam's update does not see)."""
         with self.torch.cuda.stream(self.stream):
@@ -413,7 +413,7 @@ class Trainer:
             dimg = self.dimages[b * 3 * npix:(b + 1) * 3 * npix]
             tgt = self.targets[b * 3 * npix:(b + 1) * 3 * npix]
             gbr.gbr_preprocess(c, self.raw[b:b + 1], [0, cfg.N], [self.cams[b]])
-            gbr.gbr_entry_count(c)                      # the synchronisation of each frame (Fig. 4b)
+            gbr.gbr_entry_count(c)                      # the synchronisation of each frame (Fig. 5b)
             gbr.gbr_rasterize(c, img)
             gbr.gbr_loss(c, img, tgt, cfg.loss, dimg)
             gbr.gbr_render_backward(c, dimg, self.draw[b:b + 1])

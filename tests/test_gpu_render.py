@@ -174,7 +174,7 @@ def test_overflow_is_reported_and_recoverable():
 
 
 def test_per_frame_scheme_matches_batched():
-    """preprocess -> host sync on the entry count -> rasterize (Fig. 4a)."""
+    """preprocess -> host sync on the entry count -> rasterize (Fig. 5a)."""
     import torch
     raw, cams, N = batch_case(B=3, N=2000, seed=9)
     ctx = make_ctx(max_entries=64)

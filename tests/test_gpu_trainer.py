@@ -94,7 +94,7 @@ def test_per_frame_scheme_runs_one_step_per_frame():
 
 
 def test_naive_batch_scheme_gives_the_batched_gradients():
-    """Rasterising the frames one after another (Fig. 4b) changes when the
+    """Rasterising the frames one after another (Fig. 5b) changes when the
     work runs, not what it computes: with each frame's loss normalised over
     that frame alone, every gradient is exactly B (= 4, a power of two) times
     the batched step's."""
