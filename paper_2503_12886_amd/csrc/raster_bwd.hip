@@ -555,10 +555,21 @@ __global__ __launch_bounds__(kLossThreads) void loss_kernel(const float* __restr
   (void)status;
 }
 
+// Thread t adds partials t, t + 256, ... in order (16 loads in flight at a
+// time; a missing one adds 0), then a fixed tree over the threads.
 __global__ void loss_final_kernel(const double* __restrict__ partials, int nb, int64_t n, StatusDev* status) {
   __shared__ double sm[256];
   double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) s += partials[i];
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 16 * 256) {
+    double v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int i = i0 + j * 256;
+      v[j] = i < nb ? partials[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s += v[j];
+  }
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

@@ -760,23 +760,29 @@ __global__ __launch_bounds__(64, T == 32 ? 1 : 7) void composite_fwd_kernel(Pass
           // the front-to-back step: alpha below 1/255 is skipped (w = 0, Te
           // passes unchanged), T (1 - alpha) < 1e-4 stops the pixel before
           // this entry (Te -> -T); a stopped pixel has Te <= 0, so its tn <= 0
-          // stops it again (Te kept: min(Te, -Te)) and it takes nothing
+          // stops it again (Te kept: -|Te|) and it takes nothing
           const float w = (al[u] >= kAlphaMin) ? fminf(al[u], kAlphaMax) : 0.0f;
-          const float tn = Te[p] * (1.0f - w);
+          const float tn = __builtin_fmaf(-w, Te[p], Te[p]);   // T (1 - alpha), rounded once
           const bool stop = tn < kTMin;
           const float wgt = stop ? 0.0f : w * Te[p];
           C0[p] = __builtin_fmaf(wgt, r1[u].z, C0[p]);
           C1[p] = __builtin_fmaf(wgt, r1[u].w, C1[p]);
           C2[p] = __builtin_fmaf(wgt, cb2[u], C2[p]);
-          float te_neg;
-          asm("v_min_f32 %0, %1, -%1" : "=v"(te_neg) : "v"(Te[p]));
-          Te[p] = stop ? te_neg : tn;
+          Te[p] = stop ? -fabsf(Te[p]) : tn;   // one select with source modifiers
           const bool take = wgt > 0.0f;   // w >= 1/255 and Te >= 1e-4: never 0 when taken
           lastk[p] = take ? (uint32_t)(k + u + 1) : lastk[p];
           tm[u] |= __builtin_amdgcn_ballot_w64(take);
         }
       }
-      const uint32_t m4 = (tm[0] ? 1u : 0u) | (tm[1] ? 2u : 0u) | (tm[2] ? 4u : 0u) | (tm[3] ? 8u : 0u);
+      // bit u: some pixel took candidate k + u; formed on the scalar unit
+      // (the masks are uniform; the compiler builds it with vector ORs)
+      uint32_t m4 = 0u;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        uint32_t bit;
+        asm("s_cmp_lg_u64 %1, 0\n\ts_cselect_b32 %0, %2, 0" : "=s"(bit) : "s"(tm[u]), "i"(1 << u) : "scc");
+        m4 |= bit;
+      }
       took4 = (lane == k / U) ? m4 : took4;
       bool mine_now = false;
 #pragma unroll
