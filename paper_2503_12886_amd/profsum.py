@@ -13,7 +13,11 @@ Two reports, both from rocprofv3's CSV output (``--output-format csv``):
   in the same run (the copy reads N and writes N bytes).  With ``--json`` it
   also writes the per-launch bytes, the factors and a hash of the kernel's
   source files, so a reader can tell when the figure went stale; with
-  ``--window FIRST:COUNT`` only those launches of the kernel are averaged.
+  ``--window FIRST:COUNT`` only those launches of the kernel are averaged;
+* ``counters DIR [--kernels A,B] [--window KERNEL:FIRST:COUNT ...]``: every
+  counter of a ``--pmc`` run, summed over counter instances and averaged per
+  dispatch, one row per kernel (a window restricts that kernel's average to
+  those launches).
 
 Usage:
   python -m paper_2503_12886_amd.profsum stats out/stats --window composite_bwd:24:100
@@ -127,6 +131,35 @@ def _mean_for(disp, match, win=None) -> tuple:
     return sum(vals) / len(vals), len(vals)
 
 
+def counters(d: str, kernels=None, windows=None) -> str:
+    """Markdown table: kernel, dispatches averaged, then each counter's mean
+    per dispatch (summed over its instances)."""
+    rows = _rows(_find(d, "counter_collection.csv"))
+    names = sorted({r["Counter_Name"] for r in rows})
+    per = collections.defaultdict(lambda: collections.defaultdict(float))   # dispatch -> counter -> value
+    kname = {}
+    for r in rows:
+        per[r["Dispatch_Id"]][r["Counter_Name"]] += float(r["Counter_Value"])
+        kname[r["Dispatch_Id"]] = short_name(r["Kernel_Name"])
+    by_kernel = collections.defaultdict(list)
+    for k in sorted(per, key=int):
+        by_kernel[kname[k]].append(per[k])
+    windows = windows or {}
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for kn in sorted(by_kernel):
+        if kernels and not any(kn.startswith(x) for x in kernels):
+            continue
+        v = by_kernel[kn]
+        w = next((windows[x] for x in windows if kn.startswith(x)), None)
+        if w is not None:
+            v = v[w[0]:w[0] + w[1]]
+        if not v:
+            continue
+        cells = [f"{sum(x[c] for x in v) / len(v):.4g}" for c in names]
+        out.append(f"| {kn} | {len(v)} | " + " | ".join(cells) + " |")
+    return "\n".join(out)
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int, copy_match: str, win=None):
     fetch = _per_dispatch(fetch_dir, "FETCH_SIZE")
     write = _per_dispatch(write_dir, "WRITE_SIZE")
@@ -174,7 +207,18 @@ def main(argv=None):
     t.add_argument("--copy-match", default="copy")
     t.add_argument("--json")
     t.add_argument("--window", help="FIRST:COUNT, average over those launches of the kernel only")
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--kernels", help="comma-separated name prefixes")
+    c.add_argument("--window", action="append", default=[], help="KERNEL:FIRST:COUNT (repeatable)")
     a = ap.parse_args(argv)
+    if a.cmd == "counters":
+        wins = {}
+        for w in a.window:
+            k, first, count = w.split(":")
+            wins[k] = (int(first), int(count))
+        print(counters(a.dir, a.kernels.split(",") if a.kernels else None, wins))
+        return 0
     if a.cmd == "stats":
         print(stats(a.dir, a.top))
         if a.window:
