@@ -1,7 +1,7 @@
 """Host logic of the rocprofv3 summaries (paper_2503_12886_amd/profsum.py) on
 small synthetic CSV files: short kernel names, the window average over a
-range of one kernel's launches, and the per-launch HBM bytes scaled by a
-copy of known size."""
+range of one kernel's launches, the per-launch HBM bytes scaled by a copy
+of known size, and the per-kernel counter table."""
 import csv
 import os
 
@@ -59,3 +59,20 @@ def test_traffic_scales_by_the_copy(tmp_path):
     win = profsum.traffic(str(fetch), str(write), "composite_bwd", 1024 * 1024, "copyBuffer", (1, 1))
     assert win["fetch_bytes_per_launch"] == pytest.approx(40.0 * 1024 * 2.0)
     assert win["write_bytes_per_launch"] == pytest.approx(8.0 * 1024)
+
+
+def test_counters_table_sums_instances_and_windows(tmp_path):
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    k = "void gbr::composite_fwd_kernel<16, 64>(gbr::PassArgs, float*)"
+    o = "void gbr::loss_kernel(float const*)"
+    rows = []
+    for d, v in enumerate([1.0, 2.0, 4.0, 8.0]):      # four launches of the forward, two instances each
+        rows += [[d, k, "SQ_WAVES", v], [d, k, "SQ_WAVES", v], [d, k, "SQ_INSTS_VALU", 10 * v]]
+    rows += [[10, o, "SQ_WAVES", 5.0], [10, o, "SQ_INSTS_VALU", 7.0]]
+    _write(tmp_path / "run_counter_collection.csv", hdr, rows)
+    out = profsum.counters(str(tmp_path)).splitlines()
+    assert out[0] == "| kernel | dispatches | SQ_INSTS_VALU | SQ_WAVES |"
+    assert "| composite_fwd_kernel | 4 | 37.5 | 7.5 |" in out     # means of 10..80 and of 2..16
+    assert "| loss_kernel | 1 | 7 | 5 |" in out
+    win = profsum.counters(str(tmp_path), kernels=["composite_fwd"], windows={"composite_fwd": (1, 2)}).splitlines()
+    assert len(win) == 3 and "| composite_fwd_kernel | 2 | 30 | 6 |" in win   # launches 1 and 2 only
