@@ -20,15 +20,14 @@ __device__ __forceinline__ uint32_t depth_bucket(uint32_t bits, uint32_t mn, uin
 }
 
 // Bucketing without global atomics.  Workgroup (frame b, block j) takes the
-// frame's splats [4096 j, 4096 j + 4096) and histograms their buckets in
+// frame's splats [8192 j, 8192 j + 8192) and histograms their buckets in
 // LDS; the histograms of all (frame, block) pairs form a matrix, bucket-major
 // with the blocks of a bucket adjacent, whose exclusive scan gives every
 // block its own range inside every bucket.  The scatter pass recomputes the
 // buckets and places each splat at its block's offset plus its LDS rank.
 // Depth keys come from the compact per-splat key array (invalid splats carry
 // 0xffffffff, which no positive depth has); loads are clamped into range and
-// issued unconditionally so that a thread's four loads overlap.
-constexpr int kBucketBlock = 4096;   // splats per workgroup
+// issued unconditionally so that a thread's eight loads overlap.
 constexpr int kBucketThreads = 1024;
 constexpr int kBucketItems = kBucketBlock / kBucketThreads;
 

@@ -412,7 +412,7 @@ int set_pass(gbr_ctx* c, const float* raw, const int64_t* goff, const gbr_camera
   if ((mfs + 31) / 32 > kMaxBitmapWords) return GBR_ERR_CAPACITY;
   int nbk = 64;
   while (nbk < 8192 && (int64_t)nbk * 8 < mfs) nbk *= 2;
-  const int nblk = (int)std::max<int64_t>(1, (mfs + 4095) / 4096);
+  const int nblk = (int)std::max<int64_t>(1, (mfs + kBucketBlock - 1) / kBucketBlock);
   if ((int64_t)B * nbk > c->cap_bkt || (int64_t)B * nbk * nblk > c->cap_bkt_cells) {
     if (c->capturing) return GBR_ERR_STATE;
     GBR_HIP(hipDeviceSynchronize());
@@ -503,7 +503,7 @@ void pass_caps(int B, int64_t mfs, int64_t n_tiles, int max_frame_tiles, int64_t
                int64_t* scan_words, int64_t* tbits, int64_t* seg) {
   int nbk = 64;
   while (nbk < 8192 && (int64_t)nbk * 8 < mfs) nbk *= 2;
-  const int64_t nblk = std::max<int64_t>(1, (mfs + 4095) / 4096);
+  const int64_t nblk = std::max<int64_t>(1, (mfs + kBucketBlock - 1) / kBucketBlock);
   *bkt = (int64_t)B * nbk;
   *cells = (int64_t)B * nbk * nblk;
   *scan_words = scan_scratch_words(*cells);

@@ -98,7 +98,7 @@ struct PassArgs {
   uint32_t* cls_cnt;        // [2][33] tiles per class (forward, backward)
   // per-frame depth order
   int32_t nbk;              // depth buckets per frame
-  int32_t nblk;             // workgroups of 4096 splats per frame in the bucket passes
+  int32_t nblk;             // workgroups of kBucketBlock splats per frame in the bucket passes
   int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32, rounded up to 16)
   int32_t seg_words;        // words per row segment (8 or 16); a segment's set bits are counted once
   int32_t seg_stride;       // segments per row = bitmap_words / seg_words
@@ -283,6 +283,7 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 namespace gbr {
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+constexpr int kBucketBlock = 8192;      // splats per workgroup in the depth-bucket passes
 constexpr int kBlendMaxFrames = 4096;   // frames per gbr_blend call (rows of the float64 weight table)
 constexpr int kBlendW64Stride = 64;     // K + 1 <= 64
 void launch_blend_fwd(const float* bases, const float* weights, int B, int K, int64_t N, float* raw, double* w64,
