@@ -334,3 +334,61 @@ def test_frames_with_many_tiles_build_rows_in_memory():
     srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
     assert np.array_equal(srt, sg)
     ctx.close()
+
+
+@pytest.mark.parametrize("N", [100, 1500, 5000])
+def test_equal_depths_rank_by_index(N):
+    """Gaussians all at one depth fall in one depth bucket, which is ranked
+    in LDS by comparison (100 keys), by the large-bucket pass's comparison
+    (1500) or by its radix passes (5000); equal depths go by Gaussian index,
+    so the tile lists equal the reference's bit for bit and the image agrees."""
+    rng = np.random.default_rng(N)
+    r = np.zeros((N, 16), np.float32)
+    r[:, 0] = rng.uniform(-0.08, 0.08, N)
+    r[:, 1] = rng.uniform(-0.07, 0.07, N)
+    r[:, 3] = 1.0                                  # identity rotation: every mean at camera depth 0.5
+    r[:, 7:10] = rng.normal(-5.0, 0.3, (N, 3))
+    r[:, 10] = rng.normal(0.0, 1.0, N)
+    r[:, 11:14] = rng.uniform(0.0, 1.0, (N, 3))
+    cam = synth.fixed_camera(96, 80, 150.0, 0.5, bg=(0.2, 0.3, 0.4))
+    ctx = make_ctx(tile=16)
+    imgs, _, _ = render(ctx, r, [cam])
+    proj = raster.project(r, cam)
+    v = proj["valid"] > 0
+    assert v.sum() > 0.9 * N and np.unique(proj["depth"][v].astype(np.float32)).size == 1
+    ranges, sf, sg, _ = raster.bin_and_sort([proj], [cam], 16)
+    ts = gbr.gbr_inspect(ctx, "tile_start", len(ranges) + 1).astype(np.int64)
+    assert np.array_equal(ts[:-1], ranges[:, 0]) and np.array_equal(ts[1:], ranges[:, 1])
+    srt = gbr.gbr_inspect(ctx, "sorted", len(sg)).astype(np.int64)
+    assert np.array_equal(srt, sg)
+    ref, _, _, fl = raster.render(r, cam)
+    err, masked = compare_image(imgs[0], ref, fl, tag=f"equal depths, N={N}")
+    assert err <= IMAGE_TOL and masked <= MASK_FRAC_MAX, (err, masked)
+    ctx.close()
+
+
+def test_frame_without_gaussians_in_a_batch():
+    """A frame whose Gaussian range is empty renders its background; the
+    frames around it are unaffected (bit-equal to rendering them alone), and
+    the backward gives them the same gradient."""
+    import torch
+    raw, cams, N = batch_case(B=2, N=2000, seed=21)
+    cam_e = synth.fixed_camera(40, 24, 60.0, 0.5, bg=(0.6, 0.1, 0.9))
+    cams3 = [cams[0], cam_e, cams[1]]
+    ctx = make_ctx()
+    imgs, rt, _ = render(ctx, raw, cams3, gauss_offsets=[0, N, N, 2 * N])
+    assert np.array_equal(imgs[1], np.broadcast_to(np.float32([0.6, 0.1, 0.9])[:, None, None], (3, 24, 40)))
+    rng = np.random.default_rng(22)
+    dimg = [rng.normal(size=(3, c.height, c.width)).astype(np.float32) for c in cams3]
+    draw3 = torch.zeros(2 * N, 16, device="cuda")
+    gbr.gbr_render_backward(ctx, dev(np.concatenate([d.ravel() for d in dimg])), draw3)
+    torch.cuda.synchronize()
+    ctx2 = make_ctx()
+    imgs2, rt2, _ = render(ctx2, raw, [cams[0], cams[1]])
+    assert np.array_equal(imgs[0], imgs2[0]) and np.array_equal(imgs[2], imgs2[1])
+    draw2 = torch.zeros(2 * N, 16, device="cuda")
+    gbr.gbr_render_backward(ctx2, dev(np.concatenate([dimg[0].ravel(), dimg[2].ravel()])), draw2)
+    torch.cuda.synchronize()
+    assert torch.equal(draw3, draw2)
+    ctx.close()
+    ctx2.close()
