@@ -364,7 +364,8 @@ int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
    launch of it is bracketed
    - in eager calls, by a pair of HIP events on the launch stream:
      gbr_timing_read returns the duration of the most recent eager launch
-     in ms;
+     in ms (GBR_ERR_STATE when no eager launch was bracketed since the
+     timing was enabled);
    - in eager calls and in captured graphs alike, by two one-lane stamp
      kernels on the launch stream that read the device's constant-rate
      wall clock before and after the launch and add the difference to a

@@ -22,10 +22,16 @@ constexpr int kMaxK = 63;
 constexpr int kMaxFramesHard = 4096;
 constexpr int64_t kMaxBitmapWords = 32768;   // 128 KB bitmap row per tile: frames of up to 1,048,576 Gaussians
 
-#define GBR_HIP(x)                           \
-  do {                                       \
-    hipError_t e_ = (x);                     \
-    if (e_ != hipSuccess) return GBR_ERR_HIP; \
+// A failed HIP call is reported once: its error is also taken out of HIP's
+// last-error state, which the launch checks read, so that it does not
+// surface again at an unrelated later call.
+#define GBR_HIP(x)                 \
+  do {                             \
+    hipError_t e_ = (x);           \
+    if (e_ != hipSuccess) {        \
+      (void)hipGetLastError();     \
+      return GBR_ERR_HIP;          \
+    }                              \
   } while (0)
 
 template <typename T>
@@ -146,6 +152,7 @@ struct gbr_ctx {
   // kernel timing
   bool timing_on[GBR_K_COUNT] = {};
   hipEvent_t t_ev[GBR_K_COUNT][2] = {};
+  bool t_recorded[GBR_K_COUNT] = {};       // an eager launch was bracketed since timing was enabled
   unsigned long long* t_stamp = nullptr;   // [GBR_K_COUNT][4]: start, sum of ticks, launches, unused
   int wall_khz = 0;                        // wall-clock rate of the device
   // tangent-space binding of the last pass (gbr_render_tangent); off for gbr_render
@@ -225,7 +232,10 @@ struct KTimer {
   }
   ~KTimer() {
     if (!on) return;
-    if (!c->capturing) (void)hipEventRecord(c->t_ev[k][1], s);
+    if (!c->capturing) {
+      (void)hipEventRecord(c->t_ev[k][1], s);
+      c->t_recorded[k] = true;
+    }
     timer_stamp_kernel<<<1, 64, 0, s>>>(c->t_stamp + 4 * k, 1);
   }
 };
@@ -1166,6 +1176,7 @@ int gbr_timing(gbr_ctx* c, int32_t which, int32_t enable) {
     GBR_HIP(hipMemset(c->t_stamp + 4 * which, 0, sizeof(unsigned long long) * 4));
   }
   c->timing_on[which] = enable != 0;
+  if (enable) c->t_recorded[which] = false;
   return GBR_OK;
 }
 
@@ -1184,7 +1195,9 @@ int gbr_timing_accum(gbr_ctx* c, int32_t which, int32_t reset, double* total_ms,
 
 int gbr_timing_read(gbr_ctx* c, int32_t which, float* ms) {
   if (!c || !ms || which < 0 || which >= GBR_K_COUNT) return GBR_ERR_INVALID_ARG;
-  if (!c->t_ev[which][0]) return GBR_ERR_STATE;
+  // no eager launch of the kernel since its timing was enabled: nothing to
+  // read (asking HIP would leave its error state set for the next call)
+  if (!c->t_ev[which][0] || !c->t_recorded[which]) return GBR_ERR_STATE;
   GBR_HIP(hipEventSynchronize(c->t_ev[which][1]));
   GBR_HIP(hipEventElapsedTime(ms, c->t_ev[which][0], c->t_ev[which][1]));
   return GBR_OK;

@@ -286,3 +286,20 @@ def test_graph_refuses_to_launch_after_its_buffers_moved():
     assert tr.graph is not None and not st2.overflow
     torch.cuda.synchronize()
     tr.close()
+
+
+def test_timing_read_without_a_launch_leaves_no_error():
+    """Reading the timer of a kernel that has not run since its timing was
+    enabled is refused, and the refusal leaves nothing behind for the next
+    call to report."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=9)
+    a = Trainer(cfg, bases, mlp)
+    a.set_batch(theta, targets, cams)
+    k = gbr.KERNEL_NAMES.index("composite_bwd")
+    gbr.gbr_timing(a.ctx, k, True)
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr_timing_read(a.ctx, k)
+    assert np.isfinite(a.step().loss)
+    assert gbr.gbr_timing_read(a.ctx, k) > 0.0
+    gbr.gbr_timing(a.ctx, k, False)
+    a.close()
