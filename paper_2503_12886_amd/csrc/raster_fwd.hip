@@ -131,9 +131,9 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blo
 // One thread per (frame, Gaussian).  Activations and EWA projection in
 // float64 (so that the integer decisions -- which pixels and tiles a Gaussian
 // may reach, and its binary32 depth key -- are exactly reproducible), the
-// per-pixel record rounded to float32.  Each block also counts, in LDS, how
-// many entries its Gaussians add to every tile of the frame, and flushes the
-// non-zero counts with one global atomic each.
+// per-pixel record rounded to float32.  Each block also reduces its splats'
+// depth keys to a minimum and maximum and folds them into the frame's depth
+// range with one pair of atomics (the range scales the depth buckets).
 struct Projected {
   bool valid;
   double mx, my, A, Bq, C, o, tz;
