@@ -260,81 +260,71 @@ void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* 
 }
 
 // ---------------------------------------------------------------- gather + projection adjoint
-// Two passes.  gather_sum: one thread per splat sums its entries' partials in
-// row-major tile order (unflagged entries -- no contributing pixel, or past
-// the tile's last used position -- are zero): the flags of a 64-entry window
-// are read as four 16-byte loads, then the flagged partials 4 at a time, all
-// loads in flight before any is used, and each consumed flag is reset to 0
-// for the next pass; the 9 sums go to the splat's draw row as scratch.
-// proj_adjoint:
-// one thread per splat chains those sums back through the conic, the EWA
-// projection and the activations in float64 and overwrites the row.  Kept
-// apart so the summing pass runs at full occupancy.
+// One thread per splat.  It sums its entries' partials in row-major tile
+// order (unflagged entries -- no contributing pixel, or past the tile's last
+// used position -- are zero): the flags of a 64-entry window are read as four
+// 16-byte loads, then the flagged partials 4 at a time, all loads in flight
+// before any is used, and each consumed flag is reset to 0 for the next
+// pass.  It then chains the 9 sums back through the conic, the EWA
+// projection and the activations in float64 and writes the splat's draw
+// row.  (As two passes, the sums written to the row and read back, it took
+// 12 us more: the adjoint's lower occupancy hides the gather's loads well
+// enough.)
 // Flag bytes (0 or 1) of 4 entries -> 4 bits.
 __device__ __forceinline__ uint32_t flag_nibble(uint32_t w) {
   return (w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u);
 }
 
-__global__ __launch_bounds__(256) void gather_sum_kernel(PassArgs a, float* __restrict__ draw) {
-  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (s >= a.n_splats) return;
-  const uint32_t c = a.cnt[s];
-  float acc[9];
+// The 9 sums of splat s over its c entries (acc zeroed by the caller).
+__device__ __forceinline__ void gather_splat_sums(const PassArgs& a, int64_t s, uint32_t c, float (&acc)[9]) {
+  const uint32_t off = a.soff[s], end = off + c;
+  const uint32_t* fw = reinterpret_cast<const uint32_t*>(a.part_flag);   // padded by 64 bytes past the capacity
+  // windows of 64 entries starting at a multiple of 16: the 16 flag words
+  // are read as four aligned 16-byte loads and turned into a bit mask of
+  // the flagged entries, whose partials are then read 4 at a time (all 4
+  // in flight together)
+  for (uint32_t e0 = off & ~15u; e0 < end; e0 += 64) {
+    uint32_t w[16];
+    const uint4* fq = reinterpret_cast<const uint4*>(fw + (e0 >> 2));
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-  if (!a.status->overflow && c > 0) {
-    const uint32_t off = a.soff[s], end = off + c;
-    const uint32_t* fw = reinterpret_cast<const uint32_t*>(a.part_flag);   // padded by 64 bytes past the capacity
-    // windows of 64 entries starting at a multiple of 16: the 16 flag words
-    // are read as four aligned 16-byte loads and turned into a bit mask of
-    // the flagged entries, whose partials are then read 4 at a time (all 4
-    // in flight together)
-    for (uint32_t e0 = off & ~15u; e0 < end; e0 += 64) {
-      uint32_t w[16];
-      const uint4* fq = reinterpret_cast<const uint4*>(fw + (e0 >> 2));
+    for (int k = 0; k < 4; ++k) {
+      const uint4 x = fq[k];
+      w[4 * k] = x.x; w[4 * k + 1] = x.y; w[4 * k + 2] = x.z; w[4 * k + 3] = x.w;
+    }
+    unsigned long long m = 0ull;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint4 x = fq[k];
-        w[4 * k] = x.x; w[4 * k + 1] = x.y; w[4 * k + 2] = x.z; w[4 * k + 3] = x.w;
+    for (int k = 0; k < 16; ++k) m |= (unsigned long long)flag_nibble(w[k]) << (4 * k);
+    // keep [off, end) only
+    const uint32_t lo = off > e0 ? off - e0 : 0u;
+    const uint32_t hi = end - e0 < 64u ? end - e0 : 64u;
+    m &= (hi >= 64u ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+    while (m) {
+      uint32_t e[4];
+      bool v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = m != 0ull;
+        e[u] = v[u] ? e0 + (uint32_t)(__ffsll((long long)m) - 1) : off;   // off: in range, unused
+        m &= m - 1ull;
       }
-      unsigned long long m = 0ull;
+      float4 q[4][3];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) m |= (unsigned long long)flag_nibble(w[k]) << (4 * k);
-      // keep [off, end) only
-      const uint32_t lo = off > e0 ? off - e0 : 0u;
-      const uint32_t hi = end - e0 < 64u ? end - e0 : 64u;
-      m &= (hi >= 64u ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
-      while (m) {
-        uint32_t e[4];
-        bool v[4];
+      for (int u = 0; u < 4; ++u) {
+        const float4* src = reinterpret_cast<const float4*>(a.part + (int64_t)e[u] * kPartF);
+        q[u][0] = src[0]; q[u][1] = src[1]; q[u][2] = src[2];
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          v[u] = m != 0ull;
-          e[u] = v[u] ? e0 + (uint32_t)(__ffsll((long long)m) - 1) : off;   // off: in range, unused
-          m &= m - 1ull;
-        }
-        float4 q[4][3];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float4* src = reinterpret_cast<const float4*>(a.part + (int64_t)e[u] * kPartF);
-          q[u][0] = src[0]; q[u][1] = src[1]; q[u][2] = src[2];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!v[u]) continue;
-          // the flag goes back to 0 for the next pass (only this splat's
-          // flags are written; neighbours mask this entry out of their windows)
-          a.part_flag[e[u]] = 0;
-          acc[0] += q[u][0].x; acc[1] += q[u][0].y; acc[2] += q[u][0].z; acc[3] += q[u][0].w;
-          acc[4] += q[u][1].x; acc[5] += q[u][1].y; acc[6] += q[u][1].z; acc[7] += q[u][1].w;
-          acc[8] += q[u][2].x;
-        }
+      for (int u = 0; u < 4; ++u) {
+        if (!v[u]) continue;
+        // the flag goes back to 0 for the next pass (only this splat's
+        // flags are written; neighbours mask this entry out of their windows)
+        a.part_flag[e[u]] = 0;
+        acc[0] += q[u][0].x; acc[1] += q[u][0].y; acc[2] += q[u][0].z; acc[3] += q[u][0].w;
+        acc[4] += q[u][1].x; acc[5] += q[u][1].y; acc[6] += q[u][1].z; acc[7] += q[u][1].w;
+        acc[8] += q[u][2].x;
       }
     }
   }
-  float* out = draw + s * kNF;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) out[k] = acc[k];
 }
 
 // A workgroup per (frame, 256 of its splats): the frame is the grid's y
@@ -355,7 +345,8 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   }
   float acc[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = draw[s * kNF + k];
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+  gather_splat_sums(a, s, c, acc);
 
   // ---- recompute the forward quantities (float64) ----
   const float4* src = reinterpret_cast<const float4*>(raw + s * kNF);
@@ -505,7 +496,6 @@ void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, in
 
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, int64_t max_frame_splats, hipStream_t s) {
   if (a.n_splats == 0 || max_frame_splats == 0) return;
-  hipLaunchKernelGGL(gather_sum_kernel, dim3(div_up(a.n_splats, 256)), dim3(256), 0, s, a, draw);
   hipLaunchKernelGGL(proj_adjoint_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a, raw, draw);
 }
 
