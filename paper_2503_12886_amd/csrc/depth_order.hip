@@ -208,13 +208,19 @@ __global__ __launch_bounds__(kSortThreads) void bucket_sort_big_kernel(PassArgs 
   }
 }
 
-void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s) {
-  if (a.B == 0 || max_frame_splats == 0) return;
+void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, const ScanJob& side,
+                        hipStream_t s) {
+  if (a.B == 0 || max_frame_splats == 0) {
+    launch_scan_u32(side.in, side.out, side.n, side.block_sums, a.status, side.cap_check, side.total_out, s,
+                    side.strided, side.stride);
+    return;
+  }
   const dim3 grid(a.nblk, a.B);
   const int64_t nb = (int64_t)a.B * a.nbk;
   hipLaunchKernelGGL(bucket_count_kernel, grid, dim3(kBucketThreads), 0, s, a);
   // the scan also writes each bucket's start (its first workgroup's offset) to bkt_start
-  launch_scan_u32(a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, a.status, -1, nullptr, s, a.bkt_start, a.nblk);
+  const ScanJob buckets{a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, -1, nullptr, a.bkt_start, a.nblk};
+  launch_scan_u32_pair(buckets, side, a.status, s);
   hipLaunchKernelGGL(bucket_scatter_kernel, grid, dim3(kBucketThreads), 0, s, a);
   hipLaunchKernelGGL(bucket_rank_kernel, dim3(div_up((int64_t)a.B * a.nbk, kRankBuckets)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_sort_big_kernel, dim3(std::min(a.B * a.nbk, 512)), dim3(kSortThreads), 0, s, a);

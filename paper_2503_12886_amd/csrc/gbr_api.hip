@@ -121,6 +121,7 @@ struct gbr_ctx {
   uint32_t* n_contrib = nullptr;
   float* t_final = nullptr;
   uint32_t* scan_scratch = nullptr;
+  uint32_t* scan_scratch_splat = nullptr;   // block sums of the per-splat count scan
   int64_t cap_scan_words = 0;
   float* draw_scratch = nullptr;
   float *ci_ones = nullptr, *ci_draw = nullptr;   // colour initialisation: all-ones images, second adjoint
@@ -283,7 +284,8 @@ void free_all(gbr_ctx* c) {
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
   dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
   dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
-  dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->draw_scratch);
+  dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->scan_scratch_splat);
+  dfree(c->draw_scratch);
   dfree(c->ci_ones); dfree(c->ci_draw);
   dfree(c->loss_part); dfree(c->blend_part); dfree(c->blend_w64);
   dfree(c->mlp_z1); dfree(c->mlp_z2); dfree(c->mlp_dz1); dfree(c->mlp_dz2);
@@ -373,13 +375,14 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
   }
   {
     KTimer t(c, GBR_K_DEPTH_ORDER, s);
-    launch_depth_order(a, c->max_frame_splats, c->scan_scratch, s);
+    // the scan of the splats' tile counts (preprocess output) shares the bucket scan's launches
+    const ScanJob splat_scan{c->cnt, c->soff, c->n_splats, c->scan_scratch_splat, -1, nullptr, nullptr, 1};
+    launch_depth_order(a, c->max_frame_splats, c->scan_scratch, splat_scan, s);
   }
   {
     KTimer t(c, GBR_K_BINNING, s);
     launch_bitmap_rows(a, c->max_frame_splats, c->max_frame_tiles, s);
     launch_tile_count(a, s);
-    launch_scan_u32(c->cnt, c->soff, c->n_splats, c->scan_scratch, c->d_status, -1, nullptr, s);
   }
   {
     KTimer t(c, GBR_K_TILE_SCAN, s);
@@ -495,7 +498,7 @@ int64_t workspace_bytes(const WorkspaceCaps& k) {
   b += (n(k.splats) * 2) * 8 + n(k.splats) * 4 * 2;                       // bucket keys, order, rank
   b += (n(k.bkt_cells) + n(k.bkt_cells + 1) + n(k.bkt + 1) + n(k.bkt)) * 4;  // depth buckets
   b += 3 * n(k.pixels) * 4;                                                  // n_iter, n_contrib, t_final
-  b += n(k.scan_words) * 4 + n(k.splats * kNF) * 4;
+  b += n(k.scan_words) * 4 + n(scan_scratch_words(k.splats)) * 4 + n(k.splats * kNF) * 4;
   b += n(2 * loss_partials(3 * k.pixels) + 2) * 4;
   b += n(4 * k.splats + 4096LL * k.frames + 64LL * 64 * 8) * 4;
   b += (int64_t)kBlendMaxFrames * kBlendW64Stride * 8 + 4 * n(k.frames * 1024) * 4;
@@ -603,6 +606,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   c->cap_scan_words = scan_scratch_words(std::max<int64_t>(std::max<int64_t>(c->cap_splats, c->cap_tiles),
                                                             (int64_t)8192 * c->cap_frames));
   TRY(dalloc(&c->scan_scratch, c->cap_scan_words));
+  TRY(dalloc(&c->scan_scratch_splat, scan_scratch_words(c->cap_splats)));
   TRY(dalloc(&c->draw_scratch, c->cap_splats * kNF));
   TRY(dalloc(&c->loss_part, 2 * loss_partials(3 * c->cap_pixels) + 2));
   c->blend_part_n = 4 * c->cap_splats + 4096LL * c->cap_frames + 64LL * 64 * 8;

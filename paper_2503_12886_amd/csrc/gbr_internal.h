@@ -296,9 +296,24 @@ int64_t blend_bwd_partials(int B, int K, int64_t N);
 int64_t blend_bwd_partials_used(int B, int K, int64_t N);
 // Exclusive scan of in[0, n) into out[0, n] (out[n] = total).  With strided
 // non-null, also strided[j] = out[j * stride] for every j * stride <= n.
+// The grand total is stored to total_out when non-null, and sets the
+// overflow flag when it exceeds cap_check (>= 0).  block_sums holds
+// scan_scratch_words(n) words.
+struct ScanJob {
+  const uint32_t* in;
+  uint32_t* out;
+  int64_t n;
+  uint32_t* block_sums;
+  int64_t cap_check;
+  unsigned long long* total_out;
+  uint32_t* strided;
+  int stride;
+};
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums, StatusDev* status,
                      int64_t cap_check, unsigned long long* total_out, hipStream_t s, uint32_t* strided = nullptr,
                      int stride = 1);
+// Two independent scans in the same two launches (distinct block_sums).
+void launch_scan_u32_pair(const ScanJob& j0, const ScanJob& j1, StatusDev* status, hipStream_t s);
 int64_t scan_scratch_words(int64_t n);
 void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
 // Words per bitmap row segment for frames of up to max_frame_tiles tiles
@@ -311,7 +326,10 @@ void launch_tile_count(const PassArgs& a, hipStream_t s);
 void launch_count_contrib(const PassArgs& a, hipStream_t s);
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
 
-void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, hipStream_t s);
+// The depth order of every frame's splats.  side is an independent scan whose
+// input is ready when the pass starts, run in the bucket scan's launches.
+void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, const ScanJob& side,
+                        hipStream_t s);
 void launch_composite_fwd(const PassArgs& a, float* images, int chunk, hipStream_t s);
 void launch_composite_bwd(const PassArgs& a, const float* dimages, const float* images, int chunk, hipStream_t s);
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, int64_t max_frame_splats, hipStream_t s);

@@ -29,20 +29,47 @@ void launch_fill_f32(float* p, float v, int64_t n, hipStream_t s) {
 // per-block totals, then every block adds the totals of the blocks before it
 // (read directly, summed in 64 bits) to its own rescan.  The grand total is
 // published (and checked against a capacity) by the workgroup that writes
-// out[n].  Integer sums, so the order does not matter for the result.
+// out[n].  Integer sums, so the order does not matter for the result.  One
+// launch pair can carry two independent scans: the first job's blocks come
+// first in the grid, then the second's.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanBlock = kScanThreads * kScanItems;
+
+struct ScanJobs {
+  ScanJob j0, j1;
+  int nb0;   // blocks of the first job
+};
+
+// The job of this workgroup (chosen field by field, uniformly) and its block index within it.
+__device__ __forceinline__ ScanJob scan_job(const ScanJobs& J, int* blk) {
+  const bool second = (int)blockIdx.x >= J.nb0;
+  *blk = (int)blockIdx.x - (second ? J.nb0 : 0);
+  ScanJob j;
+  j.in = second ? J.j1.in : J.j0.in;
+  j.out = second ? J.j1.out : J.j0.out;
+  j.n = second ? J.j1.n : J.j0.n;
+  j.block_sums = second ? J.j1.block_sums : J.j0.block_sums;
+  j.cap_check = second ? J.j1.cap_check : J.j0.cap_check;
+  j.total_out = second ? J.j1.total_out : J.j0.total_out;
+  j.strided = second ? J.j1.strided : J.j0.strided;
+  j.stride = second ? J.j1.stride : J.j0.stride;
+  return j;
+}
+
 __device__ __forceinline__ void publish_total(unsigned long long total, StatusDev* status, int64_t cap_check,
                                               unsigned long long* total_out) {
   if (total_out) *total_out = total;
   if (cap_check >= 0 && total > (unsigned long long)cap_check) status->overflow |= 1u;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(const uint32_t* __restrict__ in, int64_t n,
-                                                                    uint32_t* __restrict__ block_sums) {
+__global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(ScanJobs jobs) {
   __shared__ uint32_t lw[kScanThreads / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  int blk;
+  const ScanJob J = scan_job(jobs, &blk);
+  const uint32_t* __restrict__ in = J.in;
+  const int64_t n = J.n;
+  const int64_t base = (int64_t)blk * kScanBlock;
   // loads issued unconditionally (index clamped into range), then masked
   uint32_t v[kScanItems];
 #pragma unroll
@@ -55,25 +82,28 @@ __global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(const uint32_
   for (int i = 0; i < kScanItems; ++i) s += (base + (int64_t)i * kScanThreads + threadIdx.x < n) ? v[i] : 0u;
   uint32_t tot;
   block_excl_scan<kScanThreads>(s, lw, &tot);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+  if (threadIdx.x == 0) J.block_sums[blk] = tot;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t* __restrict__ in, int64_t n,
-                                                                   const uint32_t* __restrict__ block_sums,
-                                                                   uint32_t* __restrict__ out, StatusDev* status,
-                                                                   int64_t cap_check,
-                                                                   unsigned long long* total_out,
-                                                                   uint32_t* __restrict__ strided, int stride) {
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanJobs jobs, StatusDev* status) {
   __shared__ uint32_t tile[kScanBlock];
   __shared__ uint32_t lw[kScanThreads / 64];
   __shared__ unsigned long long wsum[kScanThreads / 64];
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  int blk;
+  const ScanJob J = scan_job(jobs, &blk);
+  const uint32_t* __restrict__ in = J.in;
+  const uint32_t* __restrict__ block_sums = J.block_sums;
+  uint32_t* __restrict__ out = J.out;
+  uint32_t* __restrict__ strided = J.strided;
+  const int64_t n = J.n;
+  const int stride = J.stride;
+  const int64_t base = (int64_t)blk * kScanBlock;
   uint32_t v[kScanItems];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) v[i] = (n > 0) ? in[min(base + i * kScanThreads + threadIdx.x, n - 1)] : 0u;
   // this block's offset: the totals of the blocks before it
   unsigned long long part = 0;
-  for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanThreads) part += block_sums[k];
+  for (int k = threadIdx.x; k < blk; k += kScanThreads) part += block_sums[k];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
@@ -112,19 +142,30 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const uint32_t
     const unsigned long long total = off + ex;   // ex of the last thread: the block's running total
     out[n] = (uint32_t)total;
     if (strided && (uint32_t)n % (uint32_t)stride == 0u) strided[(uint32_t)n / (uint32_t)stride] = (uint32_t)total;
-    publish_total(total, status, cap_check, total_out);
+    publish_total(total, status, J.cap_check, J.total_out);
   }
 }
 
 int64_t scan_scratch_words(int64_t n) { return div_up(n + 1, kScanBlock) + 1; }
 
+void launch_scan_u32_pair(const ScanJob& j0, const ScanJob& j1, StatusDev* status, hipStream_t s) {
+  ScanJobs J;
+  J.j0 = j0;
+  J.j1 = j1;
+  J.j0.stride = j0.stride < 1 ? 1 : j0.stride;
+  J.j1.stride = j1.stride < 1 ? 1 : j1.stride;
+  J.nb0 = (int)div_up(j0.n + 1, kScanBlock);
+  const int nb = J.nb0 + (j1.in ? (int)div_up(j1.n + 1, kScanBlock) : 0);
+  hipLaunchKernelGGL(scan_totals_kernel, dim3(nb), dim3(kScanThreads), 0, s, J);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kScanThreads), 0, s, J, status);
+}
+
 void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* block_sums, StatusDev* status,
                      int64_t cap_check, unsigned long long* total_out, hipStream_t s, uint32_t* strided,
                      int stride) {
-  const int nb = div_up(n + 1, kScanBlock);
-  hipLaunchKernelGGL(scan_totals_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(kScanThreads), 0, s, in, n, block_sums, out, status,
-                     cap_check, total_out, strided, stride < 1 ? 1 : stride);
+  const ScanJob j0{in, out, n, block_sums, cap_check, total_out, strided, stride};
+  const ScanJob none{nullptr, nullptr, 0, nullptr, -1, nullptr, nullptr, 1};
+  launch_scan_u32_pair(j0, none, status, s);
 }
 
 // ---------------------------------------------------------------- preprocess

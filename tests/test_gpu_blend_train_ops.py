@@ -103,6 +103,31 @@ def test_adam_matches_reference():
     assert gbr.gbr_query_status(ctx).adam_steps[0] == 3
 
 
+def test_adam_step_count_across_grid_shapes():
+    """Each update advances its group's step count once: over updates of one
+    workgroup, of 1313, of the 8192-workgroup grid-stride cap and of no
+    element, the counts equal the number of updates per group, and every
+    element follows the reference with the bias correction of the step it was
+    updated at."""
+    rng = np.random.default_rng(11)
+    n_big = 8192 * 256 + 1000
+    table = [1e-3] * 32
+    ctx = make_ctx()
+    p0 = rng.normal(size=n_big).astype(np.float32)
+    P = dev(p0); M = dev(np.zeros(n_big, np.float32)); V = dev(np.zeros(n_big, np.float32))
+    pr, mr, vr = p0.astype(np.float64), np.zeros(n_big), np.zeros(n_big)
+    sizes = [n_big, 1, 21 * 1000 * 16, 0, n_big, 777, 64]
+    for step, k in enumerate(sizes, start=1):
+        g = rng.normal(size=k).astype(np.float32)
+        gbr.gbr_adam_step(ctx, 2, P[:k], dev(g), M[:k], V[:k], 0, table)
+        if k:
+            pr[:k], mr[:k], vr[:k] = bs.adam_step(pr[:k], g, mr[:k], vr[:k], step, 1e-3)
+        gbr.gbr_adam_step(ctx, 3, P[:0], P[:0], P[:0], P[:0], 0, table)   # another group, no elements
+        st = gbr.gbr_query_status(ctx)
+        assert st.adam_steps[2] == step and st.adam_steps[3] == step and st.adam_steps[0] == 0
+    assert np.abs(host(P) - pr).max() <= 1e-6 + 1e-6 * np.abs(pr).max()
+
+
 def test_loss_l1_l2():
     cams = synth.make_cameras(3, 40, 24, seed=1)
     imgs = [np.random.default_rng(i).uniform(size=(3, c.height, c.width)).astype(np.float32) for i, c in enumerate(cams)]
