@@ -293,15 +293,24 @@ int gbr_adam_step(gbr_ctx* ctx, int32_t group, float* params, const float* grads
    device status (entries, overflow flag, Adam step counters, loss). */
 int gbr_query_status(gbr_ctx* ctx, void* stream, gbr_status* out);
 
-/* The same read split in two, so that the host can enqueue the next step
-   before it waits for this one's status.  gbr_status_post enqueues on
-   `stream` a copy of the device status (as it stands when the stream
-   reaches the copy) into host slot `slot` (0..3) and records that slot's
-   event; it first waits for the slot's previous copy, if any.
-   gbr_status_wait waits for the slot's event and reads the copy
-   (GBR_ERR_STATE if nothing was posted to it).  Not during capture. */
-int gbr_status_post(gbr_ctx* ctx, void* stream, int32_t slot);
-int gbr_status_wait(gbr_ctx* ctx, int32_t slot, gbr_status* out);
+/* The same read split in two, so that the host can enqueue the next steps
+   before it waits for this one's status, with nothing enqueued between the
+   steps but the steps themselves.  gbr_status_post enqueues on `stream`,
+   eagerly or into the graph being captured, a one-thread kernel that copies
+   the device status (as it stands when the stream reaches it) into a ring of
+   4 records in pinned host memory: the device numbers its posts 1, 2, ... in
+   the order it runs them, and post n lands in record n mod 4 together with n.
+   gbr_status_posts returns how many posts have been enqueued: an eager post
+   counts at once, a graph's posts each time gbr_graph_launch launches it, so
+   after enqueueing a post (or launching a graph that ends with one) its
+   number is the count.  gbr_status_wait waits (spinning on the host) until
+   post n has landed and reads it: GBR_ERR_STATE when post n was never
+   enqueued, when a newer post has overwritten its record (keep at most 4
+   posts ahead of the waits) or when the stream of the latest post has
+   finished without it; GBR_ERR_HIP when that stream reports an error. */
+int gbr_status_post(gbr_ctx* ctx, void* stream);
+int gbr_status_posts(gbr_ctx* ctx, int64_t* n);
+int gbr_status_wait(gbr_ctx* ctx, int64_t n, gbr_status* out);
 
 /* Re-stage the per-frame table (cameras, Gaussian offsets) of the last
    render without enqueueing work, so that a graph captured around gbr_render

@@ -60,6 +60,26 @@ __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
 
 __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u; }
 
+// A status record of the host ring: the device status and the number of the
+// post that wrote it.
+struct StatusRec {
+  StatusDev st;
+  unsigned long long seq;
+};
+constexpr int kStatusSlots = 4;   // records of the ring (gbr_status_post / gbr_status_wait)
+
+// Post n (the device counts its posts in the order it runs them) copies the
+// status into record n mod kStatusSlots of the host ring, then stores n with
+// a system-scope release, so that the host sees the record whole once it
+// sees n.
+__global__ void status_post_kernel(const StatusDev* __restrict__ d, StatusRec* ring, unsigned long long* count) {
+  const unsigned long long n = *count + 1ull;
+  *count = n;
+  StatusRec* r = ring + n % kStatusSlots;
+  r->st = *d;
+  __hip_atomic_store(&r->seq, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 }  // namespace
 
 // ---- scratch of the allocation-free entry point (gbr_blend_backward_noalloc)
@@ -85,8 +105,6 @@ static int scratch_of_current_device(float** out) {
   *out = g_scratch_addr[dev];
   return GBR_OK;
 }
-
-constexpr int kStatusSlots = 4;   // status records in flight (gbr_status_post / gbr_status_wait)
 
 struct gbr_ctx {
   gbr_config cfg;
@@ -138,9 +156,13 @@ struct gbr_ctx {
   // bumped whenever a buffer that captured work may reference is freed and
   // allocated again; a graph records it and refuses to launch once it moved
   uint64_t alloc_gen = 0;
-  StatusDev* h_status = nullptr;   // pinned, [1 + kStatusSlots]: gbr_query_status's record, then the posted slots
-  hipEvent_t status_ev[kStatusSlots] = {};
-  bool status_posted[kStatusSlots] = {};
+  StatusDev* h_status = nullptr;   // pinned: gbr_query_status's record
+  StatusRec* h_ring = nullptr;     // pinned, coherent, [kStatusSlots]: the posted records
+  StatusRec* d_ring = nullptr;     // the device's address of h_ring
+  unsigned long long* d_posts = nullptr;   // posts the device has run
+  int64_t posts = 0;               // posts enqueued (eagerly, or by launches of graphs holding them)
+  int64_t capture_posts = 0;       // posts in the graph being captured
+  hipStream_t post_stream = nullptr;   // the stream of the latest post
   // pass state
   bool capturing = false;
   bool have_pre = false, have_raster = false;
@@ -167,8 +189,9 @@ struct gbr_ctx {
 struct gbr_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  const gbr_ctx* ctx = nullptr;   // the context whose buffers the captured work uses
+  gbr_ctx* ctx = nullptr;         // the context whose buffers the captured work uses
   uint64_t alloc_gen = 0;         // its allocation generation at capture
+  int64_t posts = 0;              // status posts the graph holds
 };
 
 namespace {
@@ -292,11 +315,11 @@ void free_all(gbr_ctx* c) {
   dfree(c->t_stamp);
   if (c->h_frames) (void)hipHostFree(c->h_frames);
   if (c->h_status) (void)hipHostFree(c->h_status);
-  c->h_frames = nullptr; c->h_status = nullptr;
+  if (c->h_ring) (void)hipHostFree(c->h_ring);
+  dfree(c->d_posts);
+  c->h_frames = nullptr; c->h_status = nullptr; c->h_ring = nullptr; c->d_ring = nullptr;
   for (int i = 0; i < kSlots; ++i)
     if (c->slot_ev[i]) (void)hipEventDestroy(c->slot_ev[i]);
-  for (int i = 0; i < kStatusSlots; ++i)
-    if (c->status_ev[i]) (void)hipEventDestroy(c->status_ev[i]);
   for (int k = 0; k < GBR_K_COUNT; ++k)
     for (int j = 0; j < 2; ++j)
       if (c->t_ev[k][j]) (void)hipEventDestroy(c->t_ev[k][j]);
@@ -491,7 +514,7 @@ struct WorkspaceCaps {
 int64_t workspace_bytes(const WorkspaceCaps& k) {
   auto n = [](int64_t c) { return c < 1 ? (int64_t)1 : c; };   // dalloc allocates at least one element
   int64_t b = 0;
-  b += n(k.frames) * (int64_t)sizeof(FrameDev) + (int64_t)sizeof(StatusDev);
+  b += n(k.frames) * (int64_t)sizeof(FrameDev) + (int64_t)sizeof(StatusDev) + 8;   // + the post counter
   b += n(k.splats * kRecF) * 4 + n(k.splats) * 16 + n(k.splats) * 4 + n(k.splats + 1) * 4 + n(k.splats) * 4;
   b += (n(k.tiles) + n(k.tiles + 1) + n(k.tiles) + n(4 * k.tiles) + 2 * n(33 * k.tiles)) * 4 + 66 * 4;
   b += n((int64_t)kMinmaxStride * k.frames) * 4 + 4;
@@ -619,13 +642,17 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(alloc_entries(c, cfg->max_entries));
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_frames), sizeof(FrameDev) * kSlots * c->cap_frames,
                     hipHostMallocDefault) != hipSuccess) TRY(GBR_ERR_OOM);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(StatusDev) * (1 + kStatusSlots),
-                    hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_status), sizeof(StatusDev), hipHostMallocDefault) != hipSuccess)
     TRY(GBR_ERR_OOM);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_ring), sizeof(StatusRec) * kStatusSlots,
+                    hipHostMallocCoherent) != hipSuccess)
+    TRY(GBR_ERR_OOM);
+  std::memset(c->h_ring, 0, sizeof(StatusRec) * kStatusSlots);
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&c->d_ring), c->h_ring, 0) != hipSuccess) TRY(GBR_ERR_HIP);
+  TRY(dalloc(&c->d_posts, 1));
+  if (hipMemset(c->d_posts, 0, sizeof(unsigned long long)) != hipSuccess) TRY(GBR_ERR_HIP);
   for (int i = 0; i < kSlots; ++i)
     if (hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming) != hipSuccess) TRY(GBR_ERR_HIP);
-  for (int i = 0; i < kStatusSlots; ++i)
-    if (hipEventCreateWithFlags(&c->status_ev[i], hipEventDisableTiming) != hipSuccess) TRY(GBR_ERR_HIP);
   StatusDev zero;
   std::memset(&zero, 0, sizeof(zero));
   if (hipMemcpy(c->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) TRY(GBR_ERR_HIP);
@@ -983,24 +1010,55 @@ int gbr_query_status(gbr_ctx* c, void* stream, gbr_status* out) {
   return GBR_OK;
 }
 
-int gbr_status_post(gbr_ctx* c, void* stream, int32_t slot) {
-  if (!c || slot < 0 || slot >= kStatusSlots) return GBR_ERR_INVALID_ARG;
-  if (c->capturing) return GBR_ERR_STATE;
+int gbr_status_post(gbr_ctx* c, void* stream) {
+  if (!c) return GBR_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  // the slot's previous copy must have landed before it is overwritten
-  if (c->status_posted[slot]) GBR_HIP(hipEventSynchronize(c->status_ev[slot]));
-  GBR_HIP(hipMemcpyAsync(c->h_status + 1 + slot, c->d_status, sizeof(StatusDev), hipMemcpyDeviceToHost, s));
-  GBR_HIP(hipEventRecord(c->status_ev[slot], s));
-  c->status_posted[slot] = true;
+  hipLaunchKernelGGL(status_post_kernel, dim3(1), dim3(1), 0, s, c->d_status, c->d_ring, c->d_posts);
+  GBR_HIP(hipGetLastError());
+  if (c->capturing) {
+    ++c->capture_posts;
+  } else {
+    ++c->posts;
+    c->post_stream = s;
+  }
   return GBR_OK;
 }
 
-int gbr_status_wait(gbr_ctx* c, int32_t slot, gbr_status* out) {
-  if (!c || !out || slot < 0 || slot >= kStatusSlots) return GBR_ERR_INVALID_ARG;
-  if (!c->status_posted[slot]) return GBR_ERR_STATE;
-  GBR_HIP(hipEventSynchronize(c->status_ev[slot]));
-  fill_status(c, c->h_status[1 + slot], out);
+int gbr_status_posts(gbr_ctx* c, int64_t* n) {
+  if (!c || !n) return GBR_ERR_INVALID_ARG;
+  *n = c->posts;
   return GBR_OK;
+}
+
+int gbr_status_wait(gbr_ctx* c, int64_t n, gbr_status* out) {
+  if (!c || !out || n < 1) return GBR_ERR_INVALID_ARG;
+  if (n > c->posts) return GBR_ERR_STATE;   // never enqueued: it would not arrive
+  StatusRec* r = c->h_ring + n % kStatusSlots;
+  const unsigned long long want = (unsigned long long)n;
+  for (uint64_t spin = 1;; ++spin) {
+    unsigned long long seq = __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE);
+    if (seq == want) {
+      StatusDev st;
+      std::memcpy(&st, (const void*)&r->st, sizeof(st));
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      if (__atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) != want) return GBR_ERR_STATE;   // overwritten meanwhile
+      fill_status(c, st, out);
+      return GBR_OK;
+    }
+    if (seq > want) return GBR_ERR_STATE;   // overwritten: more than kStatusSlots posts ahead of the waits
+    if (spin % 4096 == 0) {                  // the stream's state: an error, or done without this post
+      const hipError_t q = hipStreamQuery(c->post_stream);
+      if (q == hipSuccess) {
+        if (__atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) == want) continue;
+        return GBR_ERR_STATE;
+      }
+      if (q != hipErrorNotReady) {
+        (void)hipGetLastError();
+        return GBR_ERR_HIP;
+      }
+    }
+    __builtin_ia32_pause();
+  }
 }
 
 int gbr_stage_frames(gbr_ctx* c, const int64_t* goff, const gbr_camera* cams, int32_t B) {
@@ -1024,6 +1082,7 @@ int gbr_graph_begin(gbr_ctx* c, void* stream) {
   if (!c || c->capturing) return GBR_ERR_STATE;
   GBR_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed));
   c->capturing = true;
+  c->capture_posts = 0;
   return GBR_OK;
 }
 
@@ -1039,6 +1098,7 @@ int gbr_graph_end(gbr_ctx* c, void* stream, gbr_graph** out) {
   }
   g->ctx = c;
   g->alloc_gen = c->alloc_gen;
+  g->posts = c->capture_posts;
   *out = g;
   return GBR_OK;
 }
@@ -1047,6 +1107,10 @@ int gbr_graph_launch(gbr_graph* g, void* stream) {
   if (!g) return GBR_ERR_INVALID_ARG;
   if (g->ctx->alloc_gen != g->alloc_gen) return GBR_ERR_STATE;   // a buffer it uses was reallocated
   GBR_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  if (g->posts) {
+    g->ctx->posts += g->posts;
+    g->ctx->post_stream = (hipStream_t)stream;
+  }
   return GBR_OK;
 }
 

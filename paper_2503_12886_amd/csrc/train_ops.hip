@@ -74,36 +74,40 @@ void launch_mlp_fwd(const float* params, const float* theta, int B, int d_in, in
 }
 
 // ---------------------------------------------------------------- MLP backward
-// dz2 = (W3^T dpsi) * [z2 > 0], then dz1 = (W2^T dz2) * [z1 > 0], in one
-// workgroup per frame: a unit's sum is split over four threads (weight rows
-// read coalesced across units), whose quarters are added in order.  Then one
-// thread per parameter sums over the frames in frame order.
-constexpr int kActSplit = 4;
+// dz2 = (W3^T dpsi) * [z2 > 0], then dz1 = (W2^T dz2) * [z1 > 0].  Each frame
+// takes kActParts workgroups: every one forms the whole of dz2 (K x hidden
+// terms; the first one stores it) and its own part of dz1's units.  A unit's
+// sum is split over as many threads as the workgroup has for it (weight rows
+// read coalesced across units, each thread's loads in flight together), and
+// the pieces are added in order.  Then one thread per parameter sums over the
+// frames in frame order.
+constexpr int kActParts = 4;
 
-// dz[i] = [z[i] > 0] * sum_k W[k][i] g[k] for i < n_x (g, dz in LDS; dz also to global)
-__device__ __forceinline__ void mlp_act_back(const float* __restrict__ W, const float* g, int n_g, int n_x,
-                                             const float* __restrict__ z, float* part, float* dz_l,
+// dz[i] = [z[i] > 0] * sum_k W[k][i] g[k] for i in [i0, i1) (g in LDS; dz to
+// dz_l (LDS, indexed by i) when non-null and to dz_g (global) when non-null).
+__device__ __forceinline__ void mlp_act_back(const float* __restrict__ W, const float* g, int n_g, int n_x, int i0,
+                                             int i1, const float* __restrict__ z, float* part, float* dz_l,
                                              float* __restrict__ dz_g) {
-  const int per = (n_g + kActSplit - 1) / kActSplit;
-  for (int base = 0; base < n_x * kActSplit; base += kMlpThreads) {
-    const int t = base + (int)threadIdx.x;
-    const int i = t % n_x, qk = t / n_x;
-    if (qk < kActSplit) {
-      const int k0 = qk * per, k1 = min(n_g, k0 + per);
-      float s = 0.0f;
-#pragma unroll 8
-      for (int k = k0; k < k1; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[k], s);
-      part[qk * kMlpMaxIn + i] = s;
-    }
+  const int nu = i1 - i0;                                          // units, <= kMlpThreads
+  const int split = min(16, max(1, kMlpThreads / max(nu, 1)));     // threads per unit
+  const int per = (n_g + split - 1) / split;
+  const int t = (int)threadIdx.x;
+  if (nu > 0 && t < nu * split) {
+    const int i = i0 + t % nu, qk = t / nu;
+    const int k0 = qk * per, k1 = min(n_g, k0 + per);
+    float s = 0.0f;
+#pragma unroll 16
+    for (int k = k0; k < k1; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[k], s);
+    part[qk * kMlpMaxIn + (i - i0)] = s;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n_x; i += kMlpThreads) {
+  for (int u = t; u < nu; u += kMlpThreads) {
     float v = 0.0f;
-#pragma unroll
-    for (int qk = 0; qk < kActSplit; ++qk) v += part[qk * kMlpMaxIn + i];
+    for (int qk = 0; qk < split; ++qk) v += part[qk * kMlpMaxIn + u];
+    const int i = i0 + u;
     v = z[i] > 0.0f ? v : 0.0f;
-    dz_l[i] = v;
-    dz_g[i] = v;
+    if (dz_l) dz_l[i] = v;
+    if (dz_g) dz_g[i] = v;
   }
   __syncthreads();
 }
@@ -114,13 +118,16 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_bwd_act_kernel(const float* _
                                                                   const float* __restrict__ z1,
                                                                   const float* __restrict__ z2, int hidden, int K,
                                                                   float* __restrict__ dz1, float* __restrict__ dz2) {
-  __shared__ float part[kActSplit * kMlpMaxIn];
+  __shared__ float part[16 * kMlpMaxIn];
   __shared__ float gk[kMlpMaxIn], gh[kMlpMaxIn];
-  const int b = blockIdx.x;
+  const int b = blockIdx.x, q = blockIdx.y;
   for (int k = threadIdx.x; k < K; k += kMlpThreads) gk[k] = dpsi[(int64_t)b * K + k];
   __syncthreads();
-  mlp_act_back(W3, gk, K, hidden, z2 + (int64_t)b * hidden, part, gh, dz2 + (int64_t)b * hidden);
-  mlp_act_back(W2, gh, hidden, hidden, z1 + (int64_t)b * hidden, part, gk, dz1 + (int64_t)b * hidden);
+  mlp_act_back(W3, gk, K, hidden, 0, hidden, z2 + (int64_t)b * hidden, part, gh,
+               q == 0 ? dz2 + (int64_t)b * hidden : nullptr);
+  const int per = (hidden + kActParts - 1) / kActParts;
+  const int i0 = min(hidden, q * per), i1 = min(hidden, i0 + per);
+  mlp_act_back(W2, gh, hidden, hidden, i0, i1, z1 + (int64_t)b * hidden, part, nullptr, dz1 + (int64_t)b * hidden);
 }
 
 __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restrict__ theta,
@@ -163,8 +170,8 @@ void launch_mlp_bwd(const float* params, const float* theta, const float* z1, co
   if (B == 0) return;
   const float* W2 = params + (int64_t)hidden * d_in + hidden;
   const float* W3 = W2 + (int64_t)hidden * hidden + hidden;
-  hipLaunchKernelGGL(mlp_bwd_act_kernel, dim3(B), dim3(kMlpThreads), 0, s, W2, W3, dpsi, z1, z2, hidden, K, dz1,
-                     dz2);
+  hipLaunchKernelGGL(mlp_bwd_act_kernel, dim3(B, kActParts), dim3(kMlpThreads), 0, s, W2, W3, dpsi, z1, z2, hidden,
+                     K, dz1, dz2);
   const int64_t total = (int64_t)hidden * d_in + hidden + (int64_t)hidden * hidden + hidden + (int64_t)K * hidden + K;
   hipLaunchKernelGGL(mlp_bwd_param_kernel, dim3(div_up(total, 256)), dim3(256), 0, s, theta, z1, z2, dz1, dz2, dpsi,
                      B, d_in, hidden, K, dparams);

@@ -86,8 +86,9 @@ _SIGS = {
     "gbr_blend_adam_step": ([_vp, _i32, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _vp, ctypes.POINTER(_f32), _f32, _f32,
                              _f32, _vp], ctypes.c_int),
     "gbr_query_status": ([_vp, _vp, ctypes.POINTER(gbr_status)], ctypes.c_int),
-    "gbr_status_post": ([_vp, _vp, _i32], ctypes.c_int),
-    "gbr_status_wait": ([_vp, _i32, ctypes.POINTER(gbr_status)], ctypes.c_int),
+    "gbr_status_post": ([_vp, _vp], ctypes.c_int),
+    "gbr_status_posts": ([_vp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "gbr_status_wait": ([_vp, ctypes.c_int64, ctypes.POINTER(gbr_status)], ctypes.c_int),
     "gbr_stage_frames": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(gbr_camera), _i32], ctypes.c_int),
     "gbr_graph_begin": ([_vp, _vp], ctypes.c_int),
     "gbr_graph_end": ([_vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
@@ -455,13 +456,19 @@ def gbr_query_status(ctx: Context, stream=None) -> gbr_status:
     return st
 
 
-def gbr_status_post(ctx: Context, slot: int, stream=None) -> None:
-    _check(lib().gbr_status_post(ctx.handle, _stream(stream), int(slot)), "gbr_status_post")
+def gbr_status_post(ctx: Context, stream=None) -> None:
+    _check(lib().gbr_status_post(ctx.handle, _stream(stream)), "gbr_status_post")
 
 
-def gbr_status_wait(ctx: Context, slot: int) -> gbr_status:
+def gbr_status_posts(ctx: Context) -> int:
+    n = ctypes.c_int64()
+    _check(lib().gbr_status_posts(ctx.handle, ctypes.byref(n)), "gbr_status_posts")
+    return int(n.value)
+
+
+def gbr_status_wait(ctx: Context, n: int) -> gbr_status:
     st = gbr_status()
-    _check(lib().gbr_status_wait(ctx.handle, int(slot), ctypes.byref(st)), "gbr_status_wait")
+    _check(lib().gbr_status_wait(ctx.handle, int(n), ctypes.byref(st)), "gbr_status_wait")
     return st
 
 

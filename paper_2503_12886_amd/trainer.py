@@ -262,21 +262,21 @@ class Trainer:
         """n steps on the current batch from the captured graph, each replay
         enqueued before the host waits for the status of the step before it:
         still one status read per step, but the GPU does not idle while the
-        host reads it and launches the next replay. A step that overflowed
-        updated nothing: the steps in flight are drained, the capacity grows,
-        the graph is captured again and the missing steps run. Returns the
-        last step's status.  With record, appends (host time when the
-        step's status arrived, its tile entries) for every completed step."""
+        host reads it and launches the next replay.  The captured step ends
+        with its own status post, so nothing is enqueued between replays.  A
+        step that overflowed updated nothing: the steps in flight are
+        drained, the capacity grows, the graph is captured again and the
+        missing steps run. Returns the last step's status.  With record,
+        appends (host time when the step's status arrived, its tile entries)
+        for every completed step."""
         assert self.graph is not None, "capture the step first"
-        assert 1 <= depth <= 4
-        done, inflight, k, retries = 0, [], 0, 0
+        assert 1 <= depth <= 4                     # the status ring holds 4 posts
+        done, inflight, retries = 0, [], 0
         last = None
         while done < n:
             while len(inflight) < depth and done + len(inflight) < n:
                 self._replay()
-                gbr.gbr_status_post(self.ctx, k % 4, self.stream)
-                inflight.append(k % 4)
-                k += 1
+                inflight.append(gbr.gbr_status_posts(self.ctx))   # this replay's post
                 self.steps_launched += 1
             st = gbr.gbr_status_wait(self.ctx, inflight.pop(0))
             if not st.overflow:
@@ -285,8 +285,8 @@ class Trainer:
                     record.append((time.perf_counter(), int(st.entries)))
                 continue
             need = st.entries
-            for slot in inflight:                 # drain the replays in flight
-                s2 = gbr.gbr_status_wait(self.ctx, slot)
+            for post in inflight:                 # drain the replays in flight
+                s2 = gbr.gbr_status_wait(self.ctx, post)
                 if s2.overflow:
                     need = max(need, s2.entries)
                 else:
@@ -324,11 +324,13 @@ class Trainer:
             gbr.gbr_graph_launch(self.graph, self.stream)
 
     def capture(self) -> None:
-        """Capture one step as a graph (after a warm-up step sized the buffers)."""
+        """Capture one step as a graph (after a warm-up step sized the buffers),
+        ending with a post of its status (gbr_status_post)."""
         self.torch.cuda.synchronize()
         gbr.gbr_graph_begin(self.ctx, self.stream)
         try:
             self.enqueue_step()
+            gbr.gbr_status_post(self.ctx, self.stream)
         finally:
             g = gbr.gbr_graph_end(self.ctx, self.stream)
         self.graph = g

@@ -65,18 +65,23 @@ def _mlp_pack(p):
     return np.concatenate([p["W1"].ravel(), p["b1"], p["W2"].ravel(), p["b2"], p["W3"].ravel(), p["b3"]])
 
 
-@pytest.mark.parametrize("B", [1, 16, 37])
-def test_mlp_forward_backward(B):
-    p = synth.make_mlp(K=20, seed=5)
-    theta = synth.make_tracking(B, seed=2)
+@pytest.mark.parametrize("B,d_in,hidden,K", [(1, 56, 256, 20), (16, 56, 256, 20), (37, 56, 256, 20),
+                                            (5, 100, 128, 40), (3, 7, 300, 64)])
+def test_mlp_forward_backward(B, d_in, hidden, K):
+    """The training shape (56 -> 256 -> 256 -> 20) and others: hidden sizes
+    that split unevenly over the backward's four workgroups per frame, and
+    the largest K."""
+    p = synth.make_mlp(K=K, seed=5, d_in=d_in, hidden=hidden)
+    rng = np.random.default_rng(2)
+    theta = synth.make_tracking(B, seed=2) if d_in == 56 else rng.normal(size=(B, d_in)).astype(np.float32)
     psi_ref, cache = bs.mlp_forward(p, theta)
     g = np.random.default_rng(0).normal(size=psi_ref.shape).astype(np.float32)
     grads = bs.mlp_backward(p, cache, g)
     ctx = make_ctx()
     P = dev(_mlp_pack(p))
     th = dev(theta)
-    psi = dev(np.zeros((B, 20), np.float32))
-    gbr.gbr_mlp_forward(ctx, P, th, 56, 256, 20, psi)
+    psi = dev(np.zeros((B, K), np.float32))
+    gbr.gbr_mlp_forward(ctx, P, th, d_in, hidden, K, psi)
     assert np.abs(host(psi) - psi_ref).max() <= 1e-5 * max(1.0, np.abs(psi_ref).max())
     dP = dev(np.zeros_like(_mlp_pack(p)))
     gbr.gbr_mlp_backward(ctx, P, dev(g), dP)

@@ -266,6 +266,44 @@ def test_pipelined_steps_equal_one_by_one_and_recover_from_overflow():
     a.close(); b.close()
 
 
+def test_status_ring_eager_and_captured_posts():
+    """Status posts land in a ring of 4 host records numbered by the device:
+    an eager post and the posts at the end of captured steps read back what
+    a synchronous read gives; a graph's post counts at each launch; a wait
+    for a post never enqueued, or for one that newer posts overwrote, is
+    refused."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=8)
+    a = Trainer(cfg, bases, mlp)
+    a.set_batch(theta, targets, cams)
+    a.step()
+    n0 = gbr.gbr_status_posts(a.ctx)
+    gbr.gbr_status_post(a.ctx, a.stream)
+    assert gbr.gbr_status_posts(a.ctx) == n0 + 1
+    st = gbr.gbr_status_wait(a.ctx, n0 + 1)
+    ref = gbr.gbr_query_status(a.ctx, a.stream)
+    assert (st.entries, st.loss, list(st.adam_steps)) == (ref.entries, ref.loss, list(ref.adam_steps))
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr_status_wait(a.ctx, n0 + 2)          # never enqueued
+    a.capture()
+    assert gbr.gbr_status_posts(a.ctx) == n0 + 1    # capturing runs nothing
+    posts = []
+    for _ in range(3):
+        a._replay()
+        posts.append(gbr.gbr_status_posts(a.ctx))
+    assert posts == [n0 + 2, n0 + 3, n0 + 4]
+    got = [gbr.gbr_status_wait(a.ctx, p) for p in posts]
+    assert [g.adam_steps[0] for g in got] == [2, 3, 4]
+    final = gbr.gbr_query_status(a.ctx, a.stream)
+    assert got[-1].loss == final.loss and got[-1].entries == final.entries and not got[-1].overflow
+    for _ in range(5):                              # posts n0+5 .. n0+9: n0+4's record is rewritten
+        gbr.gbr_status_post(a.ctx, a.stream)
+    a.torch.cuda.synchronize()
+    with pytest.raises(gbr.GbrError):
+        gbr.gbr_status_wait(a.ctx, n0 + 4)
+    assert gbr.gbr_status_wait(a.ctx, n0 + 9).adam_steps[0] == 4
+    a.close()
+
+
 def test_graph_refuses_to_launch_after_its_buffers_moved():
     """A graph keeps the buffer addresses of its capture: after the entry
     capacity grows, launching it returns GBR_ERR_STATE with nothing enqueued,
