@@ -14,8 +14,9 @@ batch-parallel scheme (one update per batch, frames rasterised one by one
 with a synchronisation each) on the same GPU, the dominant kernel's roofline
 position measured with HIP events over the timed region, a per-kernel time
 breakdown, the float64 CPU reference timed on a bounded sample, and the
-same step with the Gaussians in a mesh's tangent space.  With --k-sweep,
-also the graph-captured step time at other blendshape counts.
+same step with the Gaussians in a mesh's tangent space, and the
+graph-captured step time at other blendshape counts (--k-sweep, K = 5, 10,
+20, 40 by default).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -59,8 +60,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--per-frame-frames", type=int, default=48)
     ap.add_argument("--naive-steps", type=int, default=4, help="timed steps of the naive batch-parallel scheme")
-    ap.add_argument("--k-sweep", type=str, default="",
-                    help="comma-separated blendshape counts: graph-captured ms per step at each K")
+    ap.add_argument("--k-sweep", type=str, default="5,10,20,40",
+                    help="comma-separated blendshape counts: graph-captured ms per step at each K "
+                         "('' skips it; so do --quick and --timed-only)")
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--no-graph", action="store_true")
@@ -267,7 +269,7 @@ def main():
         out["tangent"] = tangent_leg(args)
     if not args.quick and not args.timed_only and not args.no_uneven:
         out["uneven"] = uneven_leg(args.uneven_steps)
-    if args.k_sweep:
+    if args.k_sweep and not args.quick and not args.timed_only:
         out["k_sweep"] = k_sweep_leg([int(k) for k in args.k_sweep.split(",") if k], args)
 
     if not args.quick and not args.timed_only and not args.no_serve:
