@@ -328,12 +328,16 @@ void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_sp
 // for every tile of its rect; the workgroup then stores the segment of every
 // tile of the frame (zeros included) and its bit count, so every word of
 // every row is written by exactly one workgroup and nothing needs clearing.
-// Frames with more tiles than the LDS copy holds set the bits in memory with
-// atomics after clearing the rows, and count the segments in a second pass.
-constexpr int kRowBuildWords = 16384;        // LDS words (64 KB)
+// In LDS a tile's segment takes SW + 1 words: the lanes of a half-wave OR
+// into the same word offset of their (scattered) tiles, and with a stride of
+// SW words those tiles would share a couple of banks; an odd stride spreads
+// them over all of them.  Frames with more tiles than the LDS copy holds set
+// the bits in memory with atomics after clearing the rows, and count the
+// segments in a second pass.
+constexpr int kRowBuildWords = 2048 * 9;     // LDS words (72 KB): 2048 tiles at SW = 8, 1084 at SW = 16
 
 int bitmap_seg_words(int max_frame_tiles, int64_t row_words) {
-  int sw = (int64_t)max_frame_tiles * 16 <= kRowBuildWords ? 16 : 8;
+  int sw = (int64_t)max_frame_tiles * 17 <= kRowBuildWords ? 16 : 8;
   while (row_words / sw > kMaxRowSegs) sw *= 2;
   return sw;
 }
@@ -341,6 +345,7 @@ int bitmap_seg_words(int max_frame_tiles, int64_t row_words) {
 template <int SW>
 __global__ __launch_bounds__(32 * SW) void bitmap_rows_kernel(PassArgs a) {
   constexpr int NT = 32 * SW;                 // one thread per rank of the segment
+  constexpr int ST = SW + 1;                  // LDS words per tile
   __shared__ __align__(16) uint32_t words[kRowBuildWords];
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
@@ -349,8 +354,9 @@ __global__ __launch_bounds__(32 * SW) void bitmap_rows_kernel(PassArgs a) {
   const uint32_t r0 = blockIdx.x * (uint32_t)NT;
   if (r0 >= nv || a.status->overflow) return;
   const int nw4 = F.n_tiles * (SW / 4);
+  const int nz4 = (F.n_tiles * ST + 3) / 4;   // <= kRowBuildWords / 4 (a multiple of 4 words)
   uint4* w4 = reinterpret_cast<uint4*>(words);
-  for (int q = threadIdx.x; q < nw4; q += NT) w4[q] = make_uint4(0u, 0u, 0u, 0u);
+  for (int q = threadIdx.x; q < nz4; q += NT) w4[q] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   const uint32_t r = r0 + threadIdx.x;
   if (r < nv) {
@@ -359,7 +365,7 @@ __global__ __launch_bounds__(32 * SW) void bitmap_rows_kernel(PassArgs a) {
     const uint32_t bit = 1u << (r & 31u);
     const int wl = (int)((r >> 5) & (SW - 1));
     for (int ty = rc.y; ty <= rc.w; ++ty)
-      for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(&words[(ty * F.ntx + tx) * SW + wl], bit);
+      for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(&words[(ty * F.ntx + tx) * ST + wl], bit);
   }
   __syncthreads();
   // the segment of every row (16-byte stores; rows and segments are 64-byte aligned)
@@ -367,16 +373,14 @@ __global__ __launch_bounds__(32 * SW) void bitmap_rows_kernel(PassArgs a) {
   uint32_t* rows = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (int64_t)seg * SW;
   for (int q = threadIdx.x; q < nw4; q += NT) {
     const int t = q / (SW / 4), k = q % (SW / 4);
-    reinterpret_cast<uint4*>(rows + (int64_t)t * a.bitmap_words)[k] = w4[q];
+    const uint32_t* src = words + t * ST + 4 * k;
+    reinterpret_cast<uint4*>(rows + (int64_t)t * a.bitmap_words)[k] = make_uint4(src[0], src[1], src[2], src[3]);
   }
   uint16_t* cnt = a.seg_cnt + (int64_t)F.tile_base * a.seg_stride + seg;
   for (int t = threadIdx.x; t < F.n_tiles; t += NT) {
     uint32_t c = 0;
 #pragma unroll
-    for (int k = 0; k < SW / 4; ++k) {
-      const uint4 v = w4[t * (SW / 4) + k];
-      c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
-    }
+    for (int k = 0; k < SW; ++k) c += __popc(words[t * ST + k]);
     cnt[(int64_t)t * a.seg_stride] = (uint16_t)c;
   }
 }
@@ -413,7 +417,7 @@ __global__ __launch_bounds__(256) void seg_count_kernel(PassArgs a) {
 
 void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_frame_tiles, hipStream_t s) {
   if (a.B == 0 || max_frame_splats == 0) return;
-  const bool in_lds = (int64_t)max_frame_tiles * a.seg_words <= kRowBuildWords;
+  const bool in_lds = (int64_t)max_frame_tiles * (a.seg_words + 1) <= kRowBuildWords;
   if (in_lds && a.seg_words == 32) {
     hipLaunchKernelGGL(bitmap_rows_kernel<32>, dim3(div_up(max_frame_splats, 1024), a.B), dim3(1024), 0, s, a);
   } else if (in_lds && a.seg_words == 16) {
