@@ -6,8 +6,8 @@
 //      scaled between the frame's min and max (monotone in depth);
 //   2. buckets are ranked by direct comparison, 32 buckets per workgroup
 //      in LDS (or a wave per bucket when they do not fit); large buckets go
-//      to a block that compares in LDS (<= 2048) or runs the stable radix
-//      passes through global memory.
+//      to workgroups of the same launch that compare in LDS (<= 2048) or
+//      run the stable radix passes through global memory.
 #include "gbr_device.h"
 
 namespace gbr {
@@ -94,37 +94,106 @@ __device__ __forceinline__ void emit_ranked(const PassArgs& a, unsigned long lon
 }
 
 // Ranks within buckets.  Keys are unique, so a key's rank is the number of
-// smaller keys in its bucket.  A workgroup takes 32 consecutive buckets:
-// when their keys fit in LDS, every thread ranks keys against the keys of
-// their bucket there; otherwise a wave per bucket compares through lane
-// reads.  Buckets of more than kRankMax keys (kWaveMax on the wave path) go
-// to the large-bucket pass.  The bucket count per frame is a power of two
-// of at least 64, so a workgroup's buckets belong to one frame.
+// smaller keys in its bucket.  One launch does both parts:
+//  * the ranking workgroups take 32 consecutive buckets each: when their
+//    keys fit in LDS, every thread ranks keys against the keys of their
+//    bucket there; otherwise a wave per bucket compares through lane reads.
+//    Buckets of more than kRankMax keys (kWaveMax on the wave path: the cap
+//    follows from the 32 buckets' total alone) are left to
+//  * the large-bucket workgroups, which come first in the grid (so that
+//    their longer work starts early): workgroup s of ns checks the buckets
+//    s, s + ns, ..., recomputing each one's cap from the bucket starts, and
+//    sorts those above it one at a time (comparison in LDS up to kBigDirect
+//    keys, else stable radix passes over the varying key bytes).
+// The bucket count per frame is a power of two of at least 64, so a ranking
+// workgroup's buckets belong to one frame.
 constexpr int kRankBuckets = 32;
 constexpr int kRankKeys = 2048;
 constexpr uint32_t kRankMax = 128;
 constexpr uint32_t kWaveMax = 64;
+constexpr int kBigDirect = 2048;
+constexpr int kOrderThreads = 256;
+static_assert(kSortThreads == kOrderThreads, "the radix passes run on the workgroup");
+static_assert(kBigDirect <= kRankKeys, "both parts share the key array");
 
-__global__ __launch_bounds__(256) void bucket_rank_kernel(PassArgs a) {
-  __shared__ unsigned long long keys[kRankKeys];
-  __shared__ uint32_t bs[kRankBuckets + 1];
-  __shared__ uint32_t vb;
+// the cap of bucket gb (the size above which it is a large bucket)
+__device__ __forceinline__ uint32_t bucket_cap(const PassArgs& a, int gb, int nb) {
+  const int g0 = gb - gb % kRankBuckets, g1 = min(nb, g0 + kRankBuckets);
+  return a.bkt_start[g1] - a.bkt_start[g0] <= (uint32_t)kRankKeys ? kRankMax : kWaveMax;
+}
+
+__device__ void sort_large_buckets(const PassArgs& a, int s, int ns, unsigned long long* keys, uint32_t* hist,
+                                   uint32_t* lds_waves, uint32_t* vary, uint32_t* list, uint32_t* nlist) {
   const int nb = a.B * a.nbk;
-  const int gb0 = blockIdx.x * kRankBuckets;
+  for (int round = s; round < nb; round += ns * kOrderThreads) {
+    if (threadIdx.x == 0) *nlist = 0u;
+    __syncthreads();
+    const int gb = round + ns * (int)threadIdx.x;
+    if (gb < nb) {
+      const uint32_t n = a.bkt_start[gb + 1] - a.bkt_start[gb];
+      if (n > kWaveMax && n > bucket_cap(a, gb, nb)) list[atomicAdd(nlist, 1u)] = (uint32_t)gb;
+    }
+    __syncthreads();
+    const uint32_t count = *nlist;
+    for (uint32_t item = 0; item < count; ++item) {
+      const int g = (int)list[item];
+      const uint32_t start = a.bkt_start[g];
+      const int n = (int)(a.bkt_start[g + 1] - start);
+      const uint32_t vbase = a.bkt_start[(g / a.nbk) * a.nbk];
+      __syncthreads();
+      if (n <= kBigDirect) {
+        for (int i = threadIdx.x; i < n; i += kOrderThreads) keys[i] = a.bkeys[start + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kOrderThreads) {
+          const unsigned long long k = keys[i];
+          uint32_t rank = 0;
+          for (int j = 0; j < n; ++j) rank += keys[j] < k ? 1u : 0u;
+          emit_ranked(a, k, start + rank, vbase);
+        }
+      } else {
+        unsigned long long* src = a.bkeys + start;
+        unsigned long long* alt = a.bkeys_alt + start;
+        if (threadIdx.x < 2) vary[threadIdx.x] = 0u;
+        __syncthreads();
+        const unsigned long long k0 = src[0];
+        uint32_t vlo = 0, vhi = 0;
+        for (int i = threadIdx.x; i < n; i += kOrderThreads) {
+          const unsigned long long x = src[i] ^ k0;
+          vlo |= (uint32_t)x; vhi |= (uint32_t)(x >> 32);
+        }
+        if (vlo) atomicOr(&vary[0], vlo);
+        if (vhi) atomicOr(&vary[1], vhi);
+        __syncthreads();
+        const unsigned long long varying = ((unsigned long long)vary[1] << 32) | vary[0];
+        int parity = 0;
+        for (int shift = 0; shift < 64; shift += 8) {
+          if (((varying >> shift) & 255ull) == 0) continue;
+          if (parity == 0) radix_pass(src, alt, n, shift, hist, lds_waves);
+          else radix_pass(alt, src, n, shift, hist, lds_waves);
+          parity ^= 1;
+        }
+        const unsigned long long* out = parity ? alt : src;
+        for (int i = threadIdx.x; i < n; i += kOrderThreads) emit_ranked(a, out[i], start + (uint32_t)i, vbase);
+      }
+    }
+    __syncthreads();   // the list is rewritten by the next round
+  }
+}
+
+__device__ void rank_buckets(const PassArgs& a, int blk, unsigned long long* keys, uint32_t* bs, uint32_t* vb) {
+  const int nb = a.B * a.nbk;
+  const int gb0 = blk * kRankBuckets;
   const int nbl = min(nb - gb0, kRankBuckets);
   if (threadIdx.x <= nbl) bs[threadIdx.x] = a.bkt_start[gb0 + threadIdx.x];
-  if (threadIdx.x == 0) vb = a.bkt_start[(gb0 / a.nbk) * a.nbk];
+  if (threadIdx.x == 0) *vb = a.bkt_start[(gb0 / a.nbk) * a.nbk];
   __syncthreads();
   const uint32_t k0 = bs[0], nk = bs[nbl] - k0;
   const uint32_t cap = nk <= (uint32_t)kRankKeys ? kRankMax : kWaveMax;
-  if (threadIdx.x < nbl) {
-    const uint32_t n = bs[threadIdx.x + 1] - bs[threadIdx.x];
-    if (n > cap) a.big_list[atomicAdd(a.big_count, 1u)] = (uint32_t)(gb0 + threadIdx.x);
-  }
+  const uint32_t vbase = *vb;
   if (nk <= (uint32_t)kRankKeys) {
-    for (uint32_t i = threadIdx.x; i < nk; i += 256) keys[i] = a.bkeys[k0 + i];
+    for (uint32_t i = threadIdx.x; i < nk; i += kOrderThreads) keys[i] = a.bkeys[k0 + i];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nk; i += 256) {
+    for (uint32_t i = threadIdx.x; i < nk; i += kOrderThreads) {
       // bucket of key i: the last j with bs[j] <= k0 + i
       int lo = 0, hi = nbl - 1;
       while (lo < hi) {
@@ -136,12 +205,12 @@ __global__ __launch_bounds__(256) void bucket_rank_kernel(PassArgs a) {
       const unsigned long long k = keys[i];
       uint32_t rank = 0;
       for (uint32_t j = j0; j < j1; ++j) rank += keys[j] < k ? 1u : 0u;
-      emit_ranked(a, k, k0 + j0 + rank, vb);
+      emit_ranked(a, k, k0 + j0 + rank, vbase);
     }
     return;
   }
   const int lane = threadIdx.x & 63;
-  for (int j = threadIdx.x >> 6; j < nbl; j += 4) {
+  for (int j = threadIdx.x >> 6; j < nbl; j += kOrderThreads / 64) {
     const uint32_t start = bs[j], n = bs[j + 1] - start;
     if (n == 0 || n > cap) continue;
     const unsigned long long key = (lane < (int)n) ? a.bkeys[start + lane] : ~0ull;
@@ -152,60 +221,22 @@ __global__ __launch_bounds__(256) void bucket_rank_kernel(PassArgs a) {
       const uint32_t klo = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)q);
       rank += (khi < hi || (khi == hi && klo < lo)) ? 1u : 0u;
     }
-    if (lane < (int)n) emit_ranked(a, key, start + rank, vb);
+    if (lane < (int)n) emit_ranked(a, key, start + rank, vbase);
   }
 }
 
-constexpr int kBigDirect = 2048;
-
-__global__ __launch_bounds__(kSortThreads) void bucket_sort_big_kernel(PassArgs a) {
-  __shared__ unsigned long long keys[kBigDirect];
+// Workgroups [0, ns) sort the large buckets, the rest rank 32 buckets each.
+__global__ __launch_bounds__(kOrderThreads) void bucket_order_kernel(PassArgs a, int ns) {
+  __shared__ unsigned long long keys[kRankKeys];
   __shared__ uint32_t hist[kSortWaves * 256];
   __shared__ uint32_t lds_waves[kSortWaves];
   __shared__ uint32_t vary[2];
-  const uint32_t count = *a.big_count;
-  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-    const int gb = (int)a.big_list[item];
-    const uint32_t start = a.bkt_start[gb];
-    const int n = (int)(a.bkt_start[gb + 1] - start);
-    const int b = gb / a.nbk;
-    const uint32_t vbase = a.bkt_start[b * a.nbk];
-    __syncthreads();
-    if (n <= kBigDirect) {
-      for (int i = threadIdx.x; i < n; i += kSortThreads) keys[i] = a.bkeys[start + i];
-      __syncthreads();
-      for (int i = threadIdx.x; i < n; i += kSortThreads) {
-        const unsigned long long k = keys[i];
-        uint32_t rank = 0;
-        for (int j = 0; j < n; ++j) rank += keys[j] < k ? 1u : 0u;
-        emit_ranked(a, k, start + rank, vbase);
-      }
-    } else {
-      unsigned long long* src = a.bkeys + start;
-      unsigned long long* alt = a.bkeys_alt + start;
-      if (threadIdx.x < 2) vary[threadIdx.x] = 0u;
-      __syncthreads();
-      const unsigned long long k0 = src[0];
-      uint32_t vlo = 0, vhi = 0;
-      for (int i = threadIdx.x; i < n; i += kSortThreads) {
-        const unsigned long long x = src[i] ^ k0;
-        vlo |= (uint32_t)x; vhi |= (uint32_t)(x >> 32);
-      }
-      if (vlo) atomicOr(&vary[0], vlo);
-      if (vhi) atomicOr(&vary[1], vhi);
-      __syncthreads();
-      const unsigned long long varying = ((unsigned long long)vary[1] << 32) | vary[0];
-      int parity = 0;
-      for (int shift = 0; shift < 64; shift += 8) {
-        if (((varying >> shift) & 255ull) == 0) continue;
-        if (parity == 0) radix_pass(src, alt, n, shift, hist, lds_waves);
-        else radix_pass(alt, src, n, shift, hist, lds_waves);
-        parity ^= 1;
-      }
-      const unsigned long long* out = parity ? alt : src;
-      for (int i = threadIdx.x; i < n; i += kSortThreads) emit_ranked(a, out[i], start + (uint32_t)i, vbase);
-    }
-  }
+  __shared__ uint32_t list[kOrderThreads];
+  __shared__ uint32_t nlist;
+  __shared__ uint32_t bs[kRankBuckets + 1];
+  __shared__ uint32_t vb;
+  if ((int)blockIdx.x < ns) sort_large_buckets(a, (int)blockIdx.x, ns, keys, hist, lds_waves, vary, list, &nlist);
+  else rank_buckets(a, (int)blockIdx.x - ns, keys, bs, &vb);
 }
 
 void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* scan_scratch, const ScanJob& side,
@@ -222,8 +253,8 @@ void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* s
   const ScanJob buckets{a.bkt_count, a.bkt_moff, nb * a.nblk, scan_scratch, -1, nullptr, a.bkt_start, a.nblk};
   launch_scan_u32_pair(buckets, side, a.status, s);
   hipLaunchKernelGGL(bucket_scatter_kernel, grid, dim3(kBucketThreads), 0, s, a);
-  hipLaunchKernelGGL(bucket_rank_kernel, dim3(div_up((int64_t)a.B * a.nbk, kRankBuckets)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bucket_sort_big_kernel, dim3(std::min(a.B * a.nbk, 512)), dim3(kSortThreads), 0, s, a);
+  const int ns = std::min(div_up(nb, kOrderThreads), 512);   // large-bucket workgroups: 256 buckets each at most
+  hipLaunchKernelGGL(bucket_order_kernel, dim3(ns + div_up(nb, kRankBuckets)), dim3(kOrderThreads), 0, s, a, ns);
 }
 
 }  // namespace gbr

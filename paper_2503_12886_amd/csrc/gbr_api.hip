@@ -55,7 +55,7 @@ __global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < a.B) { a.minmax[i * kMinmaxStride] = 0xffffffffu; a.minmax[i * kMinmaxStride + 1] = 0u; }
   if (i < 66) a.cls_cnt[i] = 0u;
-  if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; *a.big_count = 0u; }
+  if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; }
 }
 
 __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u; }
@@ -129,7 +129,6 @@ struct gbr_ctx {
   uint8_t* cmask = nullptr;
   // per-frame depth order
   uint32_t *minmax = nullptr, *bkt_count = nullptr, *bkt_moff = nullptr, *bkt_start = nullptr;
-  uint32_t *big_list = nullptr, *big_count = nullptr;
   unsigned long long *bkeys = nullptr, *bkeys_alt = nullptr;
   uint32_t *depth_sorted = nullptr, *rank = nullptr;
   int64_t cap_bkt = 0, cap_bkt_cells = 0;
@@ -220,7 +219,6 @@ PassArgs make_args(gbr_ctx* c) {
   a.seg_cnt = c->seg_cnt;
   a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_moff = c->bkt_moff; a.bkt_start = c->bkt_start;
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
-  a.big_list = c->big_list; a.big_count = c->big_count;
   a.n_iter = c->n_iter; a.n_contrib = c->n_contrib; a.t_final = c->t_final; a.part = c->part;
   a.tg = c->tg;
   return a;
@@ -289,13 +287,12 @@ int alloc_entries(gbr_ctx* c, int64_t cap) {
 
 int alloc_buckets(gbr_ctx* c, int64_t n, int64_t cells) {
   ++c->alloc_gen;
-  dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
+  dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start);
   c->cap_bkt = 0; c->cap_bkt_cells = 0;
   int rc = GBR_OK;
   if ((rc = dalloc(&c->bkt_count, cells))) return rc;
   if ((rc = dalloc(&c->bkt_moff, cells + 1))) return rc;
   if ((rc = dalloc(&c->bkt_start, n + 1))) return rc;
-  if ((rc = dalloc(&c->big_list, n))) return rc;
   c->cap_bkt = n; c->cap_bkt_cells = cells;
   return GBR_OK;
 }
@@ -305,8 +302,8 @@ void free_all(gbr_ctx* c) {
   dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->qlast); dfree(c->tbits); dfree(c->seg_cnt);
   dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
-  dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start); dfree(c->big_list);
-  dfree(c->big_count); dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
+  dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start);
+  dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->scan_scratch_splat);
   dfree(c->draw_scratch);
   dfree(c->ci_ones); dfree(c->ci_draw);
@@ -517,9 +514,9 @@ int64_t workspace_bytes(const WorkspaceCaps& k) {
   b += n(k.frames) * (int64_t)sizeof(FrameDev) + (int64_t)sizeof(StatusDev) + 8;   // + the post counter
   b += n(k.splats * kRecF) * 4 + n(k.splats) * 16 + n(k.splats) * 4 + n(k.splats + 1) * 4 + n(k.splats) * 4;
   b += (n(k.tiles) + n(k.tiles + 1) + n(k.tiles) + n(4 * k.tiles) + 2 * n(33 * k.tiles)) * 4 + 66 * 4;
-  b += n((int64_t)kMinmaxStride * k.frames) * 4 + 4;
+  b += n((int64_t)kMinmaxStride * k.frames) * 4;
   b += (n(k.splats) * 2) * 8 + n(k.splats) * 4 * 2;                       // bucket keys, order, rank
-  b += (n(k.bkt_cells) + n(k.bkt_cells + 1) + n(k.bkt + 1) + n(k.bkt)) * 4;  // depth buckets
+  b += (n(k.bkt_cells) + n(k.bkt_cells + 1) + n(k.bkt + 1)) * 4;  // depth buckets
   b += 3 * n(k.pixels) * 4;                                                  // n_iter, n_contrib, t_final
   b += n(k.scan_words) * 4 + n(scan_scratch_words(k.splats)) * 4 + n(k.splats * kNF) * 4;
   b += n(2 * loss_partials(3 * k.pixels) + 2) * 4;
@@ -617,7 +614,6 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->order_bwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->cls_cnt, 66));
   TRY(dalloc(&c->minmax, (int64_t)kMinmaxStride * c->cap_frames));
-  TRY(dalloc(&c->big_count, 1));
   TRY(dalloc(&c->bkeys, c->cap_splats));
   TRY(dalloc(&c->bkeys_alt, c->cap_splats));
   TRY(dalloc(&c->depth_sorted, c->cap_splats));

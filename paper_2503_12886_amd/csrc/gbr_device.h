@@ -42,7 +42,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* lds_wa
 // the keys, so (wave, step, lane) order is key order and equal digits keep
 // their relative order; the rank of a key among equal digits in its step is
 // found with ballots over the digit's bits.  src/dst may be LDS or global.
-constexpr int kSortThreads = 512;
+constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortCap = 8192;
 

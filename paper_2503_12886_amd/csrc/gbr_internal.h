@@ -111,8 +111,6 @@ struct PassArgs {
   unsigned long long* bkeys_alt;  // [S] ping-pong for large buckets
   uint32_t* depth_sorted;   // [S] valid splats of each frame in (depth, index) order
   uint32_t* rank;           // [S] frame-local position of a valid splat in that order
-  uint32_t* big_list;       // [B * nbk] buckets too large for one wave
-  uint32_t* big_count;      // [1]
   // pixel stage
   uint32_t* n_iter;         // [pixels] list position after the last contributor
   uint32_t* n_contrib;      // [pixels] number of contributors (computed on request)
