@@ -343,8 +343,8 @@ def test_equal_depths_rank_by_index(N):
     """Gaussians all at one depth fall in one depth bucket, which is ranked
     in LDS by comparison (100 keys), by the large-bucket workgroups'
     comparison (1500) or by their radix passes (5000); equal depths go by
-    Gaussian index,
-    so the tile lists equal the reference's bit for bit and the image agrees."""
+    Gaussian index, so the tile lists equal the reference's bit for bit and
+    the image agrees."""
     rng = np.random.default_rng(N)
     r = np.zeros((N, 16), np.float32)
     r[:, 0] = rng.uniform(-0.08, 0.08, N)
