@@ -388,8 +388,10 @@ int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
    gbr_timing_accum, which synchronises the device before reading. */
 #define GBR_K_BLEND 0
 #define GBR_K_PREPROCESS 1
-#define GBR_K_BINNING 2      /* splat-offset scan + per-tile rank bitmap rows */
-#define GBR_K_TILE_SORT 3    /* tile scheduling classes (the lists are ordered inside the forward pass) */
+#define GBR_K_BINNING 2      /* per-tile rank bitmap rows and tile counts */
+#define GBR_K_TILE_SORT 3    /* clearing the backward scheduling classes when a pass is rasterised again (the
+                                forward classes are built in the tile scan's launch, the lists are ordered
+                                inside the forward pass) */
 #define GBR_K_COMPOSITE_FWD 4
 #define GBR_K_COMPOSITE_BWD 5
 #define GBR_K_GATHER_BWD 6
@@ -397,8 +399,8 @@ int gbr_inspect(gbr_ctx* ctx, int32_t what, void* dst, int64_t* bytes);
 #define GBR_K_ADAM 8
 #define GBR_K_LOSS 9
 #define GBR_K_MLP 10         /* forward and backward */
-#define GBR_K_TILE_SCAN 11
-#define GBR_K_DEPTH_ORDER 12  /* per-frame depth ranks of the visible splats */
+#define GBR_K_TILE_SCAN 11   /* tile offsets, with the forward scheduling classes */
+#define GBR_K_DEPTH_ORDER 12  /* per-frame depth ranks of the visible splats (and the splat-offset scan) */
 #define GBR_K_COUNT 13
 int gbr_timing(gbr_ctx* ctx, int32_t which, int32_t enable);
 int gbr_timing_read(gbr_ctx* ctx, int32_t which, float* ms);

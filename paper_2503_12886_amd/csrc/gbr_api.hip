@@ -406,8 +406,8 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
   }
   {
     KTimer t(c, GBR_K_TILE_SCAN, s);
-    launch_scan_u32(c->tile_count, c->tile_start, c->n_tiles, c->scan_scratch, c->d_status, c->cap_entries,
-                    &c->d_status->entries, s);
+    // the forward classification (by list length) runs in the scan's first launch
+    launch_tile_scan_classify(a, c->scan_scratch, c->cap_entries, &c->d_status->entries, s);
   }
   GBR_HIP(hipGetLastError());
   c->last_raw = raw;
@@ -420,11 +420,11 @@ int enqueue_rasterize(gbr_ctx* c, float* images, hipStream_t s) {
   PassArgs a = make_args(c);
   {
     KTimer t(c, GBR_K_TILE_SORT, s);
-    // both schedules of this pass start empty: cleared at the pass start,
-    // or here when the pass is rasterised again
-    if (!c->cls_clean) launch_fill_u32(c->cls_cnt, 0u, 66, s);
+    // the forward schedule was built with the tile scan; the backward one
+    // starts empty: cleared at the pass start, or here when the pass is
+    // rasterised again
+    if (!c->cls_clean) launch_fill_u32(c->cls_cnt + 33, 0u, 33, s);
     c->cls_clean = false;
-    launch_classify_tiles(a, false, s);
   }
   {
     KTimer t(c, GBR_K_COMPOSITE_FWD, s);

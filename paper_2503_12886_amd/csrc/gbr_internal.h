@@ -323,6 +323,10 @@ void launch_tile_lists(const PassArgs& a, hipStream_t s);
 void launch_tile_count(const PassArgs& a, hipStream_t s);
 void launch_count_contrib(const PassArgs& a, hipStream_t s);
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s);
+// The tile scan (tile_count -> tile_start, total to total_out, checked against
+// cap_check) with the forward classification of the tiles in its first launch.
+void launch_tile_scan_classify(const PassArgs& a, uint32_t* block_sums, int64_t cap_check,
+                               unsigned long long* total_out, hipStream_t s);
 
 // The depth order of every frame's splats.  side is an independent scan whose
 // input is ready when the pass starts, run in the bucket scan's launches.

@@ -63,10 +63,7 @@ __device__ __forceinline__ void publish_total(unsigned long long total, StatusDe
   if (cap_check >= 0 && total > (unsigned long long)cap_check) status->overflow |= 1u;
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(ScanJobs jobs) {
-  __shared__ uint32_t lw[kScanThreads / 64];
-  int blk;
-  const ScanJob J = scan_job(jobs, &blk);
+__device__ __forceinline__ void scan_totals_block(const ScanJob& J, int blk, uint32_t* lw) {
   const uint32_t* __restrict__ in = J.in;
   const int64_t n = J.n;
   const int64_t base = (int64_t)blk * kScanBlock;
@@ -83,6 +80,13 @@ __global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(ScanJobs jobs
   uint32_t tot;
   block_excl_scan<kScanThreads>(s, lw, &tot);
   if (threadIdx.x == 0) J.block_sums[blk] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_totals_kernel(ScanJobs jobs) {
+  __shared__ uint32_t lw[kScanThreads / 64];
+  int blk;
+  const ScanJob J = scan_job(jobs, &blk);
+  scan_totals_block(J, blk, lw);
 }
 
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(ScanJobs jobs, StatusDev* status) {
@@ -454,40 +458,75 @@ void launch_tile_count(const PassArgs& a, hipStream_t s) {
 
 // ---------------------------------------------------------------- tile classes
 // Forward: work = list length; backward: entries the forward pass used (also
-// written out as the tile's last used position).  A
-// workgroup of 1024 tiles counts its tiles per class in LDS, reserves one
-// range per class in the class lists (33 global atomics), and writes its
-// tiles there.
-__global__ __launch_bounds__(1024) void classify_tiles_kernel(PassArgs a, int backward) {
-  __shared__ uint32_t cnt[33], base[33];
+// written out as the tile's last used position).  A workgroup of 1024 tiles
+// counts its tiles per class in LDS, reserves one range per class in the
+// class lists (33 global atomics), and writes its tiles there.  The forward
+// classification needs only the tile counts, so it runs in the tile scan's
+// first launch (workgroups after the scan's, 4 tiles per thread).
+template <int NTH>
+__device__ __forceinline__ void classify_block(const PassArgs& a, int blk, bool backward, uint32_t* cnt,
+                                               uint32_t* base) {
+  constexpr int PER = 1024 / NTH;   // tiles per thread
   if (threadIdx.x < 33) cnt[threadIdx.x] = 0u;
   __syncthreads();
-  const int g = blockIdx.x * 1024 + threadIdx.x;
-  int c = -1;
-  uint32_t slot = 0;
-  if (g < a.n_tiles) {
-    uint32_t work;
-    if (backward) {                       // the tile's last used position: the largest of its quadrants'
-      const uint4 ql = reinterpret_cast<const uint4*>(a.qlast)[g];
-      work = max(max(ql.x, ql.y), max(ql.z, ql.w));
-      a.tile_last[g] = work;
-    } else {
-      work = a.tile_start[g + 1] - a.tile_start[g];
+  int c[PER];
+  uint32_t slot[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int g = blk * 1024 + k * NTH + (int)threadIdx.x;
+    c[k] = -1;
+    slot[k] = 0;
+    if (g < a.n_tiles) {
+      uint32_t work;
+      if (backward) {                     // the tile's last used position: the largest of its quadrants'
+        const uint4 ql = reinterpret_cast<const uint4*>(a.qlast)[g];
+        work = max(max(ql.x, ql.y), max(ql.z, ql.w));
+        a.tile_last[g] = work;
+      } else {
+        work = a.tile_count[g];
+      }
+      c[k] = work_class(work);
+      slot[k] = atomicAdd(&cnt[c[k]], 1u);
     }
-    c = work_class(work);
-    slot = atomicAdd(&cnt[c], 1u);
   }
   __syncthreads();
   uint32_t* gcnt = a.cls_cnt + (backward ? 33 : 0);
   if (threadIdx.x < 33) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&gcnt[threadIdx.x], cnt[threadIdx.x]) : 0u;
   __syncthreads();
   uint32_t* lists = backward ? a.order_bwd : a.order_fwd;
-  if (c >= 0) lists[(int64_t)c * a.n_tiles + base[c] + slot] = (uint32_t)g;
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (c[k] >= 0) lists[(int64_t)c[k] * a.n_tiles + base[c[k]] + slot[k]] = (uint32_t)(blk * 1024 + k * NTH + threadIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void classify_tiles_kernel(PassArgs a, int backward) {
+  __shared__ uint32_t cnt[33], base[33];
+  classify_block<1024>(a, (int)blockIdx.x, backward != 0, cnt, base);
 }
 
 void launch_classify_tiles(const PassArgs& a, bool backward, hipStream_t s) {
   if (a.n_tiles == 0) return;
   hipLaunchKernelGGL(classify_tiles_kernel, dim3(div_up(a.n_tiles, 1024)), dim3(1024), 0, s, a, backward ? 1 : 0);
+}
+
+// The tile scan's totals pass (workgroups [0, nb)) and the forward
+// classification (the rest, 1024 tiles each) in one launch.
+__global__ __launch_bounds__(kScanThreads) void tile_totals_classify_kernel(ScanJobs jobs, PassArgs a) {
+  __shared__ uint32_t lw[kScanThreads / 64];
+  __shared__ uint32_t cnt[33], base[33];
+  if ((int)blockIdx.x < jobs.nb0) scan_totals_block(jobs.j0, (int)blockIdx.x, lw);
+  else classify_block<kScanThreads>(a, (int)blockIdx.x - jobs.nb0, false, cnt, base);
+}
+
+void launch_tile_scan_classify(const PassArgs& a, uint32_t* block_sums, int64_t cap_check,
+                               unsigned long long* total_out, hipStream_t s) {
+  ScanJobs J;
+  J.j0 = ScanJob{a.tile_count, a.tile_start, a.n_tiles, block_sums, cap_check, total_out, nullptr, 1};
+  J.j1 = ScanJob{nullptr, nullptr, 0, nullptr, -1, nullptr, nullptr, 1};
+  J.nb0 = (int)div_up((int64_t)a.n_tiles + 1, kScanBlock);
+  const int ncls = a.n_tiles > 0 ? div_up(a.n_tiles, 1024) : 0;
+  hipLaunchKernelGGL(tile_totals_classify_kernel, dim3(J.nb0 + ncls), dim3(kScanThreads), 0, s, J, a);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(J.nb0), dim3(kScanThreads), 0, s, J, a.status);
 }
 
 // ---------------------------------------------------------------- complete lists
