@@ -324,8 +324,13 @@ int gbr_stage_frames(gbr_ctx* ctx, const int64_t* gauss_offsets, const gbr_camer
    later call reallocates one of them (gbr_reserve, gbr_entry_count growing
    the entry capacity, a render needing larger per-pass buffers),
    gbr_graph_launch returns GBR_ERR_STATE without enqueueing anything, and
-   the caller captures again.  A graph must be destroyed before its
-   context. */
+   the caller captures again.  A captured render records no copy of its
+   per-frame table: gbr_graph_launch enqueues one on `stream` before the
+   replay when the device does not hold that table already (after the
+   capture, a gbr_stage_frames or an eager render), so replays of an
+   unchanged batch copy nothing.  Begin a capture only when earlier
+   replays of the context have completed.  A graph must be destroyed
+   before its context. */
 int gbr_graph_begin(gbr_ctx* ctx, void* stream);
 int gbr_graph_end(gbr_ctx* ctx, void* stream, gbr_graph** out);
 int gbr_graph_launch(gbr_graph* g, void* stream);

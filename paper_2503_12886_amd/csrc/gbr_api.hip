@@ -161,6 +161,11 @@ struct gbr_ctx {
   unsigned long long* d_posts = nullptr;   // posts the device has run
   int64_t posts = 0;               // posts enqueued (eagerly, or by launches of graphs holding them)
   int64_t capture_posts = 0;       // posts in the graph being captured
+  // frame table of captured passes (host capture slot): whether the device
+  // table holds it, and whether the graph being captured uses it
+  bool frames_replay_ready = false;
+  bool capture_uses_frames = false;
+  int capture_frames_B = 0;
   hipStream_t post_stream = nullptr;   // the stream of the latest post
   // pass state
   bool capturing = false;
@@ -191,6 +196,7 @@ struct gbr_graph {
   gbr_ctx* ctx = nullptr;         // the context whose buffers the captured work uses
   uint64_t alloc_gen = 0;         // its allocation generation at capture
   int64_t posts = 0;              // status posts the graph holds
+  bool uses_frames = false;       // a captured pass reads the capture slot's frame table
 };
 
 namespace {
@@ -362,22 +368,28 @@ int build_frames(gbr_ctx* c, const int64_t* goff, const gbr_camera* cams, int B,
   return GBR_OK;
 }
 
+// The frame table of a pass.  Eagerly it goes up through one of the
+// rotating host slots.  A captured pass leaves it in the capture slot and
+// records no copy: gbr_graph_launch uploads that slot before a replay when
+// the device table is not already it (after the capture, a restaging, or an
+// eager pass), so an unchanged batch costs no copy per replay.
 int stage_and_upload(gbr_ctx* c, hipStream_t s) {
-  int slot;
   if (c->capturing) {
-    slot = kCaptureSlot;
-  } else {
-    slot = c->next_slot;
-    c->next_slot = (c->next_slot + 1) % (kSlots - 1);
-    if (c->slot_used[slot]) GBR_HIP(hipEventSynchronize(c->slot_ev[slot]));
+    std::memcpy(c->h_frames + (int64_t)kCaptureSlot * c->cap_frames, c->frames_host.data(), sizeof(FrameDev) * c->B);
+    c->capture_frames_B = c->B;
+    c->capture_uses_frames = true;
+    c->frames_replay_ready = false;
+    return GBR_OK;
   }
+  const int slot = c->next_slot;
+  c->next_slot = (c->next_slot + 1) % (kSlots - 1);
+  if (c->slot_used[slot]) GBR_HIP(hipEventSynchronize(c->slot_ev[slot]));
   FrameDev* h = c->h_frames + (int64_t)slot * c->cap_frames;
   std::memcpy(h, c->frames_host.data(), sizeof(FrameDev) * c->B);
   GBR_HIP(hipMemcpyAsync(c->d_frames, h, sizeof(FrameDev) * c->B, hipMemcpyHostToDevice, s));
-  if (!c->capturing) {
-    GBR_HIP(hipEventRecord(c->slot_ev[slot], s));
-    c->slot_used[slot] = true;
-  }
+  GBR_HIP(hipEventRecord(c->slot_ev[slot], s));
+  c->slot_used[slot] = true;
+  c->frames_replay_ready = false;   // the device table is this pass's now
   return GBR_OK;
 }
 
@@ -1071,6 +1083,7 @@ int gbr_stage_frames(gbr_ctx* c, const int64_t* goff, const gbr_camera* cams, in
   }
   c->frames_host.swap(fr);
   std::memcpy(c->h_frames + (int64_t)kCaptureSlot * c->cap_frames, c->frames_host.data(), sizeof(FrameDev) * B);
+  c->frames_replay_ready = false;   // the next replay uploads it
   return GBR_OK;
 }
 
@@ -1079,6 +1092,7 @@ int gbr_graph_begin(gbr_ctx* c, void* stream) {
   GBR_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed));
   c->capturing = true;
   c->capture_posts = 0;
+  c->capture_uses_frames = false;
   return GBR_OK;
 }
 
@@ -1095,6 +1109,7 @@ int gbr_graph_end(gbr_ctx* c, void* stream, gbr_graph** out) {
   g->ctx = c;
   g->alloc_gen = c->alloc_gen;
   g->posts = c->capture_posts;
+  g->uses_frames = c->capture_uses_frames;
   *out = g;
   return GBR_OK;
 }
@@ -1102,6 +1117,12 @@ int gbr_graph_end(gbr_ctx* c, void* stream, gbr_graph** out) {
 int gbr_graph_launch(gbr_graph* g, void* stream) {
   if (!g) return GBR_ERR_INVALID_ARG;
   if (g->ctx->alloc_gen != g->alloc_gen) return GBR_ERR_STATE;   // a buffer it uses was reallocated
+  gbr_ctx* c = g->ctx;
+  if (g->uses_frames && !c->frames_replay_ready) {
+    GBR_HIP(hipMemcpyAsync(c->d_frames, c->h_frames + (int64_t)kCaptureSlot * c->cap_frames,
+                           sizeof(FrameDev) * c->capture_frames_B, hipMemcpyHostToDevice, (hipStream_t)stream));
+    c->frames_replay_ready = true;
+  }
   GBR_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
   if (g->posts) {
     g->ctx->posts += g->posts;
