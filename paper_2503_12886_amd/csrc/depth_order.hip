@@ -45,12 +45,39 @@ __device__ __forceinline__ void load_bucket_keys(const PassArgs& a, const FrameD
   for (int i = 0; i < kBucketItems; ++i) bk[i] = key[i] != 0xffffffffu ? depth_bucket(key[i], mn, mx, a.nbk) : 0u;
 }
 
+// The frame's depth range: the minimum and maximum over the projection's
+// per-workgroup slots of frame b (every thread gets it).
+__device__ __forceinline__ void frame_depth_range(const PassArgs& a, const FrameDev& F, int b, uint32_t* red,
+                                                  uint32_t& mn, uint32_t& mx) {
+  const int64_t nbp = (F.gauss_count + 255) / 256;
+  const uint32_t* mm = a.blk_mm + 2 * (F.gauss_base / 256 + b);
+  uint32_t lo = 0xffffffffu, hi = 0u;
+  for (int64_t i = threadIdx.x; i < nbp; i += kBucketThreads) {
+    lo = min(lo, mm[2 * i]);
+    hi = max(hi, mm[2 * i + 1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+  }
+  constexpr int NW = kBucketThreads / 64;
+  if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = lo; red[NW + (threadIdx.x >> 6)] = hi; }
+  __syncthreads();
+  mn = red[0];
+  mx = red[NW];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) { mn = min(mn, red[w]); mx = max(mx, red[NW + w]); }
+}
+
 __global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxBuckets];
+  __shared__ uint32_t red[2 * (kBucketThreads / 64)];
   const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
   for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
-  const uint32_t mn = a.minmax[b * kMinmaxStride], mx = a.minmax[b * kMinmaxStride + 1];
+  uint32_t mn, mx;
+  frame_depth_range(a, F, b, red, mn, mx);
   uint32_t key[kBucketItems], bk[kBucketItems];
   load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();
@@ -64,11 +91,13 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a
 
 __global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs a) {
   __shared__ uint32_t hist[kMaxBuckets];
+  __shared__ uint32_t red[2 * (kBucketThreads / 64)];
   const int b = blockIdx.y, blk = blockIdx.x;
   const FrameDev& F = a.frames[b];
   if ((int64_t)blk * kBucketBlock >= F.gauss_count) return;
   for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
-  const uint32_t mn = a.minmax[b * kMinmaxStride], mx = a.minmax[b * kMinmaxStride + 1];
+  uint32_t mn, mx;
+  frame_depth_range(a, F, b, red, mn, mx);
   uint32_t key[kBucketItems], bk[kBucketItems], rk[kBucketItems];
   load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();

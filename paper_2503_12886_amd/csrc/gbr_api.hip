@@ -48,14 +48,12 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
-// Clears the per-pass counters: per-frame depth ranges, the large-bucket
-// list, the status, and the tile-class counts of both schedules (66 words;
-// the grid has at least 256 threads).
-__global__ void begin_pass_kernel(PassArgs a, int n_bkt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < a.B) { a.minmax[i * kMinmaxStride] = 0xffffffffu; a.minmax[i * kMinmaxStride + 1] = 0u; }
-  if (i < 66) a.cls_cnt[i] = 0u;
-  if (i == 0) { a.status->overflow = 0u; a.status->entries = 0ull; }
+// Clears the per-pass counters (the status and the tile-class counts of both
+// schedules, 66 words) for a pass whose projection, which clears them
+// otherwise, does not run: no frame has Gaussians.  One block of 256.
+__global__ void begin_pass_kernel(PassArgs a) {
+  if (threadIdx.x < 66) a.cls_cnt[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) { a.status->overflow = 0u; a.status->entries = 0ull; }
 }
 
 __global__ void clear_overflow_kernel(StatusDev* status) { status->overflow = 0u; }
@@ -128,7 +126,7 @@ struct gbr_ctx {
   uint8_t* part_flag = nullptr;
   uint8_t* cmask = nullptr;
   // per-frame depth order
-  uint32_t *minmax = nullptr, *bkt_count = nullptr, *bkt_moff = nullptr, *bkt_start = nullptr;
+  uint32_t *blk_mm = nullptr, *bkt_count = nullptr, *bkt_moff = nullptr, *bkt_start = nullptr;
   unsigned long long *bkeys = nullptr, *bkeys_alt = nullptr;
   uint32_t *depth_sorted = nullptr, *rank = nullptr;
   int64_t cap_bkt = 0, cap_bkt_cells = 0;
@@ -223,7 +221,7 @@ PassArgs make_args(gbr_ctx* c) {
   a.seg_words = c->seg_words;
   a.seg_stride = a.bitmap_words / a.seg_words;
   a.seg_cnt = c->seg_cnt;
-  a.minmax = c->minmax; a.bkt_count = c->bkt_count; a.bkt_moff = c->bkt_moff; a.bkt_start = c->bkt_start;
+  a.blk_mm = c->blk_mm; a.bkt_count = c->bkt_count; a.bkt_moff = c->bkt_moff; a.bkt_start = c->bkt_start;
   a.bkeys = c->bkeys; a.bkeys_alt = c->bkeys_alt; a.depth_sorted = c->depth_sorted; a.rank = c->rank;
   a.n_iter = c->n_iter; a.n_contrib = c->n_contrib; a.t_final = c->t_final; a.part = c->part;
   a.tg = c->tg;
@@ -308,7 +306,7 @@ void free_all(gbr_ctx* c) {
   dfree(c->tile_count); dfree(c->tile_start); dfree(c->tile_last); dfree(c->qlast); dfree(c->tbits); dfree(c->seg_cnt);
   dfree(c->order_fwd); dfree(c->order_bwd); dfree(c->cls_cnt);
   dfree(c->sorted); dfree(c->part); dfree(c->part_flag); dfree(c->cmask);
-  dfree(c->minmax); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start);
+  dfree(c->blk_mm); dfree(c->bkt_count); dfree(c->bkt_moff); dfree(c->bkt_start);
   dfree(c->bkeys); dfree(c->bkeys_alt); dfree(c->depth_sorted); dfree(c->rank);
   dfree(c->n_iter); dfree(c->n_contrib); dfree(c->t_final); dfree(c->scan_scratch); dfree(c->scan_scratch_splat);
   dfree(c->draw_scratch);
@@ -397,14 +395,13 @@ int enqueue_preprocess(gbr_ctx* c, const float* raw, hipStream_t s) {
   int rc = stage_and_upload(c, s);
   if (rc) return rc;
   PassArgs a = make_args(c);
-  const int n_bkt = c->B * c->nbk;
-  hipLaunchKernelGGL(begin_pass_kernel, dim3(div_up(std::max(std::max(c->n_tiles, n_bkt), c->B), 256)), dim3(256), 0,
-                     s, a, n_bkt);
-  c->cls_clean = true;
+  bool projected;
   {
     KTimer t(c, GBR_K_PREPROCESS, s);
-    launch_preprocess(a, raw, c->max_frame_splats, s);
+    projected = launch_preprocess(a, raw, c->max_frame_splats, s);   // also clears the pass's counters
   }
+  if (!projected) hipLaunchKernelGGL(begin_pass_kernel, dim3(1), dim3(256), 0, s, a);
+  c->cls_clean = true;
   {
     KTimer t(c, GBR_K_DEPTH_ORDER, s);
     // the scan of the splats' tile counts (preprocess output) shares the bucket scan's launches
@@ -526,7 +523,7 @@ int64_t workspace_bytes(const WorkspaceCaps& k) {
   b += n(k.frames) * (int64_t)sizeof(FrameDev) + (int64_t)sizeof(StatusDev) + 8;   // + the post counter
   b += n(k.splats * kRecF) * 4 + n(k.splats) * 16 + n(k.splats) * 4 + n(k.splats + 1) * 4 + n(k.splats) * 4;
   b += (n(k.tiles) + n(k.tiles + 1) + n(k.tiles) + n(4 * k.tiles) + 2 * n(33 * k.tiles)) * 4 + 66 * 4;
-  b += n((int64_t)kMinmaxStride * k.frames) * 4;
+  b += n(2 * ((int64_t)div_up(k.splats, 256) + k.frames + 1)) * 4;   // projection workgroups' depth ranges
   b += (n(k.splats) * 2) * 8 + n(k.splats) * 4 * 2;                       // bucket keys, order, rank
   b += (n(k.bkt_cells) + n(k.bkt_cells + 1) + n(k.bkt + 1)) * 4;  // depth buckets
   b += 3 * n(k.pixels) * 4;                                                  // n_iter, n_contrib, t_final
@@ -625,7 +622,7 @@ int gbr_create(const gbr_config* cfg, gbr_ctx** out) {
   TRY(dalloc(&c->order_fwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->order_bwd, 33 * c->cap_tiles));
   TRY(dalloc(&c->cls_cnt, 66));
-  TRY(dalloc(&c->minmax, (int64_t)kMinmaxStride * c->cap_frames));
+  TRY(dalloc(&c->blk_mm, 2 * ((int64_t)div_up(c->cap_splats, 256) + c->cap_frames + 1)));
   TRY(dalloc(&c->bkeys, c->cap_splats));
   TRY(dalloc(&c->bkeys_alt, c->cap_splats));
   TRY(dalloc(&c->depth_sorted, c->cap_splats));

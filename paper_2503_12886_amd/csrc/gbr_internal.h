@@ -66,7 +66,6 @@ struct TangentArgs {
 };
 
 // Everything the pass kernels need, passed by value.
-constexpr int kMinmaxStride = 32;
 
 struct PassArgs {
   const FrameDev* frames;
@@ -102,7 +101,8 @@ struct PassArgs {
   int32_t bitmap_words;     // words per tile bitmap row (largest frame's splats / 32, rounded up to 16)
   int32_t seg_words;        // words per row segment (8 or 16); a segment's set bits are counted once
   int32_t seg_stride;       // segments per row = bitmap_words / seg_words
-  uint32_t* minmax;         // [B][kMinmaxStride] min, max binary32 depth bits of the frame's valid splats
+  uint32_t* blk_mm;         // [2 per projection workgroup] min, max binary32 depth bits of its valid splats;
+                            // frame b's workgroup j at gauss_base / 256 + b + j (frames never share one)
                             //   (a 128-byte line per frame, so frames' atomics do not share a line)
   uint32_t* bkt_count;      // [B * nbk][nblk] per-block bucket counts
   uint32_t* bkt_moff;       // [B * nbk * nblk + 1] their exclusive scan
@@ -313,7 +313,9 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blo
 // Two independent scans in the same two launches (distinct block_sums).
 void launch_scan_u32_pair(const ScanJob& j0, const ScanJob& j1, StatusDev* status, hipStream_t s);
 int64_t scan_scratch_words(int64_t n);
-void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
+// Returns whether it launched (no frame has Gaussians otherwise): the
+// launch also clears the pass's counters.
+bool launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s);
 // Words per bitmap row segment for frames of up to max_frame_tiles tiles
 // (the workgroup that builds a segment of every row of a frame holds them in LDS).
 constexpr int kMaxRowSegs = 1024;   // segments per bitmap row at most (the compositing lists them in LDS)

@@ -177,8 +177,10 @@ void launch_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* blo
 // float64 (so that the integer decisions -- which pixels and tiles a Gaussian
 // may reach, and its binary32 depth key -- are exactly reproducible), the
 // per-pixel record rounded to float32.  Each block also reduces its splats'
-// depth keys to a minimum and maximum and folds them into the frame's depth
-// range with one pair of atomics (the range scales the depth buckets).
+// depth keys to a minimum and maximum, stored in the block's own slot (the
+// depth passes take the frame's range, which scales the depth buckets, from
+// those slots).  The pass's first kernel, it also clears the pass's counters
+// (tile-class counts, overflow flag) in block (0, 0).
 struct Projected {
   bool valid;
   double mx, my, A, Bq, C, o, tz;
@@ -261,6 +263,10 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && b == 0) {   // the pass's counters: this is its first kernel
+    if (threadIdx.x < 66) a.cls_cnt[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) { a.status->overflow = 0u; a.status->entries = 0ull; }
+  }
   if ((int64_t)blockIdx.x * 256 >= F.gauss_count) return;   // uniform per block
   const int tsh = __ffs(a.tile) - 1;                         // tile is a power of two
   uint32_t dmin = 0xffffffffu, dmax = 0u;
@@ -296,24 +302,23 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PassArgs a, const float
     a.cnt[s] = count;
     a.dkey[s] = key;
   }
-  // frame depth range: wave reductions, then one pair of atomics per block
+  // the block's depth range (wave reductions), stored in its own slot: the
+  // depth passes reduce the frame's slots, so nothing is cleared or merged
   dmin = wave_min_u32(dmin);
   dmax = wave_max_u32(dmax);
   if ((threadIdx.x & 63) == 0) { wmin[threadIdx.x >> 6] = dmin; wmax[threadIdx.x >> 6] = dmax; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    dmin = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
-    dmax = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-    if (dmin <= dmax) {
-      atomicMin(&a.minmax[b * kMinmaxStride], dmin);
-      atomicMax(&a.minmax[b * kMinmaxStride + 1], dmax);
-    }
+    uint32_t* mm = a.blk_mm + 2 * (F.gauss_base / 256 + b + blockIdx.x);
+    mm[0] = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+    mm[1] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
   }
 }
 
-void launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s) {
-  if (a.B == 0 || max_frame_splats == 0) return;
+bool launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_splats, hipStream_t s) {
+  if (a.B == 0 || max_frame_splats == 0) return false;
   hipLaunchKernelGGL(preprocess_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a, raw);
+  return true;
 }
 
 // ---------------------------------------------------------------- binning
