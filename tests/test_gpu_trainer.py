@@ -266,6 +266,32 @@ def test_pipelined_steps_equal_one_by_one_and_recover_from_overflow():
     a.close(); b.close()
 
 
+def test_replay_after_an_eager_render_uploads_the_captured_frames():
+    """A captured step reads its own frame table: an eager render of other
+    cameras on the same context leaves the device holding that render's
+    table, and the next replay uploads the captured one again (the steps
+    equal those of a trainer that rendered nothing in between)."""
+    cfg, bases, mlp, theta, cams, targets = small(seed=11)
+    cams2 = synth.make_cameras(cfg.B, cfg.width, cfg.height, seed=9)
+    a = Trainer(cfg, bases, mlp)
+    b = Trainer(cfg, bases, mlp)
+    for tr in (a, b):
+        tr.set_batch(theta, targets, cams)
+        tr.step()
+        tr.capture()
+        tr.step()
+    other = a.torch.zeros(gbr.image_numel(cams2), device="cuda")
+    gbr.gbr_render(a.ctx, a.raw, a.offsets, cams2, other)     # same sizes, other poses; b renders nothing
+    gbr.gbr_query_status(a.ctx, a.stream)
+    assert float(other.abs().sum()) > 0
+    la = [a.step().loss for _ in range(2)]
+    lb = [b.step().loss for _ in range(2)]
+    assert la == lb
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+    a.close(); b.close()
+
+
 def test_status_ring_eager_and_captured_posts():
     """Status posts land in a ring of 4 host records numbered by the device:
     an eager post and the posts at the end of captured steps read back what
