@@ -118,21 +118,38 @@ def test_naive_batch_scheme_gives_the_batched_gradients():
 def test_paper_feature_mask_keeps_scale_and_opacity_unblended():
     """With the paper's feature mask (Sec. A.3: scale and opacity are not
     blended) their delta slices stay exactly zero through training while the
-    base model and the other deltas move."""
+    base model and the other deltas move.  From the same start (those slices
+    zero) one masked step equals one unmasked step bit for bit everywhere
+    but there: the mask withholds exactly their update and nothing else (the
+    gradients, and so the Adam moments, are the same)."""
+    from dataclasses import replace
     from paper_2503_12886_amd.trainer import UNBLENDED
     cfg, bases, mlp, theta, cams, targets = small(seed=5)
-    cfg.paper_mask = True
-    a = Trainer(cfg, bases, mlp)
-    a.set_batch(theta, targets, cams)
+    masked = list(UNBLENDED)
+    start = bases.copy()
+    start[1:][:, :, masked] = 0.0
+    a = Trainer(replace(cfg, paper_mask=True), start, mlp)
+    b = Trainer(cfg, start, mlp)
+    for tr in (a, b):
+        tr.set_batch(theta, targets, cams)
     b0 = a.bases.cpu().numpy().copy()
-    assert not b0[1:][:, :, list(UNBLENDED)].any()
-    for _ in range(3):
+    assert not b0[1:][:, :, masked].any()
+    a.step()
+    b.step()
+    sa, sb = state(a), state(b)
+    keep = np.ones(sa[0].shape, bool)
+    keep[1:, :, masked] = False
+    assert np.array_equal(sa[0][keep], sb[0][keep])          # bases outside the masked slices
+    assert not sa[0][~keep].any() and sb[0][~keep].any()     # masked: held in a, moved in b
+    for x, y in zip(sa[1:], sb[1:]):                          # Adam moments and the MLP: identical
+        assert np.array_equal(x, y)
+    for _ in range(2):
         a.step()
     b1 = a.bases.cpu().numpy()
-    assert not b1[1:][:, :, list(UNBLENDED)].any()
+    assert not b1[1:][:, :, masked].any()
     assert not np.array_equal(b1[0], b0[0])
     assert not np.array_equal(b1[1:][:, :, :3], b0[1:][:, :, :3])
-    a.close()
+    a.close(); b.close()
 
 
 def test_online_trainer_streams_frames_through_the_pools():
