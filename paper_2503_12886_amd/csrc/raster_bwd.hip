@@ -78,6 +78,31 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
   }
 }
 
+// The sums over the 16 lanes of each row of 9 values, transposed into one
+// register: at each halving step two registers are paired, each lane keeping
+// one of the two values and adding its partner's copy of it (partners by
+// row_ror:8, row_half_mirror, quad_perm xor 2, then xor 1), so 27 VALU
+// operations replace 36 in-row shifts.  Lane i of a row ends with the row's
+// total of value 8 when i is odd, else of value 4 i1 + 2 i2 + i3 (i1, i2, i3
+// the bits 1 to 3 of i); every lane's total covers each of the 16 lanes once.
+template <int CTRL>
+__device__ __forceinline__ float pair_fold(float x, float y, bool hi) {
+  const float z = hi ? y : x, w = hi ? x : y;
+  return z + dpp_mov<CTRL, 0xf, 0xf, false>(w);
+}
+__device__ __forceinline__ float rows_transposed9(const float (&v)[9], int lane) {
+  constexpr int kRor8 = 0x128, kHalfMirror = 0x141, kQuadXor2 = 0x4e, kQuadXor1 = 0xb1;
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+  const float a0 = pair_fold<kRor8>(v[0], v[1], b3), a1 = pair_fold<kRor8>(v[2], v[3], b3);
+  const float a2 = pair_fold<kRor8>(v[4], v[5], b3), a3 = pair_fold<kRor8>(v[6], v[7], b3);
+  const float a4 = v[8] + dpp_mov<kRor8, 0xf, 0xf, false>(v[8]);
+  const float c0 = pair_fold<kHalfMirror>(a0, a1, b2), c1 = pair_fold<kHalfMirror>(a2, a3, b2);
+  const float c2 = a4 + dpp_mov<kHalfMirror, 0xf, 0xf, false>(a4);
+  const float d0 = pair_fold<kQuadXor2>(c0, c1, b1);
+  const float d1 = c2 + dpp_mov<kQuadXor2, 0xf, 0xf, false>(c2);
+  return pair_fold<kQuadXor1>(d0, d1, b0);
+}
+
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
@@ -195,23 +220,25 @@ __global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_
         // Sums of the 4 x 9 partials over the wave's 64 lanes, in a fixed
         // order: fold lanes 32 apart (entries 0|1 and 2|3 into one register
         // per value), then 16 apart (all four entries of a value in one
-        // register, a row each), then four in-row shifts.  Lane 16r + 15 of
-        // acc[0][c] ends with value c of entry (r >> 1) | ((r & 1) << 1).
+        // register, a row each: row r holds entry (r >> 1) | ((r & 1) << 1)),
+        // then the transposed in-row sums, which leave each of the entry's 9
+        // totals in its own lane of the row.
         fold32x9(acc[0], acc[1]);
         fold32x9(acc[2], acc[3]);
         fold16x9(acc[0], acc[2]);
-        row_sum9_to15(acc[0]);
+        const float tot = rows_transposed9(acc[0], lane);
         // the group's chunk positions (< CHUNK <= 256), one byte each, so that
-        // a row's leader picks its entry with one shift
+        // a lane picks its row's entry with one shift
         const uint32_t epack = (uint32_t)(e[0] & 0xff) | ((uint32_t)(e[1] & 0xff) << 8) |
                                ((uint32_t)(e[2] & 0xff) << 16) | ((uint32_t)(e[3] & 0xff) << 24);
-        if ((lane & 15) == 15) {
+        const int li = lane & 15;
+        if ((li & 1) == 0 || li == 1) {   // one lane per value of the row
           const int r = lane >> 4, u = (r >> 1) | ((r & 1) << 1);
           const int eu = (int)((epack >> (8 * u)) & 0xffu);
+          const int c = (li & 1) ? 8 : (((li >> 1) & 1) << 2) | (((li >> 2) & 1) << 1) | ((li >> 3) & 1);
           if (u < cnt) {
-#pragma unroll
-            for (int c = 0; c < 9; ++c) red[eu][w][c] = acc[0][c];
-            wany8[eu * 4 + w] = 1;
+            red[eu][w][c] = tot;
+            if (li == 1) wany8[eu * 4 + w] = 1;
           }
         }
       }
