@@ -81,27 +81,44 @@ __device__ __forceinline__ void entry_grad(const float4 r0, const float4 r1, con
 // The sums over the 16 lanes of each row of 9 values, transposed into one
 // register: at each halving step two registers are paired, each lane keeping
 // one of the two values and adding its partner's copy of it (partners by
-// row_ror:8, row_half_mirror, quad_perm xor 2, then xor 1), so 27 VALU
+// row_ror:8, row_half_mirror, quad_perm xor 2, then xor 1), so 21 VALU
 // operations replace 36 in-row shifts.  Lane i of a row ends with the row's
 // total of value 8 when i is odd, else of value 4 i1 + 2 i2 + i3 (i1, i2, i3
 // the bits 1 to 3 of i); every lane's total covers each of the 16 lanes once.
+// In the first two steps the two halves of a pair are whole DPP banks (4
+// lanes), so each half is one DPP add that writes only its banks, in place
+// (inline assembly: two wait states before DPP reads of VALU results);
+// the last two steps select between the registers.
 template <int CTRL>
 __device__ __forceinline__ float pair_fold(float x, float y, bool hi) {
   const float z = hi ? y : x, w = hi ? x : y;
   return z + dpp_mov<CTRL, 0xf, 0xf, false>(w);
 }
+#define GBR_BANK_PAIR(ctrl, x, y, mx, my)                                                    \
+  "v_add_f32_dpp %" #x ", %" #x ", %" #x " " ctrl " row_mask:0xf bank_mask:" mx "\n\t"     \
+  "v_add_f32_dpp %" #x ", %" #y ", %" #y " " ctrl " row_mask:0xf bank_mask:" my "\n\t"
 __device__ __forceinline__ float rows_transposed9(const float (&v)[9], int lane) {
-  constexpr int kRor8 = 0x128, kHalfMirror = 0x141, kQuadXor2 = 0x4e, kQuadXor1 = 0xb1;
-  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
-  const float a0 = pair_fold<kRor8>(v[0], v[1], b3), a1 = pair_fold<kRor8>(v[2], v[3], b3);
-  const float a2 = pair_fold<kRor8>(v[4], v[5], b3), a3 = pair_fold<kRor8>(v[6], v[7], b3);
-  const float a4 = v[8] + dpp_mov<kRor8, 0xf, 0xf, false>(v[8]);
-  const float c0 = pair_fold<kHalfMirror>(a0, a1, b2), c1 = pair_fold<kHalfMirror>(a2, a3, b2);
-  const float c2 = a4 + dpp_mov<kHalfMirror, 0xf, 0xf, false>(a4);
-  const float d0 = pair_fold<kQuadXor2>(c0, c1, b1);
-  const float d1 = c2 + dpp_mov<kQuadXor2, 0xf, 0xf, false>(c2);
+  constexpr int kQuadXor2 = 0x4e, kQuadXor1 = 0xb1;
+  float a0 = v[0], a1 = v[2], a2 = v[4], a3 = v[6], a4 = v[8];
+  // partners 8 apart: the first value in lanes 0-7 (banks 0, 1), the second in 8-15
+  asm volatile("s_nop 1\n\t"
+               GBR_BANK_PAIR("row_ror:8", 0, 5, "0x3", "0xc") GBR_BANK_PAIR("row_ror:8", 1, 6, "0x3", "0xc")
+               GBR_BANK_PAIR("row_ror:8", 2, 7, "0x3", "0xc") GBR_BANK_PAIR("row_ror:8", 3, 8, "0x3", "0xc")
+               "v_add_f32_dpp %4, %4, %4 row_ror:8 row_mask:0xf bank_mask:0xf"
+               : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4)
+               : "v"(v[1]), "v"(v[3]), "v"(v[5]), "v"(v[7]));
+  // partners mirrored inside 8 lanes: the first value in banks 0 and 2, the second in 1 and 3
+  asm volatile("s_nop 1\n\t"
+               GBR_BANK_PAIR("row_half_mirror", 0, 3, "0x5", "0xa") GBR_BANK_PAIR("row_half_mirror", 1, 4, "0x5", "0xa")
+               "v_add_f32_dpp %2, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xf"
+               : "+v"(a0), "+v"(a2), "+v"(a4)
+               : "v"(a1), "v"(a3));
+  const bool b1 = lane & 2, b0 = lane & 1;
+  const float d0 = pair_fold<kQuadXor2>(a0, a2, b1);
+  const float d1 = a4 + dpp_mov<kQuadXor2, 0xf, 0xf, false>(a4);
   return pair_fold<kQuadXor1>(d0, d1, b0);
 }
+#undef GBR_BANK_PAIR
 
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_bwd_kernel(PassArgs a,
