@@ -189,43 +189,6 @@ __device__ __forceinline__ int tile_of_rank(const uint32_t* cnt, const uint32_t*
   return -1;
 }
 
-// Sums over the 16 lanes of each row of 9 values; each row's totals land in
-// its lane 15 (lanes 15, 31, 47, 63).  Three shifts (out-of-row sources read
-// zero), then a rotation by 8: lane 15 reads lane 7, as a shift would.  The
-// last level is written as DPP adds in inline assembly (the compiler sinks
-// that level's adds into the lane-15 branch and would keep a separate DPP
-// move per value), after the two wait states that a DPP read of a VALU
-// result needs.
-__device__ __forceinline__ void row_sum9_to15(float* x) {
-#pragma unroll
-  for (int c = 0; c < 9; ++c) {
-    x[c] += dpp_mov<0x111, 0xf, 0xf, true>(x[c]);   // row_shr:1
-    x[c] += dpp_mov<0x112, 0xf, 0xf, true>(x[c]);   // row_shr:2
-    x[c] += dpp_mov<0x114, 0xf, 0xf, true>(x[c]);   // row_shr:4
-  }
-#define GBR_ROR8_ADD(i) "v_add_f32_dpp %" #i ", %" #i ", %" #i " row_ror:8 row_mask:0xf bank_mask:0xf\n\t"
-  asm volatile("s_nop 1\n\t"
-               GBR_ROR8_ADD(0) GBR_ROR8_ADD(1) GBR_ROR8_ADD(2) GBR_ROR8_ADD(3) GBR_ROR8_ADD(4)
-               GBR_ROR8_ADD(5) GBR_ROR8_ADD(6) GBR_ROR8_ADD(7) GBR_ROR8_ADD(8)
-               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
-                 "+v"(x[8]));
-#undef GBR_ROR8_ADD
-}
-
-// After row_sum9_to15: lanes 31 and 63 add the totals of the row before
-// them (lanes 15 and 47), so each half-wave's total lands in its last lane.
-// DPP row_bcast:15 with row mask 0b1010 (rows 1 and 3 written), after the
-// two wait states a DPP read of a VALU result needs.
-__device__ __forceinline__ void row_pair_add9(float* x) {
-#define GBR_BCAST15_ADD(i) "v_add_f32_dpp %" #i ", %" #i ", %" #i " row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
-  asm volatile("s_nop 1\n\t"
-               GBR_BCAST15_ADD(0) GBR_BCAST15_ADD(1) GBR_BCAST15_ADD(2) GBR_BCAST15_ADD(3) GBR_BCAST15_ADD(4)
-               GBR_BCAST15_ADD(5) GBR_BCAST15_ADD(6) GBR_BCAST15_ADD(7) GBR_BCAST15_ADD(8)
-               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]), "+v"(x[7]),
-                 "+v"(x[8]));
-#undef GBR_BCAST15_ADD
-}
-
 // Lane swaps of gfx950: after swap32(x, y), x holds (x lanes 0-31, y lanes
 // 0-31) and y holds (x lanes 32-63, y lanes 32-63); after swap16(x, y), by
 // rows of 16 lanes, x holds (x0, y0, x2, y2) and y holds (x1, y1, x3, y3).
@@ -247,16 +210,6 @@ __device__ __forceinline__ void fold32x9(float* x, float* y) {   // x[c] <- x[c]
                  "+v"(y[7]), "+v"(y[8]));
 #pragma unroll
   for (int c = 0; c < 9; ++c) x[c] += y[c];
-}
-__device__ __forceinline__ void fold16x5(float* x, float* y) {   // x[j] <- x[j] + y[j] folded, j < 5
-  asm volatile("s_nop 1\n\t"
-               GBR_SWAP_PAIR("v_permlane16_swap_b32", 0, 5) GBR_SWAP_PAIR("v_permlane16_swap_b32", 1, 6)
-               GBR_SWAP_PAIR("v_permlane16_swap_b32", 2, 7) GBR_SWAP_PAIR("v_permlane16_swap_b32", 3, 8)
-               GBR_SWAP_PAIR("v_permlane16_swap_b32", 4, 9) "s_nop 1"
-               : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(y[0]), "+v"(y[1]), "+v"(y[2]),
-                 "+v"(y[3]), "+v"(y[4]));
-#pragma unroll
-  for (int j = 0; j < 5; ++j) x[j] += y[j];
 }
 __device__ __forceinline__ void fold16x9(float* x, float* y) {   // x[c] <- x[c] + y[c] folded, c < 9
   asm volatile("s_nop 1\n\t"

@@ -120,6 +120,14 @@ __device__ __forceinline__ float rows_transposed9(const float (&v)[9], int lane)
 }
 #undef GBR_BANK_PAIR
 
+// Adds rows 0 and 1, and rows 2 and 3, lane by lane (each half-wave's two
+// rows end with the same sums): a lane swap of the register with its copy.
+__device__ __forceinline__ float row_pair_sum(float x) {
+  float y = x;
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+  return x + y;
+}
+
 template <int T, int CHUNK>
 __global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_bwd_kernel(PassArgs a,
                                                                          const float* __restrict__ dimages) {
@@ -203,8 +211,8 @@ __global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_
         }
         if (cnt <= 2) {
           // a short group (the tail of a chunk): two entries, one lane-swap
-          // fold, the row sums, then each row pair added (lanes 31 and 63
-          // end with entries 0 and 1)
+          // fold (entry 0 in lanes 0-31, entry 1 in 32-63), the transposed
+          // row sums, then each half-wave's two rows added
           float acc2[2][9];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
@@ -213,15 +221,15 @@ __global__ __launch_bounds__(TileShapeB<T>::NT, T == 16 ? 8 : 1) void composite_
             entry_grad<S::PX>(s0[i], s1[i], s2[i].x, li, pxf, pyf, nit, T_, SG, G0, G1, G2, acc2[u]);
           }
           fold32x9(acc2[0], acc2[1]);
-          row_sum9_to15(acc2[0]);
-          row_pair_add9(acc2[0]);
-          if ((lane & 31) == 31) {
+          const float tot = row_pair_sum(rows_transposed9(acc2[0], lane));
+          const int li = lane & 15;
+          if ((lane & 16) == 0 && ((li & 1) == 0 || li == 1)) {   // rows 0 and 2, one lane per value
             const int u = lane >> 5;
             const int eu = u == 0 ? e[0] : e[1];
+            const int c = (li & 1) ? 8 : (((li >> 1) & 1) << 2) | (((li >> 2) & 1) << 1) | ((li >> 3) & 1);
             if (u < cnt) {
-#pragma unroll
-              for (int c = 0; c < 9; ++c) red[eu][w][c] = acc2[0][c];
-              wany8[eu * 4 + w] = 1;
+              red[eu][w][c] = tot;
+              if (li == 1) wany8[eu * 4 + w] = 1;
             }
           }
           continue;
