@@ -70,12 +70,20 @@ __device__ __forceinline__ void frame_depth_range(const PassArgs& a, const Frame
   for (int w = 1; w < NW; ++w) { mn = min(mn, red[w]); mx = max(mx, red[NW + w]); }
 }
 
+// A block's buckets are split between kBucketParts workgroups (grid x =
+// block * kBucketParts + part): each reads the block's keys and handles
+// only those in its share of the buckets, so the pass fills twice as many
+// CUs as there are (frame, block) pairs.  nbk is a power of two >= 64.
+constexpr int kBucketParts = 2;
+
 __global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a) {
-  __shared__ uint32_t hist[kMaxBuckets];
+  __shared__ uint32_t hist[kMaxBuckets / kBucketParts];
   __shared__ uint32_t red[2 * (kBucketThreads / 64)];
-  const int b = blockIdx.y, blk = blockIdx.x;
+  const int b = blockIdx.y, blk = blockIdx.x / kBucketParts;
+  const int per = a.nbk / kBucketParts;
+  const uint32_t lo = (uint32_t)((blockIdx.x % kBucketParts) * per);
   const FrameDev& F = a.frames[b];
-  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
+  for (int t = threadIdx.x; t < per; t += kBucketThreads) hist[t] = 0u;
   uint32_t mn, mx;
   frame_depth_range(a, F, b, red, mn, mx);
   uint32_t key[kBucketItems], bk[kBucketItems];
@@ -83,35 +91,41 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kBucketItems; ++i)
-    if (key[i] != 0xffffffffu) atomicAdd(&hist[bk[i]], 1u);
+    if (key[i] != 0xffffffffu && bk[i] - lo < (uint32_t)per) atomicAdd(&hist[bk[i] - lo], 1u);
   __syncthreads();
-  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads)   // every row is written, zeros included
-    a.bkt_count[((int64_t)b * a.nbk + t) * a.nblk + blk] = hist[t];
+  for (int t = threadIdx.x; t < per; t += kBucketThreads)   // every row is written, zeros included
+    a.bkt_count[((int64_t)b * a.nbk + lo + t) * a.nblk + blk] = hist[t];
 }
 
 __global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs a) {
-  __shared__ uint32_t hist[kMaxBuckets];
+  __shared__ uint32_t hist[kMaxBuckets / kBucketParts];
   __shared__ uint32_t red[2 * (kBucketThreads / 64)];
-  const int b = blockIdx.y, blk = blockIdx.x;
+  const int b = blockIdx.y, blk = blockIdx.x / kBucketParts;
+  const int per = a.nbk / kBucketParts;
+  const uint32_t lo = (uint32_t)((blockIdx.x % kBucketParts) * per);
   const FrameDev& F = a.frames[b];
   if ((int64_t)blk * kBucketBlock >= F.gauss_count) return;
-  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads) hist[t] = 0u;
+  for (int t = threadIdx.x; t < per; t += kBucketThreads) hist[t] = 0u;
   uint32_t mn, mx;
   frame_depth_range(a, F, b, red, mn, mx);
   uint32_t key[kBucketItems], bk[kBucketItems], rk[kBucketItems];
   load_bucket_keys(a, F, blk, mn, mx, key, bk);
   __syncthreads();
+  bool mine[kBucketItems];
 #pragma unroll
-  for (int i = 0; i < kBucketItems; ++i) rk[i] = key[i] != 0xffffffffu ? atomicAdd(&hist[bk[i]], 1u) : 0u;
+  for (int i = 0; i < kBucketItems; ++i) {
+    mine[i] = key[i] != 0xffffffffu && bk[i] - lo < (uint32_t)per;
+    rk[i] = mine[i] ? atomicAdd(&hist[bk[i] - lo], 1u) : 0u;
+  }
   __syncthreads();
-  for (int t = threadIdx.x; t < a.nbk; t += kBucketThreads)
-    hist[t] = a.bkt_moff[((int64_t)b * a.nbk + t) * a.nblk + blk];
+  for (int t = threadIdx.x; t < per; t += kBucketThreads)
+    hist[t] = a.bkt_moff[((int64_t)b * a.nbk + lo + t) * a.nblk + blk];
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kBucketItems; ++i) {
-    if (key[i] == 0xffffffffu) continue;
+    if (!mine[i]) continue;
     const int64_t s = F.gauss_base + (int64_t)blk * kBucketBlock + i * kBucketThreads + threadIdx.x;
-    a.bkeys[hist[bk[i]] + rk[i]] = ((unsigned long long)key[i] << 32) | (uint32_t)s;
+    a.bkeys[hist[bk[i] - lo] + rk[i]] = ((unsigned long long)key[i] << 32) | (uint32_t)s;
   }
 }
 
@@ -275,7 +289,7 @@ void launch_depth_order(const PassArgs& a, int64_t max_frame_splats, uint32_t* s
                     side.strided, side.stride);
     return;
   }
-  const dim3 grid(a.nblk, a.B);
+  const dim3 grid(a.nblk * kBucketParts, a.B);
   const int64_t nb = (int64_t)a.B * a.nbk;
   hipLaunchKernelGGL(bucket_count_kernel, grid, dim3(kBucketThreads), 0, s, a);
   // the scan also writes each bucket's start (its first workgroup's offset) to bkt_start
