@@ -208,35 +208,50 @@ __global__ __launch_bounds__(256) void blend_dweights_kernel(const float* __rest
 #pragma unroll
     for (int j = 0; j < MAXKT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t e0 = e_begin; e0 < e_end; e0 += 16) {
-    const int64_t e = e0 + 4 * q;            // L is a multiple of 16: the block is whole
-    f4 a[MAXBT], bb[MAXKT];
-    // unconditional loads (row clamped into range), masked afterwards
+  // Blocks of 16 elements, G at a time: every load of a group is issued
+  // before its products, and the products of out-of-range tiles are taken on
+  // zeros rather than branched around, so that the group's loads are in
+  // flight together.  A wave's last group may run past its blocks: those
+  // re-read the wave's last block and are zeroed.  The products are summed
+  // block by block as without grouping.
+  constexpr int G = (MAXBT + MAXKT <= 4) ? 4 : 1;
+  const int nit = e_end > e_begin ? (int)((e_end - e_begin) / 16) : 0;   // (uniform; L is a multiple of 16)
+  for (int it0 = 0; it0 < nit; it0 += G) {
+    f4 a[G][MAXBT], bb[G][MAXKT];
 #pragma unroll
-    for (int i = 0; i < MAXBT; ++i) {
-      const int b = 16 * i + x;
-      a[i] = *reinterpret_cast<const f4*>(draw + (int64_t)min(b, B - 1) * L + e);
-      if (!(i < nbt && b < B)) a[i] = zero;
+    for (int u = 0; u < G; ++u) {
+      const bool live = it0 + u < nit;
+      const int64_t e = e_begin + (int64_t)min(it0 + u, nit - 1) * 16 + 4 * q;
+      // unconditional loads (row and block clamped into range), masked afterwards
+#pragma unroll
+      for (int i = 0; i < MAXBT; ++i) {
+        const int b = 16 * i + x;
+        a[u][i] = *reinterpret_cast<const f4*>(draw + (int64_t)min(b, B - 1) * L + e);
+        if (!(live && i < nbt && b < B)) a[u][i] = zero;
+      }
+#pragma unroll
+      for (int j = 0; j < MAXKT; ++j) {
+        const int k = 16 * j + x + 1;
+        bb[u][j] = *reinterpret_cast<const f4*>(bases + (int64_t)min(k, K) * L + e);
+        if (!(live && j < nkt && k <= K)) bb[u][j] = zero;
+      }
+      if (q == 3) {                          // features 14 and 15 are pads
+#pragma unroll
+        for (int i = 0; i < MAXBT; ++i) { a[u][i][2] = 0.f; a[u][i][3] = 0.f; }
+#pragma unroll
+        for (int j = 0; j < MAXKT; ++j) { bb[u][j][2] = 0.f; bb[u][j][3] = 0.f; }
+      }
     }
+    __builtin_amdgcn_sched_barrier(0);      // keep the group's loads ahead of its products
 #pragma unroll
-    for (int j = 0; j < MAXKT; ++j) {
-      const int k = 16 * j + x + 1;
-      bb[j] = *reinterpret_cast<const f4*>(bases + (int64_t)min(k, K) * L + e);
-      if (!(j < nkt && k <= K)) bb[j] = zero;
-    }
-    if (q == 3) {                            // features 14 and 15 are pads
+    for (int u = 0; u < G; ++u)
 #pragma unroll
-      for (int i = 0; i < MAXBT; ++i) { a[i][2] = 0.f; a[i][3] = 0.f; }
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int j = 0; j < MAXKT; ++j) { bb[j][2] = 0.f; bb[j][3] = 0.f; }
-    }
+        for (int i = 0; i < MAXBT; ++i)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int i = 0; i < MAXBT; ++i)
-#pragma unroll
-        for (int j = 0; j < MAXKT; ++j)
-          if (i < nbt && j < nkt) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][c], bb[j][c], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < MAXKT; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][i][c], bb[u][j][c], acc[i][j], 0, 0, 0);
   }
   // D layout of the f32 16x16x4 op: lane l, item r holds row 4(l/16) + r, column l%16.
   if constexpr (MAXBT * MAXKT <= 2) {
