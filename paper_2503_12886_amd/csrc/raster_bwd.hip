@@ -327,9 +327,9 @@ __device__ __forceinline__ uint32_t flag_nibble(uint32_t w) {
   return (w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u);
 }
 
-// The 9 sums of splat s over its c entries (acc zeroed by the caller).
-__device__ __forceinline__ void gather_splat_sums(const PassArgs& a, int64_t s, uint32_t c, float (&acc)[9]) {
-  const uint32_t off = a.soff[s], end = off + c;
+// The 9 sums of a splat over its c entries from off on (acc zeroed by the caller).
+__device__ __forceinline__ void gather_splat_sums(const PassArgs& a, uint32_t off, uint32_t c, float (&acc)[9]) {
+  const uint32_t end = off + c;
   const uint32_t* fw = reinterpret_cast<const uint32_t*>(a.part_flag);   // padded by 64 bytes past the capacity
   // windows of 64 entries starting at a multiple of 16: the 16 flag words
   // are read as four aligned 16-byte loads and turned into a bit mask of
@@ -389,8 +389,18 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   if (n >= F.gauss_count) return;
   const int64_t s = F.gauss_base + n;
   float4* out = reinterpret_cast<float4*>(draw + s * kNF);
-  const uint32_t c = a.cnt[s];
-  if (a.status->overflow || c == 0) {
+  // the overflow flag, the count, the entry offset and the splat's blended
+  // Gaussian are read together, so that one load latency precedes the
+  // gather instead of three
+  const uint32_t ovf = a.status->overflow, c = a.cnt[s], off = a.soff[s];
+  const float4* src = reinterpret_cast<const float4*>(raw + s * kNF);
+  float4 v0 = src[0], v1 = src[1];
+  const float4 v2 = src[2];
+  // (an empty use before the branch, or the compiler sinks the last two
+  // loads past it and waits for the count first)
+  asm volatile("" ::"v"(ovf), "v"(off), "v"(v0.x), "v"(v0.y), "v"(v0.z), "v"(v0.w), "v"(v1.x), "v"(v1.y), "v"(v1.z),
+               "v"(v1.w), "v"(v2.x), "v"(v2.y), "v"(v2.z));
+  if (ovf || c == 0) {
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
     out[0] = z; out[1] = z; out[2] = z; out[3] = z;
     return;
@@ -398,12 +408,9 @@ __global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const flo
   float acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
-  gather_splat_sums(a, s, c, acc);
+  gather_splat_sums(a, off, c, acc);
 
   // ---- recompute the forward quantities (float64) ----
-  const float4* src = reinterpret_cast<const float4*>(raw + s * kNF);
-  float4 v0 = src[0], v1 = src[1];
-  const float4 v2 = src[2];
   if (a.tg.on) tangent_deform(a.tg, b, n, v0, v1, v0, v1);   // as the forward pass did
   const float gp[11] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z};
   const double mu0 = gp[0], mu1 = gp[1], mu2 = gp[2];
