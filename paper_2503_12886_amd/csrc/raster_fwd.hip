@@ -334,9 +334,11 @@ bool launch_preprocess(const PassArgs& a, const float* raw, int64_t max_frame_sp
 // Rows are built by rank: workgroup j of a frame takes the splats of ranks
 // [32 SW j, 32 SW (j + 1)), which own segment j (words [SW j, SW (j + 1)))
 // of every row.  Each splat ORs its bit into an LDS copy of those SW words
-// for every tile of its rect; the workgroup then stores the segment of every
-// tile of the frame (zeros included) and its bit count, so every word of
-// every row is written by exactly one workgroup and nothing needs clearing.
+// for every tile of its rect; the workgroup then stores the bit count of
+// every tile's segment and the segments that have set bits.  Every count is
+// written by exactly one workgroup, and a segment whose count is zero is
+// never read (its words keep whatever an earlier pass left there), so
+// nothing needs clearing and rows of empty tiles cost no stores.
 // In LDS a tile's segment takes SW + 1 words: the lanes of a half-wave OR
 // into the same word offset of their (scattered) tiles, and with a stride of
 // SW words those tiles would share a couple of banks; an odd stride spreads
@@ -377,20 +379,24 @@ __global__ __launch_bounds__(32 * SW) void bitmap_rows_kernel(PassArgs a) {
       for (int tx = rc.x; tx <= rc.z; ++tx) atomicOr(&words[(ty * F.ntx + tx) * ST + wl], bit);
   }
   __syncthreads();
-  // the segment of every row (16-byte stores; rows and segments are 64-byte aligned)
+  // every tile's bit count, also kept in its segment's pad word
   const int seg = (int)blockIdx.x;
-  uint32_t* rows = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (int64_t)seg * SW;
-  for (int q = threadIdx.x; q < nw4; q += NT) {
-    const int t = q / (SW / 4), k = q % (SW / 4);
-    const uint32_t* src = words + t * ST + 4 * k;
-    reinterpret_cast<uint4*>(rows + (int64_t)t * a.bitmap_words)[k] = make_uint4(src[0], src[1], src[2], src[3]);
-  }
   uint16_t* cnt = a.seg_cnt + (int64_t)F.tile_base * a.seg_stride + seg;
   for (int t = threadIdx.x; t < F.n_tiles; t += NT) {
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < SW; ++k) c += __popc(words[t * ST + k]);
     cnt[(int64_t)t * a.seg_stride] = (uint16_t)c;
+    words[t * ST + SW] = c;
+  }
+  __syncthreads();
+  // the segments with set bits (16-byte stores; rows and segments are 64-byte aligned)
+  uint32_t* rows = a.tbits + (int64_t)F.tile_base * a.bitmap_words + (int64_t)seg * SW;
+  for (int q = threadIdx.x; q < nw4; q += NT) {
+    const int t = q / (SW / 4), k = q % (SW / 4);
+    const uint32_t* src = words + t * ST + 4 * k;
+    if (words[t * ST + SW] == 0u) continue;
+    reinterpret_cast<uint4*>(rows + (int64_t)t * a.bitmap_words)[k] = make_uint4(src[0], src[1], src[2], src[3]);
   }
 }
 
@@ -551,13 +557,17 @@ __global__ __launch_bounds__(256) void tile_lists_kernel(PassArgs a) {
   const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - vbase;
   const uint32_t W = (nv + 31) / 32;
   const uint32_t* row = a.tbits + (int64_t)g * a.bitmap_words;
+  const uint16_t* segc = a.seg_cnt + (int64_t)g * a.seg_stride;
+  const uint32_t sh = (uint32_t)__ffs(a.seg_words) - 1u;
+  // the words of a segment with no set bits are not stored: read as zero
+  auto word = [&](uint32_t w) { return segc[w >> sh] ? row[w] : 0u; };
   const uint32_t wpt = (W + 255) / 256;
   const uint32_t w0 = min(W, threadIdx.x * wpt), w1 = min(W, w0 + wpt);
   uint32_t c = 0;
-  for (uint32_t w = w0; w < w1; ++w) c += __popc(row[w]);
+  for (uint32_t w = w0; w < w1; ++w) c += __popc(word(w));
   uint32_t out = start + block_excl_scan<256>(c, lw, nullptr);
   for (uint32_t w = w0; w < w1; ++w) {
-    uint32_t bits = row[w];
+    uint32_t bits = word(w);
     while (bits) {
       const uint32_t bit = __ffs(bits) - 1u;
       bits &= bits - 1u;

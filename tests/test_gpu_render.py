@@ -67,9 +67,14 @@ def test_projection_records_and_rects():
 
 
 def test_tile_lists_bit_exact():
+    """Each context first renders another scene, so bitmap segments that
+    have set bits there and none here hold stale words: the lists must not
+    see them."""
     raw, cams, N = batch_case(B=4, N=2500, seed=3)
+    other, _, _ = batch_case(B=4, N=2500, seed=11)
     for tile in (8, 16, 32):
         ctx = make_ctx(tile=tile)
+        render(ctx, other, cams)
         render(ctx, raw, cams)
         projs = [raster.project(raw[b * N:(b + 1) * N], c) for b, c in enumerate(cams)]
         ranges, sf, sg, tile_base = raster.bin_and_sort(projs, cams, tile)
