@@ -22,24 +22,44 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
 }
 
 // out[j] = bias[j] + sum_c W[j][c] act(in[c]) for j < n_out; act = ReLU when relu_in.
+// A wave forms kRows output units at a time over passes of 256 inputs: lane
+// l takes inputs c0 + l + 64 t (t < 4), and every weight load of a pass
+// (rows and inputs clamped into range, masked afterwards) is issued before
+// the first product, so a layer costs a load latency per pass rather than
+// one per input step.
+constexpr int kRows = 8;
+
 __device__ __forceinline__ void mlp_layer(const float* __restrict__ W, const float* __restrict__ bias,
                                           const float* in, int n_in, int n_out, bool relu_in,
                                           float* __restrict__ out_g, float* out_l) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int j0 = w * 4; j0 < n_out; j0 += kMlpWaves * 4) {
-    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int c = lane; c < n_in; c += 64) {
-      const float xv = relu_in ? fmaxf(in[c], 0.0f) : in[c];
+  for (int j0 = w * kRows; j0 < n_out; j0 += kMlpWaves * kRows) {
+    float s[kRows];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = min(j0 + r, n_out - 1);
-        s[r] = __builtin_fmaf(W[(int64_t)j * n_in + c], xv, s[r]);
+    for (int r = 0; r < kRows; ++r) s[r] = 0.0f;
+    for (int c0 = 0; c0 < n_in; c0 += 256) {
+      float xv[4], wv[kRows][4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + 64 * t + lane;
+        const int cc = min(c, n_in - 1);
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) wv[r][t] = W[(int64_t)min(j0 + r, n_out - 1) * n_in + cc];
+        const float v = in[cc];
+        xv[t] = c < n_in ? (relu_in ? fmaxf(v, 0.0f) : v) : 0.0f;
       }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) s[r] = __builtin_fmaf(wv[r][t], xv[t], s[r]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) s[r] = wave_sum_f32(s[r]);
-    if (lane < 4 && j0 + lane < n_out) {
-      const float v = (lane == 0 ? s[0] : lane == 1 ? s[1] : lane == 2 ? s[2] : s[3]) + bias[j0 + lane];
+    for (int r = 0; r < kRows; ++r) s[r] = wave_sum_f32(s[r]);
+    if (lane < kRows && j0 + lane < n_out) {
+      float v = s[0];
+#pragma unroll
+      for (int r = 1; r < kRows; ++r) v = lane == r ? s[r] : v;
+      v += bias[j0 + lane];
       out_g[j0 + lane] = v;
       if (out_l) out_l[j0 + lane] = v;
     }
