@@ -150,6 +150,29 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_bwd_act_kernel(const float* _
   mlp_act_back(W2, gh, hidden, hidden, i0, i1, z1 + (int64_t)b * hidden, part, nullptr, dz1 + (int64_t)b * hidden);
 }
 
+// sum over frames b of x[b xs] * act(y[b ys]) (y absent: of x[b xs]), in frame
+// order, one rounding per step; frames are read 16 at a time (index clamped
+// into range) so that their loads are in flight together, and the steps past
+// the last frame add exact zeros (0 * 0), which leave the sum as it is.
+template <bool HAS_Y, bool RELU_Y>
+__device__ __forceinline__ float frame_sum(int B, const float* x, int64_t xs, const float* y, int64_t ys) {
+  float s = 0.0f;
+  for (int b0 = 0; b0 < B; b0 += 16) {
+    float xv[16], yv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t b = min(b0 + u, B - 1);
+      const bool in = b0 + u < B;
+      const float xl = x[b * xs], yl = HAS_Y ? y[b * ys] : 1.0f;
+      xv[u] = in ? xl : 0.0f;
+      yv[u] = in ? (RELU_Y ? fmaxf(yl, 0.0f) : yl) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s = HAS_Y ? __builtin_fmaf(xv[u], yv[u], s) : s + xv[u];
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restrict__ theta,
                                                             const float* __restrict__ z1,
                                                             const float* __restrict__ z2,
@@ -161,26 +184,24 @@ __global__ __launch_bounds__(256) void mlp_bwd_param_kernel(const float* __restr
   const int64_t total = n1 + hidden + n2 + hidden + n3 + K;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= total) return;
-  float s = 0.0f;
+  float s;
   int64_t r = i;
   if (r < n1) {                                    // W1[j][c] = sum_b dz1[b][j] theta[b][c]
     const int j = (int)(r / d_in), c = (int)(r % d_in);
-    for (int b = 0; b < B; ++b) s = __builtin_fmaf(dz1[(int64_t)b * hidden + j], theta[(int64_t)b * d_in + c], s);
+    s = frame_sum<true, false>(B, dz1 + j, hidden, theta + c, d_in);
   } else if ((r -= n1) < hidden) {                 // b1
-    for (int b = 0; b < B; ++b) s += dz1[(int64_t)b * hidden + r];
+    s = frame_sum<false, false>(B, dz1 + r, hidden, nullptr, 0);
   } else if ((r -= hidden) < n2) {                 // W2[j][c] = sum_b dz2[b][j] relu(z1[b][c])
     const int j = (int)(r / hidden), c = (int)(r % hidden);
-    for (int b = 0; b < B; ++b)
-      s = __builtin_fmaf(dz2[(int64_t)b * hidden + j], fmaxf(z1[(int64_t)b * hidden + c], 0.0f), s);
+    s = frame_sum<true, true>(B, dz2 + j, hidden, z1 + c, hidden);
   } else if ((r -= n2) < hidden) {                 // b2
-    for (int b = 0; b < B; ++b) s += dz2[(int64_t)b * hidden + r];
+    s = frame_sum<false, false>(B, dz2 + r, hidden, nullptr, 0);
   } else if ((r -= hidden) < n3) {                 // W3[k][c] = sum_b dpsi[b][k] relu(z2[b][c])
     const int k = (int)(r / hidden), c = (int)(r % hidden);
-    for (int b = 0; b < B; ++b)
-      s = __builtin_fmaf(dpsi[(int64_t)b * K + k], fmaxf(z2[(int64_t)b * hidden + c], 0.0f), s);
+    s = frame_sum<true, true>(B, dpsi + k, K, z2 + c, hidden);
   } else {                                         // b3
     r -= n3;
-    for (int b = 0; b < B; ++b) s += dpsi[(int64_t)b * K + r];
+    s = frame_sum<false, false>(B, dpsi + r, K, nullptr, 0);
   }
   dP[i] = s;
 }
