@@ -31,8 +31,8 @@ __device__ __forceinline__ uint32_t depth_bucket(uint32_t bits, uint32_t mn, uin
 constexpr int kBucketThreads = 1024;
 constexpr int kBucketItems = kBucketBlock / kBucketThreads;
 
-__device__ __forceinline__ void load_bucket_keys(const PassArgs& a, const FrameDev& F, int blk, uint32_t mn,
-                                                 uint32_t mx, uint32_t* key, uint32_t* bk) {
+// (issued before the frame's depth range is reduced, which they do not need)
+__device__ __forceinline__ void load_bucket_keys(const PassArgs& a, const FrameDev& F, int blk, uint32_t* key) {
   const int64_t cnt = F.gauss_count;
 #pragma unroll
   for (int i = 0; i < kBucketItems; ++i) {
@@ -41,6 +41,10 @@ __device__ __forceinline__ void load_bucket_keys(const PassArgs& a, const FrameD
     key[i] = cnt > 0 ? a.dkey[F.gauss_base + nn] : 0xffffffffu;
     if (n >= cnt) key[i] = 0xffffffffu;
   }
+}
+
+__device__ __forceinline__ void key_buckets(const PassArgs& a, uint32_t mn, uint32_t mx, const uint32_t* key,
+                                            uint32_t* bk) {
 #pragma unroll
   for (int i = 0; i < kBucketItems; ++i) bk[i] = key[i] != 0xffffffffu ? depth_bucket(key[i], mn, mx, a.nbk) : 0u;
 }
@@ -83,11 +87,12 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_count_kernel(PassArgs a
   const int per = a.nbk / kBucketParts;
   const uint32_t lo = (uint32_t)((blockIdx.x % kBucketParts) * per);
   const FrameDev& F = a.frames[b];
+  uint32_t key[kBucketItems], bk[kBucketItems];
+  load_bucket_keys(a, F, blk, key);
   for (int t = threadIdx.x; t < per; t += kBucketThreads) hist[t] = 0u;
   uint32_t mn, mx;
   frame_depth_range(a, F, b, red, mn, mx);
-  uint32_t key[kBucketItems], bk[kBucketItems];
-  load_bucket_keys(a, F, blk, mn, mx, key, bk);
+  key_buckets(a, mn, mx, key, bk);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kBucketItems; ++i)
@@ -105,11 +110,21 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs
   const uint32_t lo = (uint32_t)((blockIdx.x % kBucketParts) * per);
   const FrameDev& F = a.frames[b];
   if ((int64_t)blk * kBucketBlock >= F.gauss_count) return;
+  // the keys and this block's offsets in its buckets are read first: neither
+  // depends on the depth range or the LDS ranks
+  uint32_t key[kBucketItems], bk[kBucketItems], rk[kBucketItems];
+  load_bucket_keys(a, F, blk, key);
+  constexpr int kOffPer = kMaxBuckets / kBucketParts / kBucketThreads;
+  uint32_t moff[kOffPer];
+#pragma unroll
+  for (int j = 0; j < kOffPer; ++j) {
+    const int t = (int)threadIdx.x + j * kBucketThreads;
+    moff[j] = t < per ? a.bkt_moff[((int64_t)b * a.nbk + lo + t) * a.nblk + blk] : 0u;
+  }
   for (int t = threadIdx.x; t < per; t += kBucketThreads) hist[t] = 0u;
   uint32_t mn, mx;
   frame_depth_range(a, F, b, red, mn, mx);
-  uint32_t key[kBucketItems], bk[kBucketItems], rk[kBucketItems];
-  load_bucket_keys(a, F, blk, mn, mx, key, bk);
+  key_buckets(a, mn, mx, key, bk);
   __syncthreads();
   bool mine[kBucketItems];
 #pragma unroll
@@ -118,8 +133,11 @@ __global__ __launch_bounds__(kBucketThreads) void bucket_scatter_kernel(PassArgs
     rk[i] = mine[i] ? atomicAdd(&hist[bk[i] - lo], 1u) : 0u;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < per; t += kBucketThreads)
-    hist[t] = a.bkt_moff[((int64_t)b * a.nbk + lo + t) * a.nblk + blk];
+#pragma unroll
+  for (int j = 0; j < kOffPer; ++j) {
+    const int t = (int)threadIdx.x + j * kBucketThreads;
+    if (t < per) hist[t] = moff[j];
+  }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kBucketItems; ++i) {
