@@ -115,9 +115,20 @@ __device__ __forceinline__ void mlp_act_back(const float* __restrict__ W, const 
   if (nu > 0 && t < nu * split) {
     const int i = i0 + t % nu, qk = t / nu;
     const int k0 = qk * per, k1 = min(n_g, k0 + per);
+    // 16 steps at a time, every weight load issued first (index clamped into
+    // range); steps past k1 add 0 * w, which leaves the sum as it is
     float s = 0.0f;
-#pragma unroll 16
-    for (int k = k0; k < k1; ++k) s = __builtin_fmaf(W[(int64_t)k * n_x + i], g[k], s);
+    for (int kb = k0; kb < k1; kb += 16) {
+      float wv[16], gv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int k = min(kb + u, k1 - 1);
+        wv[u] = W[(int64_t)k * n_x + i];
+        gv[u] = kb + u < k1 ? g[k] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) s = __builtin_fmaf(wv[u], gv[u], s);
+    }
     part[qk * kMlpMaxIn + (i - i0)] = s;
   }
   __syncthreads();
