@@ -447,17 +447,22 @@ void launch_bitmap_rows(const PassArgs& a, int64_t max_frame_splats, int max_fra
 }
 
 // A tile's entry count is the sum of its row's segment counts: one wave per
-// tile, lanes over the segments.
+// tile, lanes over the segments.  The first 128 counts are read (clamped to
+// the row) before the frame's segment count is known, which only masks
+// them, so that their loads overlap the frame lookup.
 __global__ __launch_bounds__(256) void tile_count_kernel(PassArgs a) {
-  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // (the wave's tile, declared uniform so that the frame lookup runs on scalar loads)
+  const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (g >= a.n_tiles) return;
   const int lane = threadIdx.x & 63;
+  const uint16_t* sc = a.seg_cnt + (int64_t)g * a.seg_stride;
+  const uint32_t last = (uint32_t)a.seg_stride - 1u;
+  const uint32_t v0 = sc[min((uint32_t)lane, last)], v1 = sc[min((uint32_t)lane + 64u, last)];
   const int b = frame_of_tile(a.frames, a.B, g);
   const uint32_t nv = a.bkt_start[(b + 1) * a.nbk] - a.bkt_start[b * a.nbk];
   const uint32_t nseg = ((nv + 31) / 32 + a.seg_words - 1) / a.seg_words;
-  const uint16_t* sc = a.seg_cnt + (int64_t)g * a.seg_stride;
-  uint32_t c = 0;
-  for (uint32_t q = lane; q < nseg; q += 64) c += sc[q];
+  uint32_t c = ((uint32_t)lane < nseg ? v0 : 0u) + ((uint32_t)lane + 64u < nseg ? v1 : 0u);
+  for (uint32_t q = lane + 128; q < nseg; q += 64) c += sc[q];
   for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
   if (lane == 0) a.tile_count[g] = c;
 }
