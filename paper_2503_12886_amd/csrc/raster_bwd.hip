@@ -379,13 +379,16 @@ __device__ __forceinline__ void gather_splat_sums(const PassArgs& a, uint32_t of
   }
 }
 
-// A workgroup per (frame, 256 of its splats): the frame is the grid's y
-// index, so its camera is read at uniform addresses.
-__global__ __launch_bounds__(256) void proj_adjoint_kernel(PassArgs a, const float* __restrict__ raw,
-                                                           float* __restrict__ draw) {
+// A workgroup per (frame, 64 of its splats): the frame is the grid's y
+// index, so its camera is read at uniform addresses.  One-wave workgroups
+// let the chip's last round of waves be filled finely (the splats' gathers
+// differ in length).
+constexpr int kAdjThreads = 64;
+__global__ __launch_bounds__(kAdjThreads) void proj_adjoint_kernel(PassArgs a, const float* __restrict__ raw,
+                                                                   float* __restrict__ draw) {
   const int b = blockIdx.y;
   const FrameDev& F = a.frames[b];
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
   if (n >= F.gauss_count) return;
   const int64_t s = F.gauss_base + n;
   float4* out = reinterpret_cast<float4*>(draw + s * kNF);
@@ -555,7 +558,8 @@ void launch_color_init_apply(const float* draw_i, const float* draw_1, int B, in
 
 void launch_gather_bwd(const PassArgs& a, const float* raw, float* draw, int64_t max_frame_splats, hipStream_t s) {
   if (a.n_splats == 0 || max_frame_splats == 0) return;
-  hipLaunchKernelGGL(proj_adjoint_kernel, dim3(div_up(max_frame_splats, 256), a.B), dim3(256), 0, s, a, raw, draw);
+  hipLaunchKernelGGL(proj_adjoint_kernel, dim3(div_up(max_frame_splats, kAdjThreads), a.B), dim3(kAdjThreads), 0, s, a,
+                     raw, draw);
 }
 
 // ---------------------------------------------------------------- loss
